@@ -1,0 +1,240 @@
+"""PCVOF ORACLE -- test infrastructure, not part of the product.
+
+ctypes shim over ``liboracle.so``, the plain FP64 CPU reference of one step of
+the paper's geometric PLIC-VOF advection with conservative thermal-energy
+advection (section 3.3 and section 3.4.1). Only ``tests/``, the smoke check in
+``__graft_entry__`` and the CPU-baseline leg of ``bench.py`` may import this
+module. It shares no code with the HIP library in ``paper_2001_03477_amd``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+_dp = C.POINTER(C.c_double)
+
+
+class Grid(C.Structure):
+    _fields_ = [("ndim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("h", C.c_double), ("bc", C.c_int * 3)]
+
+
+class Params(C.Structure):
+    _fields_ = [("cp_l", C.c_double), ("cp_g", C.c_double), ("rho_l", C.c_double),
+                ("T_gamma", C.c_double), ("eps_mixed", C.c_double), ("weno_eps", C.c_double),
+                ("normal", C.c_int)]
+
+
+STAT_NAMES = ("vol", "energy", "vol_clip", "energy_clip", "vol_phase", "energy_phase",
+              "vol_bnd_out", "energy_bnd_out", "vol_src", "energy_src", "max_cfl")
+
+
+class Stats(C.Structure):
+    _fields_ = [(n, C.c_double) for n in STAT_NAMES]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n in STAT_NAMES}
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(_LIB_PATH)
+        L.or_volume.restype = C.c_double
+        L.or_volume.argtypes = [_dp, C.c_double]
+        L.or_area.restype = C.c_double
+        L.or_area.argtypes = [_dp, C.c_double]
+        L.or_alpha.restype = C.c_double
+        L.or_alpha.argtypes = [_dp, C.c_double]
+        L.or_normal.restype = None
+        L.or_normal.argtypes = [_dp, C.c_int, _dp]
+        L.or_slab.restype = C.c_double
+        L.or_slab.argtypes = [_dp, C.c_double, C.c_int, C.c_double]
+        L.or_weno5.restype = C.c_double
+        L.or_weno5.argtypes = [_dp, C.c_double]
+        for nm in ("or_volume_n", "or_area_n", "or_alpha_n"):
+            f = getattr(L, nm)
+            f.restype = None
+            f.argtypes = [C.c_int, _dp, _dp, _dp]
+        L.or_slab_n.restype = None
+        L.or_slab_n.argtypes = [C.c_int, _dp, _dp, C.POINTER(C.c_int), _dp, _dp]
+        L.or_prologue.restype = None
+        L.or_prologue.argtypes = [C.POINTER(Grid), C.POINTER(Params), _dp, _dp, _dp, _dp]
+        L.or_sweep.restype = C.c_int
+        L.or_sweep.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.c_int, _dp, _dp, _dp, _dp,
+                               _dp, C.c_double, _dp, _dp, _dp]
+        L.or_phase_change.restype = C.c_int
+        L.or_phase_change.argtypes = [C.POINTER(Grid), C.POINTER(Params), _dp, _dp, _dp,
+                                      C.c_double, _dp, _dp, _dp]
+        L.or_step.restype = C.c_int
+        L.or_step.argtypes = [C.POINTER(Grid), C.POINTER(Params), _dp, _dp, _dp, _dp, _dp, _dp,
+                              C.c_double, C.c_double, C.c_long, _dp, _dp, C.POINTER(Stats)]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+# ---------------------------------------------------------------- geometry
+def volume(m, alpha) -> float:
+    return lib().or_volume(_ptr(_f64(m)), float(alpha))
+
+
+def area(m, alpha) -> float:
+    return lib().or_area(_ptr(_f64(m)), float(alpha))
+
+
+def alpha_of(m, c) -> float:
+    return lib().or_alpha(_ptr(_f64(m)), float(c))
+
+
+def normal(c27, method: int = 1) -> np.ndarray:
+    out = np.zeros(3)
+    lib().or_normal(_ptr(_f64(c27).reshape(27)), int(method), _ptr(out))
+    return out
+
+
+def slab(m, alpha, axis: int, lam) -> float:
+    return lib().or_slab(_ptr(_f64(m)), float(alpha), int(axis), float(lam))
+
+
+def weno5(v, eps: float = 1e-6) -> float:
+    return lib().or_weno5(_ptr(_f64(v)), float(eps))
+
+
+def volume_n(m, alpha) -> np.ndarray:
+    m = _f64(m).reshape(-1, 3)
+    a = _f64(alpha).reshape(-1)
+    out = np.empty(len(a))
+    lib().or_volume_n(len(a), _ptr(m), _ptr(a), _ptr(out))
+    return out
+
+
+def area_n(m, alpha) -> np.ndarray:
+    m = _f64(m).reshape(-1, 3)
+    a = _f64(alpha).reshape(-1)
+    out = np.empty(len(a))
+    lib().or_area_n(len(a), _ptr(m), _ptr(a), _ptr(out))
+    return out
+
+
+def alpha_n(m, c) -> np.ndarray:
+    m = _f64(m).reshape(-1, 3)
+    cc = _f64(c).reshape(-1)
+    out = np.empty(len(cc))
+    lib().or_alpha_n(len(cc), _ptr(m), _ptr(cc), _ptr(out))
+    return out
+
+
+def slab_n(m, alpha, axis, lam) -> np.ndarray:
+    m = _f64(m).reshape(-1, 3)
+    a = _f64(alpha).reshape(-1)
+    ax = np.ascontiguousarray(np.asarray(axis, dtype=np.int32).reshape(-1))
+    lm = _f64(lam).reshape(-1)
+    out = np.empty(len(a))
+    lib().or_slab_n(len(a), _ptr(m), _ptr(a), ax.ctypes.data_as(C.POINTER(C.c_int)), _ptr(lm),
+                    _ptr(out))
+    return out
+
+
+# ---------------------------------------------------------------- step
+@dataclass
+class Config:
+    """Grid and physical parameters of one domain (same meaning as the library's)."""
+    shape: tuple            # (nz, ny, nx); nz == 1 for 2D
+    h: float
+    ndim: int = 3
+    bc: tuple = (0, 0, 0)   # per axis x, y, z: 0 periodic, 1 outflow
+    cp_l: float = 1.0
+    cp_g: float = 1.0
+    rho_l: float = 1.0
+    T_gamma: float = 1.0
+    eps_mixed: float = 1e-12
+    weno_eps: float = 1e-6
+    normal: int = 1
+
+    def grid(self) -> Grid:
+        nz, ny, nx = self.shape
+        g = Grid(self.ndim, nx, ny, nz, self.h)
+        for i in range(3):
+            g.bc[i] = int(self.bc[i])
+        return g
+
+    def params(self) -> Params:
+        return Params(self.cp_l, self.cp_g, self.rho_l, self.T_gamma, self.eps_mixed,
+                      self.weno_eps, int(self.normal))
+
+
+def prologue(cfg: Config, c, e):
+    c = _f64(c)
+    e = _f64(e)
+    cc = np.empty_like(c)
+    ec = np.empty_like(c)
+    g, p = cfg.grid(), cfg.params()
+    lib().or_prologue(C.byref(g), C.byref(p), _ptr(c), _ptr(e), _ptr(cc), _ptr(ec))
+    return cc, ec
+
+
+def sweep(cfg: Config, axis: int, c, e, cc, ec, vel, kfac: float):
+    """One direction sweep; returns (c', e', acc) with acc the sweep's
+    (vol_clip, energy_clip, vol_bnd_out, energy_bnd_out, vol_src, energy_src) in cell units."""
+    c, e, cc, ec, vel = map(_f64, (c, e, cc, ec, vel))
+    co = np.empty_like(c)
+    eo = np.empty_like(e)
+    acc = np.zeros(6)
+    g, p = cfg.grid(), cfg.params()
+    rc = lib().or_sweep(C.byref(g), C.byref(p), int(axis), _ptr(c), _ptr(e), _ptr(cc), _ptr(ec),
+                        _ptr(vel), float(kfac), _ptr(co), _ptr(eo), _ptr(acc))
+    if rc != 0:
+        raise ValueError(f"or_sweep failed ({rc})")
+    return co, eo, acc
+
+
+def phase_change(cfg: Config, c, e, mdot, dt: float):
+    c, e, mdot = map(_f64, (c, e, mdot))
+    co = np.empty_like(c)
+    eo = np.empty_like(e)
+    acc = np.zeros(2)
+    g, p = cfg.grid(), cfg.params()
+    rc = lib().or_phase_change(C.byref(g), C.byref(p), _ptr(c), _ptr(e), _ptr(mdot), float(dt),
+                               _ptr(co), _ptr(eo), _ptr(acc))
+    if rc != 0:
+        raise ValueError(f"or_phase_change failed ({rc})")
+    return co, eo, acc
+
+
+def step(cfg: Config, c, e, u, v, w=None, mdot=None, dt: float = 0.0, u_scale: float = 1.0,
+         step_index: int = 0):
+    """One full time step; returns (c_new, e_new, stats dict)."""
+    c, e, u, v = map(_f64, (c, e, u, v))
+    w = _f64(w) if w is not None else np.zeros(1)
+    md = _f64(mdot) if mdot is not None else None
+    co = np.empty_like(c)
+    eo = np.empty_like(e)
+    st = Stats()
+    g, p = cfg.grid(), cfg.params()
+    rc = lib().or_step(C.byref(g), C.byref(p), _ptr(c), _ptr(e), _ptr(u), _ptr(v), _ptr(w),
+                       _ptr(md) if md is not None else None, float(dt), float(u_scale),
+                       int(step_index), _ptr(co), _ptr(eo), C.byref(st))
+    if rc != 0:
+        raise ValueError(f"or_step failed ({rc})")
+    return co, eo, st.as_dict()
