@@ -1,0 +1,170 @@
+"""Benchmark of the advection step on one MI355X.
+
+Workload (default): the 3D 128^3 LeVeque deformation of a sphere R = 0.15 at
+(0.35, 0.35, 0.35), CFL 0.3, per-phase random temperatures, rho c_p 1000 : 1,
+m'' = 0, FP64. A step is the whole hot path: prologue, three direction sweeps
+(geometric VOF fluxes + conservative WENO5 energy fluxes), checksums.
+
+Prints one JSON line: whole-job cell-updates/s over the timed steps (inputs already
+resident in HBM), the roofline of the dominant kernel (the sweep; algorithmic bytes
+per launch over its average duration measured with HIP events on the library's
+stream), and the oracle timed on the host on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "VOF+energy advect cell-updates/s (FP64 vs mixed), % HBM peak, volume drift"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes of one sweep per cell (FP64): read c, e, e_c (8 each), the
+# dilatation flag c_c (1) and the face velocity (8 per face), write c, e (8 each)
+SWEEP_BYTES_PER_CELL = 8 + 8 + 8 + 1 + 8 + 8
+PROLOGUE_BYTES_PER_CELL = 8 + 8 + 1 + 8
+
+
+def workload(name):
+    from paper_2001_03477_amd import workloads as W
+    if name == "leveque128":
+        return W.leveque_3d(128)
+    if name == "leveque256":
+        return W.leveque_3d(256)
+    if name == "circle2d":
+        return W.circle_2d(64)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def sweep_bytes(wl, axis):
+    nz, ny, nx = wl.shape
+    faces = [nz * ny * (nx + 1), nz * (ny + 1) * nx, (nz + 1) * ny * nx][axis]
+    return (SWEEP_BYTES_PER_CELL - 8) * wl.ncells + 8 * faces
+
+
+def cpu_baseline(wl, budget_s=20.0):
+    """The oracle on the host: whole steps of the same workload until the budget is
+    used (at least one step)."""
+    import oracle
+    cfg = oracle.Config(shape=wl.shape, h=wl.h, ndim=wl.ndim, bc=wl.bc, cp_l=wl.cp_l,
+                        cp_g=wl.cp_g, rho_l=wl.rho_l, T_gamma=wl.T_gamma, normal=wl.normal)
+    c, e = wl.c, wl.e
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        c, e, _ = oracle.step(cfg, c, e, wl.u, wl.v, wl.w, wl.mdot, wl.dt, wl.u_scale(n), n)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or n >= 3:
+            break
+    return {"value": wl.ncells * n / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} full step(s) of the {wl.name} workload, single-threaded, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="leveque128")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the advection step of one domain is measured on "
+              "one MI355X (multi-GPU sharding is a design note, not part of this build)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2001_03477_amd import pcvof
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    wl = workload(args.workload)
+    spec = pcvof.DomainSpec(shape=wl.shape, h=wl.h, ndim=wl.ndim, bc=wl.bc, cp_l=wl.cp_l,
+                            cp_g=wl.cp_g, rho_l=wl.rho_l, T_gamma=wl.T_gamma, normal=wl.normal)
+    stream = torch.cuda.current_stream()
+    dom = pcvof.Domain(spec, stream=stream)
+    dom.set_vof(wl.c)
+    dom.set_energy(wl.e)
+    dom.set_velocity(wl.u, wl.v, wl.w)
+    if wl.mdot is not None:
+        dom.set_mass_flux(wl.mdot)
+    vol0 = float(dom.vof().sum()) * wl.h ** wl.ndim
+
+    def one_step(n, ev=None):
+        dom.begin_step()
+        for s in range(wl.ndim):
+            axis = (n + s) % wl.ndim
+            if ev is not None:
+                ev[s][0].record(stream)
+            dom.sweep(axis, wl.dt, wl.u_scale(n))
+            if ev is not None:
+                ev[s][1].record(stream)
+        if wl.mdot is not None:
+            dom.phase_change(wl.dt)
+        dom.end_step(stats=False)
+
+    n = 0
+    for _ in range(args.warmup):
+        one_step(n)
+        n += 1
+    torch.cuda.synchronize()
+    events = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+               for _ in range(wl.ndim)] for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for k in range(args.steps):
+        one_step(n, events[k])
+        n += 1
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_end)
+    sweep_ms = np.zeros(wl.ndim)
+    sweep_bytes_tot = 0.0
+    for k in range(args.steps):
+        for s in range(wl.ndim):
+            axis = (args.warmup + k + s) % wl.ndim
+            sweep_ms[axis] += events[k][s][0].elapsed_time(events[k][s][1])
+            sweep_bytes_tot += sweep_bytes(wl, axis)
+    nsweeps = args.steps * wl.ndim
+    avg_sweep_ms = float(sweep_ms.sum() / nsweeps)
+    achieved = sweep_bytes_tot / nsweeps / (avg_sweep_ms * 1e-3) / 1e9
+    vol1 = float(dom.vof().sum()) * wl.h ** wl.ndim
+
+    value = wl.ncells * args.steps / (total_ms * 1e-3)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "grid": list(wl.shape[::-1]), "ndim": wl.ndim,
+                   "bc": "outflow" if wl.bc[0] else "periodic", "cfl": 0.3, "normal": "MYC",
+                   "mdot": "on" if wl.mdot is not None else "off", "precision": "fp64",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_sweep (x, y, z)", "avg_launch_ms": avg_sweep_ms,
+                     "per_axis_ms": [float(t / args.steps) for t in sweep_ms]},
+        "volume_drift": abs(vol1 - vol0) / vol0,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,159 @@
+/*
+ * pcvof -- geometric PLIC-VOF advection with conservative thermal-energy
+ * advection and the two-step phase-change shift, on AMD Instinct MI355X (gfx950).
+ *
+ * One call to pcvof_advect_step advances the volume fraction c and the thermal
+ * energy e = C_p T (C_p = rho c_p per unit volume, eq. c_vol_avg) of a uniform
+ * Cartesian MAC grid by one time step:
+ *   - step 1 of the paper's VOF scheme (section 3.3.1): ndim direction-split
+ *     geometric sweeps with the given divergence-free liquid velocity; each sweep
+ *     reconstructs a plane m.x = alpha per mixed cell (section 3.2, eq. plane_m),
+ *     takes the liquid volume of the upwind face-flux region of the donor cell, and
+ *     carries the heat capacity of the fluxed liquid and gas volumes at the WENO5
+ *     face temperature (section 3.4.1, eq. disc_et_adv);
+ *   - step 2 (section 3.3.2, eq. vof_step2_full): the interface shift by
+ *     Delta d = -(m''/rho_l) dt / h in mixed cells, with the capped motion carried
+ *     into the neighbours the interface moves into, and the latent energy correction
+ *     Delta e = Delta c (C_pl - C_pg) T_Gamma (section 3.4.1).
+ *
+ * Layout. Cell arrays are [nz][ny][nx] doubles, x fastest. MAC face velocities:
+ * u [nz][ny][nx+1] on x-faces, v [nz][ny+1][nx] on y-faces, w [nz+1][ny][nx] on
+ * z-faces (face i lies between cells i-1 and i). For a periodic axis the last face
+ * must equal the first. 2D grids have ndim = 2, nz = 1 and no w.
+ *
+ * Ownership. The caller owns all memory: a device workspace of
+ * pcvof_workspace_bytes() bytes (for instance a torch uint8 tensor) and the HIP
+ * stream (for instance torch.cuda.current_stream().cuda_stream). The library never
+ * allocates device memory, never keeps pointers passed to set_/get_ calls, and
+ * enqueues all work on the given stream. Calls with mem = PCVOF_MEM_DEVICE copy
+ * asynchronously on the stream; calls with mem = PCVOF_MEM_HOST return after the
+ * copy has completed.
+ *
+ * Errors. Every call returns a status (0 = PCVOF_OK, negative = error) and never
+ * throws or exits; pcvof_last_error() gives a message for the calling thread.
+ */
+#ifndef PCVOF_H
+#define PCVOF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PCVOF_OK = 0,
+    PCVOF_ERR_ARG = -1,        /* invalid argument (null pointer, bad size, bad enum) */
+    PCVOF_ERR_CFL = -2,        /* max |u_f| * |u_scale| * dt / h above params.cfl_max */
+    PCVOF_ERR_NONFINITE = -3,  /* NaN or Inf in an input field */
+    PCVOF_ERR_BOUNDS = -4,     /* volume fraction outside [0, 1] */
+    PCVOF_ERR_WORKSPACE = -5,  /* workspace too small or misaligned */
+    PCVOF_ERR_HIP = -6,        /* a HIP runtime call failed */
+    PCVOF_ERR_STATE = -7       /* call out of order (e.g. step before set_vof) */
+};
+
+enum { PCVOF_MEM_HOST = 0, PCVOF_MEM_DEVICE = 1 };
+enum { PCVOF_BC_PERIODIC = 0, PCVOF_BC_OUTFLOW = 1 };
+enum { PCVOF_NORMAL_YOUNGS = 0, PCVOF_NORMAL_MYC = 1, PCVOF_NORMAL_CC = 2 };
+
+typedef struct {
+    int ndim;        /* 2 or 3 */
+    int nx, ny, nz;  /* cells per axis (nz == 1 when ndim == 2), each >= 1 */
+    double h;        /* cubic cell edge, > 0 */
+    int bc[3];       /* per axis x, y, z: PCVOF_BC_PERIODIC or PCVOF_BC_OUTFLOW
+                        (outflow: ghost cells copy the nearest interior cell) */
+} pcvof_grid;
+
+typedef struct {
+    double cp_l, cp_g;  /* volumetric heat capacities rho c_p of liquid and gas, > 0 */
+    double rho_l;       /* liquid density used by the phase-change shift, > 0 */
+    double T_gamma;     /* interface (saturation) temperature */
+    double eps_mixed;   /* mixed cell: eps < c < 1 - eps (section 3.1 uses 1e-12) */
+    double weno_eps;    /* epsilon of the WENO5 nonlinear weights (1e-6) */
+    double cfl_max;     /* largest admissible face CFL number (0.5) */
+    int normal;         /* PCVOF_NORMAL_*: interface normal estimator (MYC per section 3.2) */
+    int reserved;       /* must be 0 */
+} pcvof_params;
+
+/* Checksums of one step (cell volume hv = h^ndim). The change of total volume obeys
+   vol(n+1) - vol(n) = -vol_bnd_out + vol_src + vol_clip + vol_phase, and likewise for
+   the energy, up to round-off. */
+typedef struct {
+    double vol, energy;                  /* hv * sum c, hv * sum e after the step */
+    double vol_clip, energy_clip;        /* sweep clipping of c into [0,1] (T kept) */
+    double vol_phase, energy_phase;      /* step 2 change of c, and its latent correction */
+    double vol_bnd_out, energy_bnd_out;  /* net outflow through outflow boundaries */
+    double vol_src, energy_src;          /* split dilatation terms c_c dlam, e_c dlam */
+    double max_cfl;                      /* max |lambda_f| used by the step */
+} pcvof_stats;
+
+typedef struct pcvof_handle pcvof_handle;
+
+/* Bytes of device workspace a domain needs (0 on invalid arguments). */
+size_t pcvof_workspace_bytes(const pcvof_grid* grid, const pcvof_params* params);
+
+/* Binds a domain to a caller-owned device workspace (256-byte aligned, at least
+   pcvof_workspace_bytes) and a HIP stream (NULL = the null stream). */
+int pcvof_create(const pcvof_grid* grid, const pcvof_params* params, void* d_workspace,
+                 size_t workspace_bytes, void* hip_stream, pcvof_handle** out);
+int pcvof_destroy(pcvof_handle* h);
+
+/* Field input. set_vof checks 0 <= c <= 1 and finiteness (PCVOF_ERR_BOUNDS /
+   PCVOF_ERR_NONFINITE, synchronising). set_energy sets e directly; set_temperature
+   sets e = C_p(c) T and needs c first. set_velocity copies the three MAC face arrays
+   (w ignored in 2D), checks finiteness and periodic face equality, and records
+   max |u_f| for the CFL check (synchronising). set_mass_flux sets m'' per cell
+   (mass per area and time, positive = evaporation); NULL switches step 2 off. */
+int pcvof_set_vof(pcvof_handle* h, const double* c, int mem);
+int pcvof_set_energy(pcvof_handle* h, const double* e, int mem);
+int pcvof_set_temperature(pcvof_handle* h, const double* T, int mem);
+int pcvof_set_velocity(pcvof_handle* h, const double* u, const double* v, const double* w,
+                       int mem);
+int pcvof_set_mass_flux(pcvof_handle* h, const double* mdot, int mem);
+
+/* One time step with face CFL numbers lambda_f = u_f * (u_scale * dt) / h:
+   prologue, ndim sweeps in the axis order rotated by the step counter (x,y,z /
+   y,z,x / z,x,y), step 2 when a mass flux is set, checksums. Increments the step
+   counter. stats may be NULL (no synchronisation); otherwise the call waits for the
+   step and fills it. */
+int pcvof_advect_step(pcvof_handle* h, double dt, double u_scale, pcvof_stats* stats);
+
+/* The stages of pcvof_advect_step, for staged use and testing. begin_step freezes
+   c_c = [c >= 1/2] and e_c = C_p(c_c) T for the sweeps of a step; sweep runs one
+   direction sweep (axis 0..ndim-1); phase_change runs step 2 with time step dt;
+   end_step reduces the checksums (stats may be NULL) and increments the counter. */
+int pcvof_begin_step(pcvof_handle* h);
+int pcvof_sweep(pcvof_handle* h, int axis, double dt, double u_scale);
+int pcvof_phase_change(pcvof_handle* h, double dt);
+int pcvof_end_step(pcvof_handle* h, pcvof_stats* stats);
+
+/* Field output (same layout as the input). */
+int pcvof_get_vof(pcvof_handle* h, double* out, int mem);
+int pcvof_get_energy(pcvof_handle* h, double* out, int mem);
+int pcvof_get_temperature(pcvof_handle* h, double* out, int mem);
+
+/* Step counter (sets the sweep order); part of the state for checkpoint / resume. */
+int pcvof_get_step(pcvof_handle* h, long* step);
+int pcvof_set_step(pcvof_handle* h, long step);
+
+const char* pcvof_last_error(void);
+
+/* Batched cell geometry on device arrays of n entries (testing and reuse), enqueued
+   on the given stream. m holds 3 doubles per entry; the volume functions accept any
+   non-zero m, the plane constant is returned in the same scaling as m.
+   volume: |{x in [0,1]^3 : m.x <= alpha}|; alpha: inverse of volume for c in (0,1);
+   slab: liquid volume (cell units) of the donor region crossing a face in a sweep
+   along axis with face CFL number lam (x_axis in [1-lam,1] for lam > 0, [0,|lam|]
+   for lam < 0); normal: normal from 27 fractions c27[(dz+1)*9+(dy+1)*3+(dx+1)];
+   weno5: face value between v[2] and v[3] from 5 values per entry. */
+int pcvof_geom_volume(int n, const double* m, const double* alpha, double* out, void* stream);
+int pcvof_geom_alpha(int n, const double* m, const double* c, double* out, void* stream);
+int pcvof_geom_slab(int n, const double* m, const double* alpha, const int* axis,
+                    const double* lam, double* out, void* stream);
+int pcvof_geom_normal(int n, const double* c27, int method, double* m, void* stream);
+int pcvof_geom_weno5(int n, const double* v, double eps, double* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PCVOF_H */

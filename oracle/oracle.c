@@ -181,16 +181,22 @@ static void youngs_gradient(const double* c27, double g[3]) {
     }
 }
 
+/* Decisions of the normal estimator use a tie band: gradients of magnitude up to
+   NORMAL_TIE count as zero and candidates within NORMAL_TIE count as equal (lowest
+   axis first), so that round-off differences of the inputs cannot change which
+   formula is used (symmetric configurations tie exactly). */
+static const double NORMAL_TIE = 1e-12;
+
 /* Centred-columns candidate for column axis d: the liquid heights of the 3-cell
    columns along d at the four transverse neighbours give the transverse slopes
    m_t = (H(t=-1) - H(t=+1)) / 2; the column component is +1 when the liquid lies
    towards -d (Youngs' gradient along d negative), -1 when it lies towards +d, and the
-   candidate is invalid when that gradient is exactly zero. Returns validity; comp
-   holds the unnormalised components and *L their l1 norm. */
+   candidate is invalid when that gradient is zero (within the tie band). Returns
+   validity; comp holds the unnormalised components and *L their l1 norm. */
 static int cc_candidate(const double* c27, const double g[3], int d, double comp[3], double* L) {
     int t1, t2;
     transverse(d, &t1, &t2);
-    if (g[d] == 0.0) return 0;
+    if (fabs(g[d]) <= NORMAL_TIE) return 0;
     double H[2][2];
     for (int s = 0; s < 2; ++s) {
         int o = s == 0 ? -1 : 1;
@@ -213,16 +219,18 @@ static int cc_candidate(const double* c27, const double g[3], int d, double comp
    that fail to bracket the interface flatten that candidate, which shows as an own
    component larger than every component of Youngs' normal; in that case, or when no
    candidate is valid, Youngs' normal is used, otherwise the centred-columns one.
+   Zero tests and comparisons use the tie band NORMAL_TIE.
    method 2: the best centred-columns candidate alone (Youngs when none is valid). */
 void or_normal(const double c27[27], int method, double m[3]) {
     double g[3];
     youngs_gradient(c27, g);
     double LY = (fabs(g[0]) + fabs(g[1])) + fabs(g[2]);
     double my[3] = {1.0, 0.0, 0.0};
-    if (LY != 0.0) {
+    int flat = LY <= NORMAL_TIE;
+    if (!flat) {
         for (int i = 0; i < 3; ++i) my[i] = -g[i] / LY;
     }
-    if (method == 0 || LY == 0.0) {
+    if (method == 0 || flat) {
         memcpy(m, my, sizeof my);
         return;
     }
@@ -232,7 +240,7 @@ void or_normal(const double c27[27], int method, double m[3]) {
         double comp[3], L;
         if (!cc_candidate(c27, g, d, comp, &L)) continue;
         double own = 1.0 / L;
-        if (best < 0 || own > best_own) {
+        if (best < 0 || own > best_own + NORMAL_TIE) {
             best = d;
             best_own = own;
             best_L = L;
@@ -247,7 +255,7 @@ void or_normal(const double c27[27], int method, double m[3]) {
         double ymax = fabs(my[0]);
         if (fabs(my[1]) > ymax) ymax = fabs(my[1]);
         if (fabs(my[2]) > ymax) ymax = fabs(my[2]);
-        if (best_own > ymax) {
+        if (best_own > ymax + NORMAL_TIE) {
             memcpy(m, my, sizeof my);
             return;
         }

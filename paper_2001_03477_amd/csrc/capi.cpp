@@ -1,0 +1,502 @@
+// C-ABI of the advection library: handle life cycle, workspace layout, argument and
+// state checks, and the launch sequence of one time step.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "../../include/pcvof.h"
+#include "kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t _e = (expr);                                                        \
+        if (_e != hipSuccess)                                                          \
+            return fail(PCVOF_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(_e)); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+long face_count(const pcvof_grid& g, int a) {
+    const long nx = g.nx, ny = g.ny, nz = g.nz;
+    if (a == 0) return nz * ny * (nx + 1);
+    if (a == 1) return nz * (ny + 1) * nx;
+    return (nz + 1) * ny * nx;
+}
+
+// Workspace layout (offsets in bytes, each 256-byte aligned).
+struct Layout {
+    size_t c[2], e[2], ec, cc, vel[3], mdot, rec, part, stats, flags, total;
+    int nblocks;
+};
+
+bool grid_ok(const pcvof_grid* g) {
+    if (!g) return false;
+    if (g->ndim != 2 && g->ndim != 3) return false;
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1) return false;
+    if (g->ndim == 2 && g->nz != 1) return false;
+    if (!(g->h > 0.0) || !isfinite(g->h)) return false;
+    for (int a = 0; a < 3; ++a)
+        if (g->bc[a] != PCVOF_BC_PERIODIC && g->bc[a] != PCVOF_BC_OUTFLOW) return false;
+    const double n = (double)g->nx * g->ny * g->nz;
+    return n < 4.0e9;
+}
+
+bool params_ok(const pcvof_params* p) {
+    if (!p) return false;
+    if (!(p->cp_l > 0.0) || !(p->cp_g > 0.0) || !(p->rho_l > 0.0)) return false;
+    if (!isfinite(p->cp_l) || !isfinite(p->cp_g) || !isfinite(p->rho_l) || !isfinite(p->T_gamma)) return false;
+    if (!(p->eps_mixed >= 0.0 && p->eps_mixed < 0.5)) return false;
+    if (!(p->weno_eps > 0.0) || !isfinite(p->weno_eps)) return false;
+    if (!(p->cfl_max > 0.0 && p->cfl_max <= 1.0)) return false;
+    if (p->normal < 0 || p->normal > 2 || p->reserved != 0) return false;
+    return true;
+}
+
+pcv::Dom make_dom(const pcvof_grid& g, const pcvof_params& p) {
+    pcv::Dom d;
+    d.ndim = g.ndim;
+    d.n[0] = g.nx;
+    d.n[1] = g.ny;
+    d.n[2] = g.nz;
+    for (int a = 0; a < 3; ++a) d.bc[a] = g.bc[a];
+    d.ncell = (long)g.nx * g.ny * g.nz;
+    d.cp_l = p.cp_l;
+    d.cp_g = p.cp_g;
+    d.rho_l = p.rho_l;
+    d.T_gamma = p.T_gamma;
+    d.eps = p.eps_mixed;
+    d.weno_eps = p.weno_eps;
+    d.normal = p.normal;
+    return d;
+}
+
+Layout make_layout(const pcvof_grid& g, const pcvof_params& p) {
+    Layout L;
+    const pcv::Dom d = make_dom(g, p);
+    const size_t n = (size_t)d.ncell;
+    const size_t dbl = sizeof(double);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    for (int b = 0; b < 2; ++b) {
+        L.c[b] = take(n * dbl);
+        L.e[b] = take(n * dbl);
+    }
+    L.ec = take(n * dbl);
+    L.cc = take(n);
+    for (int a = 0; a < 3; ++a) L.vel[a] = take((a < g.ndim ? (size_t)face_count(g, a) : 1) * dbl);
+    L.mdot = take(n * dbl);
+    L.rec = take(5 * n * dbl);
+    L.nblocks = pcv::cell_launch(d).nblocks;
+    L.part = take((size_t)pcv::kSlots * L.nblocks * pcv::kPartialWidth * dbl);
+    L.stats = take(16 * dbl);
+    L.flags = take(4 * sizeof(unsigned long long));
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+struct pcvof_handle {
+    pcvof_grid g;
+    pcvof_params p;
+    pcv::Dom d;
+    Layout L;
+    char* ws;
+    hipStream_t stream;
+    int cur;                 // index of the current state buffer
+    bool has_vof, has_energy, has_vel, has_mdot;
+    double umax[3];          // max |u_f| per axis, from set_velocity
+    long step;
+    // stage bookkeeping of the step in progress
+    bool in_step;
+    int sweeps_done;
+    int slot_mask, last_slot;
+    double step_cfl;
+
+    double* c(int b) { return (double*)(ws + L.c[b]); }
+    double* e(int b) { return (double*)(ws + L.e[b]); }
+    double* ec() { return (double*)(ws + L.ec); }
+    uint8_t* cc() { return (uint8_t*)(ws + L.cc); }
+    double* vel(int a) { return (double*)(ws + L.vel[a]); }
+    double* mdot() { return (double*)(ws + L.mdot); }
+    double* rec() { return (double*)(ws + L.rec); }
+    double* part() { return (double*)(ws + L.part); }
+    double* stats() { return (double*)(ws + L.stats); }
+    unsigned int* flags() { return (unsigned int*)(ws + L.flags); }
+    unsigned long long* maxbits() { return (unsigned long long*)(ws + L.flags + 8); }
+};
+
+namespace {
+
+int check_handle(pcvof_handle* h) {
+    if (!h || !h->ws) return fail(PCVOF_ERR_ARG, "null or destroyed handle");
+    return PCVOF_OK;
+}
+
+hipMemcpyKind kind_in(int mem) { return mem == PCVOF_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice; }
+hipMemcpyKind kind_out(int mem) { return mem == PCVOF_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost; }
+
+int copy_in(pcvof_handle* h, double* dst, const double* src, size_t count, int mem) {
+    if (mem != PCVOF_MEM_HOST && mem != PCVOF_MEM_DEVICE) return fail(PCVOF_ERR_ARG, "bad mem kind %d", mem);
+    HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(double), kind_in(mem), h->stream));
+    if (mem == PCVOF_MEM_HOST) HIP_TRY(hipStreamSynchronize(h->stream));
+    return PCVOF_OK;
+}
+
+int copy_out(pcvof_handle* h, double* dst, const double* src, size_t count, int mem) {
+    if (mem != PCVOF_MEM_HOST && mem != PCVOF_MEM_DEVICE) return fail(PCVOF_ERR_ARG, "bad mem kind %d", mem);
+    HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(double), kind_out(mem), h->stream));
+    if (mem == PCVOF_MEM_HOST) HIP_TRY(hipStreamSynchronize(h->stream));
+    return PCVOF_OK;
+}
+
+// Runs the check kernel on x and returns the flags (synchronising).
+int check_field(pcvof_handle* h, const double* x, long n, int range, unsigned int* out) {
+    HIP_TRY(hipMemsetAsync(h->flags(), 0, sizeof(unsigned int), h->stream));
+    HIP_TRY(pcv::launch_check(x, n, range, h->flags(), h->stream));
+    HIP_TRY(hipMemcpyAsync(out, h->flags(), sizeof(unsigned int), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return PCVOF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pcvof_workspace_bytes(const pcvof_grid* grid, const pcvof_params* params) {
+    if (!grid_ok(grid) || !params_ok(params)) return 0;
+    return make_layout(*grid, *params).total;
+}
+
+int pcvof_create(const pcvof_grid* grid, const pcvof_params* params, void* d_workspace,
+                 size_t workspace_bytes, void* hip_stream, pcvof_handle** out) {
+    if (!out) return fail(PCVOF_ERR_ARG, "out is null");
+    *out = nullptr;
+    if (!grid_ok(grid)) return fail(PCVOF_ERR_ARG, "invalid grid");
+    if (!params_ok(params)) return fail(PCVOF_ERR_ARG, "invalid params");
+    if (!d_workspace) return fail(PCVOF_ERR_WORKSPACE, "workspace is null");
+    if (((uintptr_t)d_workspace) % kAlign) return fail(PCVOF_ERR_WORKSPACE, "workspace not 256-byte aligned");
+    const Layout L = make_layout(*grid, *params);
+    if (workspace_bytes < L.total)
+        return fail(PCVOF_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, L.total);
+    pcvof_handle* h = new (std::nothrow) pcvof_handle();
+    if (!h) return fail(PCVOF_ERR_ARG, "out of host memory");
+    h->g = *grid;
+    h->p = *params;
+    h->d = make_dom(*grid, *params);
+    h->L = L;
+    h->ws = (char*)d_workspace;
+    h->stream = (hipStream_t)hip_stream;
+    h->cur = 0;
+    h->has_vof = h->has_energy = h->has_vel = h->has_mdot = false;
+    h->umax[0] = h->umax[1] = h->umax[2] = 0.0;
+    h->step = 0;
+    h->in_step = false;
+    *out = h;
+    return PCVOF_OK;
+}
+
+int pcvof_destroy(pcvof_handle* h) {
+    if (!h) return fail(PCVOF_ERR_ARG, "null handle");
+    h->ws = nullptr;
+    delete h;
+    return PCVOF_OK;
+}
+
+int pcvof_set_vof(pcvof_handle* h, const double* c, int mem) {
+    if (int r = check_handle(h)) return r;
+    if (!c) return fail(PCVOF_ERR_ARG, "c is null");
+    if (int r = copy_in(h, h->c(h->cur), c, h->d.ncell, mem)) return r;
+    unsigned int f = 0;
+    if (int r = check_field(h, h->c(h->cur), h->d.ncell, 1, &f)) return r;
+    if (f & 1u) return fail(PCVOF_ERR_NONFINITE, "volume fraction has NaN or Inf");
+    if (f & 2u) return fail(PCVOF_ERR_BOUNDS, "volume fraction outside [0,1]");
+    h->has_vof = true;
+    return PCVOF_OK;
+}
+
+int pcvof_set_energy(pcvof_handle* h, const double* e, int mem) {
+    if (int r = check_handle(h)) return r;
+    if (!e) return fail(PCVOF_ERR_ARG, "e is null");
+    if (int r = copy_in(h, h->e(h->cur), e, h->d.ncell, mem)) return r;
+    unsigned int f = 0;
+    if (int r = check_field(h, h->e(h->cur), h->d.ncell, 0, &f)) return r;
+    if (f) return fail(PCVOF_ERR_NONFINITE, "energy has NaN or Inf");
+    h->has_energy = true;
+    return PCVOF_OK;
+}
+
+int pcvof_set_temperature(pcvof_handle* h, const double* T, int mem) {
+    if (int r = check_handle(h)) return r;
+    if (!T) return fail(PCVOF_ERR_ARG, "T is null");
+    if (!h->has_vof) return fail(PCVOF_ERR_STATE, "set_temperature needs the volume fraction first");
+    // stage T in the other energy buffer, then e = C_p(c) T
+    double* tmp = h->e(1 - h->cur);
+    if (int r = copy_in(h, tmp, T, h->d.ncell, mem)) return r;
+    unsigned int f = 0;
+    if (int r = check_field(h, tmp, h->d.ncell, 0, &f)) return r;
+    if (f) return fail(PCVOF_ERR_NONFINITE, "temperature has NaN or Inf");
+    HIP_TRY(pcv::launch_energy_from_T(h->d, h->c(h->cur), tmp, h->e(h->cur), h->stream));
+    h->has_energy = true;
+    return PCVOF_OK;
+}
+
+int pcvof_set_velocity(pcvof_handle* h, const double* u, const double* v, const double* w, int mem) {
+    if (int r = check_handle(h)) return r;
+    const double* src[3] = {u, v, w};
+    for (int a = 0; a < h->g.ndim; ++a)
+        if (!src[a]) return fail(PCVOF_ERR_ARG, "velocity component %d is null", a);
+    for (int a = 0; a < h->g.ndim; ++a) {
+        const long nf = face_count(h->g, a);
+        if (int r = copy_in(h, h->vel(a), src[a], nf, mem)) return r;
+        unsigned int f = 0;
+        HIP_TRY(hipMemsetAsync(h->flags(), 0, 16, h->stream));
+        HIP_TRY(pcv::launch_check(h->vel(a), nf, 0, h->flags(), h->stream));
+        HIP_TRY(pcv::launch_maxabs(h->vel(a), nf, h->maxbits(), h->stream));
+        if (h->g.bc[a] == PCVOF_BC_PERIODIC)
+            HIP_TRY(pcv::launch_periodic_faces(h->d, a, h->vel(a), h->flags(), h->stream));
+        unsigned long long mb = 0;
+        HIP_TRY(hipMemcpyAsync(&f, h->flags(), sizeof f, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipMemcpyAsync(&mb, h->maxbits(), sizeof mb, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        if (f & 1u) return fail(PCVOF_ERR_NONFINITE, "velocity component %d has NaN or Inf", a);
+        if (f & 4u)
+            return fail(PCVOF_ERR_ARG, "periodic axis %d: first and last face velocities differ", a);
+        double m;
+        memcpy(&m, &mb, sizeof m);
+        h->umax[a] = m;
+    }
+    h->has_vel = true;
+    return PCVOF_OK;
+}
+
+int pcvof_set_mass_flux(pcvof_handle* h, const double* mdot, int mem) {
+    if (int r = check_handle(h)) return r;
+    if (!mdot) {
+        h->has_mdot = false;
+        return PCVOF_OK;
+    }
+    if (int r = copy_in(h, h->mdot(), mdot, h->d.ncell, mem)) return r;
+    unsigned int f = 0;
+    if (int r = check_field(h, h->mdot(), h->d.ncell, 0, &f)) return r;
+    if (f) return fail(PCVOF_ERR_NONFINITE, "mass flux has NaN or Inf");
+    h->has_mdot = true;
+    return PCVOF_OK;
+}
+
+int pcvof_begin_step(pcvof_handle* h) {
+    if (int r = check_handle(h)) return r;
+    if (!h->has_vof || !h->has_energy) return fail(PCVOF_ERR_STATE, "volume fraction and energy must be set");
+    HIP_TRY(pcv::launch_prologue(h->d, h->c(h->cur), h->e(h->cur), h->cc(), h->ec(), h->stream));
+    h->in_step = true;
+    h->sweeps_done = 0;
+    h->slot_mask = 0;
+    h->last_slot = -1;
+    h->step_cfl = 0.0;
+    return PCVOF_OK;
+}
+
+int pcvof_sweep(pcvof_handle* h, int axis, double dt, double u_scale) {
+    if (int r = check_handle(h)) return r;
+    if (!h->in_step) return fail(PCVOF_ERR_STATE, "sweep outside begin_step / end_step");
+    if (!h->has_vel) return fail(PCVOF_ERR_STATE, "velocity not set");
+    if (axis < 0 || axis >= h->g.ndim) return fail(PCVOF_ERR_ARG, "bad axis %d", axis);
+    if (h->sweeps_done >= 3) return fail(PCVOF_ERR_STATE, "more than three sweeps in one step");
+    if (!isfinite(dt) || !(dt >= 0.0) || !isfinite(u_scale)) return fail(PCVOF_ERR_ARG, "bad dt or u_scale");
+    const double kfac = (u_scale * dt) / h->g.h;
+    const double cfl = h->umax[axis] * fabs(kfac);
+    if (cfl > h->p.cfl_max)
+        return fail(PCVOF_ERR_CFL, "axis %d: CFL %.6g above the limit %.6g", axis, cfl, h->p.cfl_max);
+    if (cfl > h->step_cfl) h->step_cfl = cfl;
+    const int slot = h->sweeps_done;
+    double* part = h->part() + (size_t)slot * h->L.nblocks * pcv::kPartialWidth;
+    const int nxt = 1 - h->cur;
+    HIP_TRY(pcv::launch_sweep(h->d, axis, h->c(h->cur), h->e(h->cur), h->cc(), h->ec(), h->vel(axis), kfac,
+                              h->c(nxt), h->e(nxt), part, h->stream));
+    h->cur = nxt;
+    h->sweeps_done++;
+    h->slot_mask |= 1 << slot;
+    h->last_slot = slot;
+    return PCVOF_OK;
+}
+
+int pcvof_phase_change(pcvof_handle* h, double dt) {
+    if (int r = check_handle(h)) return r;
+    if (!h->in_step) return fail(PCVOF_ERR_STATE, "phase_change outside begin_step / end_step");
+    if (!h->has_mdot) return fail(PCVOF_ERR_STATE, "mass flux not set");
+    if (!isfinite(dt) || !(dt >= 0.0)) return fail(PCVOF_ERR_ARG, "bad dt");
+    const int slot = 3;
+    double* part = h->part() + (size_t)slot * h->L.nblocks * pcv::kPartialWidth;
+    const int nxt = 1 - h->cur;
+    HIP_TRY(pcv::launch_phase(h->d, h->c(h->cur), h->e(h->cur), h->mdot(), dt, h->g.h, h->rec(), h->c(nxt),
+                              h->e(nxt), part, h->stream));
+    h->cur = nxt;
+    h->slot_mask |= 1 << slot;
+    h->last_slot = slot;
+    return PCVOF_OK;
+}
+
+int pcvof_end_step(pcvof_handle* h, pcvof_stats* stats) {
+    if (int r = check_handle(h)) return r;
+    if (!h->in_step) return fail(PCVOF_ERR_STATE, "end_step without begin_step");
+    h->in_step = false;
+    h->step++;
+    if (h->last_slot < 0) return fail(PCVOF_ERR_STATE, "empty step");
+    const double hv = h->g.ndim == 3 ? h->g.h * h->g.h * h->g.h : h->g.h * h->g.h;
+    HIP_TRY(pcv::launch_reduce(h->part(), h->L.nblocks, h->slot_mask, h->last_slot, hv, h->stats(), h->stream));
+    if (stats) {
+        double s[10];
+        HIP_TRY(hipMemcpyAsync(s, h->stats(), sizeof s, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        stats->vol = s[0];
+        stats->energy = s[1];
+        stats->vol_clip = s[2];
+        stats->energy_clip = s[3];
+        stats->vol_phase = s[4];
+        stats->energy_phase = s[5];
+        stats->vol_bnd_out = s[6];
+        stats->energy_bnd_out = s[7];
+        stats->vol_src = s[8];
+        stats->energy_src = s[9];
+        stats->max_cfl = h->step_cfl;
+    }
+    return PCVOF_OK;
+}
+
+int pcvof_advect_step(pcvof_handle* h, double dt, double u_scale, pcvof_stats* stats) {
+    if (int r = check_handle(h)) return r;
+    if (!h->has_vel) return fail(PCVOF_ERR_STATE, "velocity not set");
+    if (!isfinite(dt) || !(dt >= 0.0) || !isfinite(u_scale)) return fail(PCVOF_ERR_ARG, "bad dt or u_scale");
+    // check the CFL limit of all axes before anything is enqueued
+    const double kfac = (u_scale * dt) / h->g.h;
+    for (int a = 0; a < h->g.ndim; ++a)
+        if (h->umax[a] * fabs(kfac) > h->p.cfl_max)
+            return fail(PCVOF_ERR_CFL, "axis %d: CFL %.6g above the limit %.6g", a, h->umax[a] * fabs(kfac),
+                        h->p.cfl_max);
+    if (int r = pcvof_begin_step(h)) return r;
+    for (int s = 0; s < h->g.ndim; ++s) {
+        const int axis = (int)((h->step + s) % h->g.ndim);
+        if (int r = pcvof_sweep(h, axis, dt, u_scale)) {
+            h->in_step = false;
+            return r;
+        }
+    }
+    if (h->has_mdot) {
+        if (int r = pcvof_phase_change(h, dt)) {
+            h->in_step = false;
+            return r;
+        }
+    }
+    return pcvof_end_step(h, stats);
+}
+
+int pcvof_get_vof(pcvof_handle* h, double* out, int mem) {
+    if (int r = check_handle(h)) return r;
+    if (!out) return fail(PCVOF_ERR_ARG, "out is null");
+    if (!h->has_vof) return fail(PCVOF_ERR_STATE, "volume fraction not set");
+    return copy_out(h, out, h->c(h->cur), h->d.ncell, mem);
+}
+
+int pcvof_get_energy(pcvof_handle* h, double* out, int mem) {
+    if (int r = check_handle(h)) return r;
+    if (!out) return fail(PCVOF_ERR_ARG, "out is null");
+    if (!h->has_energy) return fail(PCVOF_ERR_STATE, "energy not set");
+    return copy_out(h, out, h->e(h->cur), h->d.ncell, mem);
+}
+
+int pcvof_get_temperature(pcvof_handle* h, double* out, int mem) {
+    if (int r = check_handle(h)) return r;
+    if (!out) return fail(PCVOF_ERR_ARG, "out is null");
+    if (!h->has_vof || !h->has_energy) return fail(PCVOF_ERR_STATE, "fields not set");
+    if (h->in_step) return fail(PCVOF_ERR_STATE, "get_temperature inside a step");
+    // T in the spare energy buffer, then copy out
+    double* tmp = h->e(1 - h->cur);
+    HIP_TRY(pcv::launch_T_from_energy(h->d, h->c(h->cur), h->e(h->cur), tmp, h->stream));
+    return copy_out(h, out, tmp, h->d.ncell, mem);
+}
+
+int pcvof_get_step(pcvof_handle* h, long* step) {
+    if (int r = check_handle(h)) return r;
+    if (!step) return fail(PCVOF_ERR_ARG, "step is null");
+    *step = h->step;
+    return PCVOF_OK;
+}
+
+int pcvof_set_step(pcvof_handle* h, long step) {
+    if (int r = check_handle(h)) return r;
+    if (step < 0) return fail(PCVOF_ERR_ARG, "negative step");
+    if (h->in_step) return fail(PCVOF_ERR_STATE, "set_step inside a step");
+    h->step = step;
+    return PCVOF_OK;
+}
+
+const char* pcvof_last_error(void) { return g_err.c_str(); }
+
+#define GEOM_GUARD(cond)                                              \
+    do {                                                              \
+        if (n < 0) return fail(PCVOF_ERR_ARG, "negative n");          \
+        if (n == 0) return PCVOF_OK;                                  \
+        if (!(cond)) return fail(PCVOF_ERR_ARG, "null array argument"); \
+    } while (0)
+
+int pcvof_geom_volume(int n, const double* m, const double* alpha, double* out, void* stream) {
+    GEOM_GUARD(m && alpha && out);
+    HIP_TRY(pcv::launch_geom_volume(n, m, alpha, out, (hipStream_t)stream));
+    return PCVOF_OK;
+}
+
+int pcvof_geom_alpha(int n, const double* m, const double* c, double* out, void* stream) {
+    GEOM_GUARD(m && c && out);
+    HIP_TRY(pcv::launch_geom_alpha(n, m, c, out, (hipStream_t)stream));
+    return PCVOF_OK;
+}
+
+int pcvof_geom_slab(int n, const double* m, const double* alpha, const int* axis, const double* lam,
+                    double* out, void* stream) {
+    GEOM_GUARD(m && alpha && axis && lam && out);
+    HIP_TRY(pcv::launch_geom_slab(n, m, alpha, axis, lam, out, (hipStream_t)stream));
+    return PCVOF_OK;
+}
+
+int pcvof_geom_normal(int n, const double* c27, int method, double* m, void* stream) {
+    GEOM_GUARD(c27 && m);
+    if (method < 0 || method > 2) return fail(PCVOF_ERR_ARG, "bad normal method %d", method);
+    HIP_TRY(pcv::launch_geom_normal(n, c27, method, m, (hipStream_t)stream));
+    return PCVOF_OK;
+}
+
+int pcvof_geom_weno5(int n, const double* v, double eps, double* out, void* stream) {
+    GEOM_GUARD(v && out);
+    HIP_TRY(pcv::launch_geom_weno5(n, v, eps, out, (hipStream_t)stream));
+    return PCVOF_OK;
+}
+
+}  // extern "C"

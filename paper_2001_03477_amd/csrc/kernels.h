@@ -1,0 +1,60 @@
+// Internal interface between the C-ABI layer and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pcv {
+
+// Everything a kernel needs to know about a domain, passed by value.
+struct Dom {
+    int ndim;
+    int n[3];      // cells per axis
+    int bc[3];     // 0 periodic, 1 outflow
+    long ncell;
+    double cp_l, cp_g, rho_l, T_gamma, eps, weno_eps;
+    int normal;
+};
+
+// Per-block partial sums written by every stage kernel: 8 doubles per block.
+// Sweeps: clip_v, clip_e, bnd_v, bnd_e, src_v, src_e, tot_v, tot_e.
+// Phase change: phase_v, phase_e, 0, 0, 0, 0, tot_v, tot_e.
+constexpr int kPartialWidth = 8;
+constexpr int kSlots = 4;  // 3 sweeps + phase change
+
+struct Launch {
+    dim3 grid, block;
+    int nblocks;
+};
+Launch cell_launch(const Dom& d);
+
+hipError_t launch_prologue(const Dom& d, const double* c, const double* e, uint8_t* cc, double* ec,
+                           hipStream_t s);
+hipError_t launch_sweep(const Dom& d, int axis, const double* c, const double* e, const uint8_t* cc,
+                        const double* ec, const double* vel, double kfac, double* c_out,
+                        double* e_out, double* part, hipStream_t s);
+hipError_t launch_phase(const Dom& d, const double* c, const double* e, const double* mdot, double dt,
+                        double h, double* rec, double* c_out, double* e_out, double* part,
+                        hipStream_t s);
+// stats[0..9] = vol, energy, clip_v, clip_e, phase_v, phase_e, bnd_v, bnd_e, src_v, src_e
+hipError_t launch_reduce(const double* part, int nblocks, int slot_mask, int last_slot, double hv,
+                         double* stats, hipStream_t s);
+
+hipError_t launch_energy_from_T(const Dom& d, const double* c, const double* T, double* e, hipStream_t s);
+hipError_t launch_T_from_energy(const Dom& d, const double* c, const double* e, double* T, hipStream_t s);
+// flags[0] |= 1 (non-finite), 2 (outside [0,1] when check_range)
+hipError_t launch_check(const double* x, long n, int check_range, unsigned int* flags, hipStream_t s);
+// *maxbits = max over |x| as the bit pattern of a non-negative double (atomic max)
+hipError_t launch_maxabs(const double* x, long n, unsigned long long* maxbits, hipStream_t s);
+// flags |= 4 when the two boundary faces of a periodic axis differ
+hipError_t launch_periodic_faces(const Dom& d, int axis, const double* vel, unsigned int* flags,
+                                 hipStream_t s);
+
+hipError_t launch_geom_volume(int n, const double* m, const double* a, double* out, hipStream_t s);
+hipError_t launch_geom_alpha(int n, const double* m, const double* c, double* out, hipStream_t s);
+hipError_t launch_geom_slab(int n, const double* m, const double* a, const int* axis, const double* lam,
+                            double* out, hipStream_t s);
+hipError_t launch_geom_normal(int n, const double* c27, int method, double* m, hipStream_t s);
+hipError_t launch_geom_weno5(int n, const double* v, double eps, double* out, hipStream_t s);
+
+}  // namespace pcv

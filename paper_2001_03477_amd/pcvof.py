@@ -1,0 +1,306 @@
+"""Python binding of the pcvof C-ABI (include/pcvof.h): argument marshalling only.
+
+Every step of the advection runs in the HIP library ``libpcvof.so``; torch provides
+the device workspace and the stream. Loading fails loudly when the library is
+missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpcvof.so")
+
+PCVOF_MEM_HOST, PCVOF_MEM_DEVICE = 0, 1
+BC_PERIODIC, BC_OUTFLOW = 0, 1
+NORMAL_YOUNGS, NORMAL_MYC, NORMAL_CC = 0, 1, 2
+
+STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_CFL", -3: "ERR_NONFINITE", -4: "ERR_BOUNDS",
+          -5: "ERR_WORKSPACE", -6: "ERR_HIP", -7: "ERR_STATE"}
+
+EXPORTS = (
+    "pcvof_workspace_bytes", "pcvof_create", "pcvof_destroy", "pcvof_set_vof", "pcvof_set_energy",
+    "pcvof_set_temperature", "pcvof_set_velocity", "pcvof_set_mass_flux", "pcvof_advect_step",
+    "pcvof_begin_step", "pcvof_sweep", "pcvof_phase_change", "pcvof_end_step", "pcvof_get_vof",
+    "pcvof_get_energy", "pcvof_get_temperature", "pcvof_get_step", "pcvof_set_step",
+    "pcvof_last_error", "pcvof_geom_volume", "pcvof_geom_alpha", "pcvof_geom_slab",
+    "pcvof_geom_normal", "pcvof_geom_weno5",
+)
+
+
+class PcvofError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Grid(C.Structure):
+    _fields_ = [("ndim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("h", C.c_double), ("bc", C.c_int * 3)]
+
+
+class Params(C.Structure):
+    _fields_ = [("cp_l", C.c_double), ("cp_g", C.c_double), ("rho_l", C.c_double),
+                ("T_gamma", C.c_double), ("eps_mixed", C.c_double), ("weno_eps", C.c_double),
+                ("cfl_max", C.c_double), ("normal", C.c_int), ("reserved", C.c_int)]
+
+
+STAT_NAMES = ("vol", "energy", "vol_clip", "energy_clip", "vol_phase", "energy_phase",
+              "vol_bnd_out", "energy_bnd_out", "vol_src", "energy_src", "max_cfl")
+
+
+class Stats(C.Structure):
+    _fields_ = [(n, C.c_double) for n in STAT_NAMES]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n in STAT_NAMES}
+
+
+_lib = None
+_vp = C.c_void_p
+_dp = C.POINTER(C.c_double)
+
+
+def lib():
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2001_03477_amd.build` (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        L.pcvof_workspace_bytes.restype = C.c_size_t
+        L.pcvof_workspace_bytes.argtypes = [C.POINTER(Grid), C.POINTER(Params)]
+        L.pcvof_create.argtypes = [C.POINTER(Grid), C.POINTER(Params), _vp, C.c_size_t, _vp,
+                                   C.POINTER(_vp)]
+        L.pcvof_destroy.argtypes = [_vp]
+        for nm in ("pcvof_set_vof", "pcvof_set_energy", "pcvof_set_temperature",
+                   "pcvof_set_mass_flux", "pcvof_get_vof", "pcvof_get_energy",
+                   "pcvof_get_temperature"):
+            getattr(L, nm).argtypes = [_vp, _vp, C.c_int]
+        L.pcvof_set_velocity.argtypes = [_vp, _vp, _vp, _vp, C.c_int]
+        L.pcvof_advect_step.argtypes = [_vp, C.c_double, C.c_double, C.POINTER(Stats)]
+        L.pcvof_begin_step.argtypes = [_vp]
+        L.pcvof_sweep.argtypes = [_vp, C.c_int, C.c_double, C.c_double]
+        L.pcvof_phase_change.argtypes = [_vp, C.c_double]
+        L.pcvof_end_step.argtypes = [_vp, C.POINTER(Stats)]
+        L.pcvof_get_step.argtypes = [_vp, C.POINTER(C.c_long)]
+        L.pcvof_set_step.argtypes = [_vp, C.c_long]
+        L.pcvof_last_error.restype = C.c_char_p
+        L.pcvof_last_error.argtypes = []
+        L.pcvof_geom_volume.argtypes = [C.c_int, _vp, _vp, _vp, _vp]
+        L.pcvof_geom_alpha.argtypes = [C.c_int, _vp, _vp, _vp, _vp]
+        L.pcvof_geom_slab.argtypes = [C.c_int, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.pcvof_geom_normal.argtypes = [C.c_int, _vp, C.c_int, _vp, _vp]
+        L.pcvof_geom_weno5.argtypes = [C.c_int, _vp, C.c_double, _vp, _vp]
+        for nm in EXPORTS:
+            f = getattr(L, nm)
+            if nm not in ("pcvof_workspace_bytes", "pcvof_last_error"):
+                f.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def check(rc: int):
+    if rc != 0:
+        raise PcvofError(rc, lib().pcvof_last_error().decode())
+
+
+def _stream_ptr(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+@dataclass
+class DomainSpec:
+    shape: tuple              # (nz, ny, nx); nz == 1 for 2D
+    h: float
+    ndim: int = 3
+    bc: tuple = (0, 0, 0)     # per axis x, y, z
+    cp_l: float = 1.0
+    cp_g: float = 1.0
+    rho_l: float = 1.0
+    T_gamma: float = 1.0
+    eps_mixed: float = 1e-12
+    weno_eps: float = 1e-6
+    cfl_max: float = 0.5
+    normal: int = NORMAL_MYC
+
+    def grid(self) -> Grid:
+        nz, ny, nx = self.shape
+        g = Grid(self.ndim, nx, ny, nz, self.h)
+        for a in range(3):
+            g.bc[a] = int(self.bc[a])
+        return g
+
+    def params(self) -> Params:
+        return Params(self.cp_l, self.cp_g, self.rho_l, self.T_gamma, self.eps_mixed,
+                      self.weno_eps, self.cfl_max, int(self.normal), 0)
+
+
+def workspace_bytes(spec: DomainSpec) -> int:
+    g, p = spec.grid(), spec.params()
+    n = lib().pcvof_workspace_bytes(C.byref(g), C.byref(p))
+    if n == 0:
+        raise PcvofError(-1, "invalid grid or params")
+    return int(n)
+
+
+class Domain:
+    """One advected domain bound to a torch-owned device workspace and stream."""
+
+    def __init__(self, spec: DomainSpec, device="cuda", stream=None):
+        import torch
+        self.spec = spec
+        self.device = torch.device(device)
+        nbytes = workspace_bytes(spec)
+        # torch's caching allocator returns 256-byte (or better) aligned blocks
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream
+        self._h = _vp()
+        g, p = spec.grid(), spec.params()
+        check(lib().pcvof_create(C.byref(g), C.byref(p), self.workspace.data_ptr(), nbytes,
+                                 _stream_ptr(stream), C.byref(self._h)))
+
+    # -- helpers
+    @property
+    def ncell(self) -> int:
+        return int(np.prod(self.spec.shape))
+
+    def _dev(self, a):
+        import torch
+        t = torch.as_tensor(a, dtype=torch.float64)
+        if t.device != self.device:
+            t = t.to(self.device)
+        return t.contiguous()
+
+    def _set(self, fn, a):
+        if a is None:
+            check(fn(self._h, None, PCVOF_MEM_DEVICE))
+            return
+        t = self._dev(a)
+        check(fn(self._h, t.data_ptr(), PCVOF_MEM_DEVICE))
+        self._keep = t  # keep alive until the asynchronous copy has been enqueued and run
+
+    def set_vof(self, c):
+        self._set(lib().pcvof_set_vof, c)
+
+    def set_energy(self, e):
+        self._set(lib().pcvof_set_energy, e)
+
+    def set_temperature(self, T):
+        self._set(lib().pcvof_set_temperature, T)
+
+    def set_mass_flux(self, mdot):
+        self._set(lib().pcvof_set_mass_flux, mdot)
+
+    def set_velocity(self, u, v, w=None):
+        tu, tv = self._dev(u), self._dev(v)
+        tw = self._dev(w) if w is not None else None
+        check(lib().pcvof_set_velocity(self._h, tu.data_ptr(), tv.data_ptr(),
+                                       tw.data_ptr() if tw is not None else None,
+                                       PCVOF_MEM_DEVICE))
+        self._keep = (tu, tv, tw)
+
+    def _get(self, fn):
+        import torch
+        out = torch.empty(self.spec.shape, dtype=torch.float64, device=self.device)
+        check(fn(self._h, out.data_ptr(), PCVOF_MEM_DEVICE))
+        return out
+
+    def vof(self):
+        return self._get(lib().pcvof_get_vof)
+
+    def energy(self):
+        return self._get(lib().pcvof_get_energy)
+
+    def temperature(self):
+        return self._get(lib().pcvof_get_temperature)
+
+    # -- stepping
+    def step(self, dt: float, u_scale: float = 1.0, stats: bool = False):
+        st = Stats() if stats else None
+        check(lib().pcvof_advect_step(self._h, float(dt), float(u_scale),
+                                      C.byref(st) if st is not None else None))
+        return st.as_dict() if st is not None else None
+
+    def begin_step(self):
+        check(lib().pcvof_begin_step(self._h))
+
+    def sweep(self, axis: int, dt: float, u_scale: float = 1.0):
+        check(lib().pcvof_sweep(self._h, int(axis), float(dt), float(u_scale)))
+
+    def phase_change(self, dt: float):
+        check(lib().pcvof_phase_change(self._h, float(dt)))
+
+    def end_step(self, stats: bool = True):
+        st = Stats() if stats else None
+        check(lib().pcvof_end_step(self._h, C.byref(st) if st is not None else None))
+        return st.as_dict() if st is not None else None
+
+    @property
+    def step_index(self) -> int:
+        v = C.c_long()
+        check(lib().pcvof_get_step(self._h, C.byref(v)))
+        return v.value
+
+    @step_index.setter
+    def step_index(self, n: int):
+        check(lib().pcvof_set_step(self._h, int(n)))
+
+    def close(self):
+        if self._h:
+            check(lib().pcvof_destroy(self._h))
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ batched geometry
+def geom_volume(m, alpha):
+    import torch
+    out = torch.empty_like(alpha)
+    check(lib().pcvof_geom_volume(alpha.numel(), m.data_ptr(), alpha.data_ptr(), out.data_ptr(),
+                                  _stream_ptr()))
+    return out
+
+
+def geom_alpha(m, c):
+    import torch
+    out = torch.empty_like(c)
+    check(lib().pcvof_geom_alpha(c.numel(), m.data_ptr(), c.data_ptr(), out.data_ptr(),
+                                 _stream_ptr()))
+    return out
+
+
+def geom_slab(m, alpha, axis, lam):
+    import torch
+    out = torch.empty_like(alpha)
+    check(lib().pcvof_geom_slab(alpha.numel(), m.data_ptr(), alpha.data_ptr(), axis.data_ptr(),
+                                lam.data_ptr(), out.data_ptr(), _stream_ptr()))
+    return out
+
+
+def geom_normal(c27, method: int):
+    import torch
+    n = c27.shape[0]
+    out = torch.empty((n, 3), dtype=torch.float64, device=c27.device)
+    check(lib().pcvof_geom_normal(n, c27.data_ptr(), int(method), out.data_ptr(), _stream_ptr()))
+    return out
+
+
+def geom_weno5(v, eps: float = 1e-6):
+    import torch
+    n = v.shape[0]
+    out = torch.empty(n, dtype=torch.float64, device=v.device)
+    check(lib().pcvof_geom_weno5(n, v.data_ptr(), float(eps), out.data_ptr(), _stream_ptr()))
+    return out
