@@ -95,46 +95,26 @@ def main():
         dom.set_mass_flux(wl.mdot)
     vol0 = float(dom.vof().sum()) * wl.h ** wl.ndim
 
-    def one_step(n, ev=None):
-        dom.begin_step()
-        for s in range(wl.ndim):
-            axis = (n + s) % wl.ndim
-            if ev is not None:
-                ev[s][0].record(stream)
-            dom.sweep(axis, wl.dt, wl.u_scale(n))
-            if ev is not None:
-                ev[s][1].record(stream)
-        if wl.mdot is not None:
-            dom.phase_change(wl.dt)
-        dom.end_step(stats=False)
-
-    n = 0
-    for _ in range(args.warmup):
-        one_step(n)
-        n += 1
+    scales = np.array([wl.u_scale(k) for k in range(args.warmup + args.steps)])
+    dom.steps(args.warmup, wl.dt, scales[:args.warmup])
     torch.cuda.synchronize()
-    events = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
-               for _ in range(wl.ndim)] for _ in range(args.steps)]
+    # kernel durations: HIP events recorded by the library around each of its launches,
+    # on the stream the kernels run on, over the timed steps
+    dom.set_profiling(True)
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t_start.record(stream)
-    for k in range(args.steps):
-        one_step(n, events[k])
-        n += 1
+    dom.steps(args.steps, wl.dt, scales[args.warmup:])
     t_end.record(stream)
     torch.cuda.synchronize()
     total_ms = t_start.elapsed_time(t_end)
-    sweep_ms = np.zeros(wl.ndim)
-    sweep_bytes_tot = 0.0
-    for k in range(args.steps):
-        for s in range(wl.ndim):
-            axis = (args.warmup + k + s) % wl.ndim
-            sweep_ms[axis] += events[k][s][0].elapsed_time(events[k][s][1])
-            sweep_bytes_tot += sweep_bytes(wl, axis)
-    nsweeps = args.steps * wl.ndim
-    avg_sweep_ms = float(sweep_ms.sum() / nsweeps)
-    achieved = sweep_bytes_tot / nsweeps / (avg_sweep_ms * 1e-3) / 1e9
+    prof = dom.profile()
+    dom.set_profiling(False)
+    sweep_ms = np.array([prof[f"sweep_{a}"]["ms"] for a in "xyz"[:wl.ndim]])
+    sweep_n = np.array([prof[f"sweep_{a}"]["launches"] for a in "xyz"[:wl.ndim]])
+    sweep_bytes_tot = sum(sweep_bytes(wl, a) * sweep_n[a] for a in range(wl.ndim))
+    avg_sweep_ms = float(sweep_ms.sum() / sweep_n.sum())
+    achieved = sweep_bytes_tot / (sweep_ms.sum() * 1e-3) / 1e9
     vol1 = float(dom.vof().sum()) * wl.h ** wl.ndim
 
     value = wl.ncells * args.steps / (total_ms * 1e-3)
@@ -157,8 +137,11 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_sweep (x, y, z)", "avg_launch_ms": avg_sweep_ms,
-                     "per_axis_ms": [float(t / args.steps) for t in sweep_ms]},
+                     "kernel": "k_sweep_x / k_sweep_t<1> / k_sweep_t<2>",
+                     "avg_launch_ms": avg_sweep_ms,
+                     "per_axis_ms": [float(t / n) for t, n in zip(sweep_ms, sweep_n)],
+                     "bytes_per_cell": SWEEP_BYTES_PER_CELL},
+        "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items() if v["launches"]},
         "volume_drift": abs(vol1 - vol0) / vol0,
     }
     if not args.no_cpu_baseline:

@@ -127,6 +127,33 @@ int pcvof_sweep(pcvof_handle* h, int axis, double dt, double u_scale);
 int pcvof_phase_change(pcvof_handle* h, double dt);
 int pcvof_end_step(pcvof_handle* h, pcvof_stats* stats);
 
+/* nsteps consecutive pcvof_advect_step calls from one host call, with the velocity
+   scale of step k in u_scale[k] (host array of nsteps values; NULL = 1 for all).
+   last (nullable) receives the checksums of the final step. */
+int pcvof_advect_steps(pcvof_handle* h, int nsteps, double dt, const double* u_scale,
+                       pcvof_stats* last);
+
+/* Kernel timing. While enabled, every launch of the library is bracketed by HIP events
+   recorded on the library's stream; pcvof_get_profile waits for the stream and returns
+   the accumulated device time per kernel class since profiling was (re)enabled.
+   Enabling resets the accumulators; disabling keeps them readable. */
+enum {
+    PCVOF_PROF_GEOMETRY = 0,  /* reconstruction of the mixed donors of a sweep */
+    PCVOF_PROF_SWEEP_X = 1,   /* sweep kernels, per axis */
+    PCVOF_PROF_SWEEP_Y = 2,
+    PCVOF_PROF_SWEEP_Z = 3,
+    PCVOF_PROF_PHASE = 4,     /* step 2 (both of its kernels) */
+    PCVOF_PROF_CHECKSUM = 5,  /* column sums of the checksums */
+    PCVOF_PROF_CLASSIFY = 6,  /* mixed-cell list after the fractions were set */
+    PCVOF_PROF_CLASSES = 7
+};
+typedef struct {
+    double ms[PCVOF_PROF_CLASSES];     /* total device time, milliseconds */
+    long launches[PCVOF_PROF_CLASSES];
+} pcvof_profile;
+int pcvof_set_profiling(pcvof_handle* h, int enable);
+int pcvof_get_profile(pcvof_handle* h, pcvof_profile* out);
+
 /* Field output (same layout as the input). */
 int pcvof_get_vof(pcvof_handle* h, double* out, int mem);
 int pcvof_get_energy(pcvof_handle* h, double* out, int mem);

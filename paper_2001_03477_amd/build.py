@@ -1,7 +1,8 @@
 """Builds the HIP library libpcvof.so for gfx950 (MI355X) in-tree with hipcc.
 
-Floating-point contraction is off (the decisions of the reconstruction are
-evaluated exactly as written) and packed FP32 instructions are disabled."""
+Multiply-adds are contracted into FMAs except in the interface-normal estimator,
+which turns contraction off in its own scope so that its decisions are evaluated
+exactly as written; packed FP32 instructions are disabled."""
 import os
 import subprocess
 import sys
@@ -12,9 +13,9 @@ LIB = os.path.join(HERE, "libpcvof.so")
 ARCH = os.environ.get("PCVOF_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall",
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=fast", "-Wall",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["kernels.hip", "capi.cpp"]
+SOURCES = ["sweep.hip", "kernels.hip", "capi.cpp"]
 
 
 def build(verbose: bool = False) -> str:

@@ -10,6 +10,8 @@
 
 #include <new>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "../../include/pcvof.h"
 #include "kernels.h"
@@ -49,8 +51,8 @@ long face_count(const pcvof_grid& g, int a) {
 
 // Workspace layout (offsets in bytes, each 256-byte aligned).
 struct Layout {
-    size_t c[2], e[2], ec, cc, vel[3], mdot, rec, part, stats, flags, total;
-    int nblocks;
+    size_t c[2], e[2], ec, cc, vel[3], fgeo, mdot, rec, list[2], counts, part, colsum, flags, total;
+    int maxb;  // rows of each partial table
 };
 
 bool grid_ok(const pcvof_grid* g) {
@@ -111,12 +113,21 @@ Layout make_layout(const pcvof_grid& g, const pcvof_params& p) {
     }
     L.ec = take(n * dbl);
     L.cc = take(n);
-    for (int a = 0; a < 3; ++a) L.vel[a] = take((a < g.ndim ? (size_t)face_count(g, a) : 1) * dbl);
+    size_t maxf = 1;
+    for (int a = 0; a < 3; ++a) {
+        const size_t nf = a < g.ndim ? (size_t)face_count(g, a) : 1;
+        L.vel[a] = take(nf * dbl);
+        if (nf > maxf) maxf = nf;
+    }
+    L.fgeo = take(maxf * dbl);
     L.mdot = take(n * dbl);
     L.rec = take(5 * n * dbl);
-    L.nblocks = pcv::cell_launch(d).nblocks;
-    L.part = take((size_t)pcv::kSlots * L.nblocks * pcv::kPartialWidth * dbl);
-    L.stats = take(16 * dbl);
+    L.list[0] = take(n * sizeof(unsigned));
+    L.list[1] = take(n * sizeof(unsigned));
+    L.counts = take(2 * sizeof(unsigned));
+    L.maxb = pcv::max_partial_blocks(d);
+    L.part = take((size_t)pcv::kSlots * pcv::kPartialWidth * L.maxb * dbl);
+    L.colsum = take((size_t)pcv::kSlots * pcv::kPartialWidth * dbl);
     L.flags = take(4 * sizeof(unsigned long long));
     L.total = off;
     return L;
@@ -132,14 +143,23 @@ struct pcvof_handle {
     char* ws;
     hipStream_t stream;
     int cur;                 // index of the current state buffer
+    int lcur;                // index of the list holding the mixed cells of the current state
+    bool list_valid;
     bool has_vof, has_energy, has_vel, has_mdot;
     double umax[3];          // max |u_f| per axis, from set_velocity
     long step;
     // stage bookkeeping of the step in progress
-    bool in_step;
+    bool in_step, first_pending;
     int sweeps_done;
-    int slot_mask, last_slot;
+    int nb[pcv::kSlots];  // partial rows written per slot (0: stage did not run)
+    int last_slot;
     double step_cfl;
+    // kernel timing
+    bool prof_on;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending[PCVOF_PROF_CLASSES];
+    std::vector<hipEvent_t> prof_pool;
+    double prof_ms[PCVOF_PROF_CLASSES];
+    long prof_n[PCVOF_PROF_CLASSES];
 
     double* c(int b) { return (double*)(ws + L.c[b]); }
     double* e(int b) { return (double*)(ws + L.e[b]); }
@@ -148,13 +168,59 @@ struct pcvof_handle {
     double* vel(int a) { return (double*)(ws + L.vel[a]); }
     double* mdot() { return (double*)(ws + L.mdot); }
     double* rec() { return (double*)(ws + L.rec); }
-    double* part() { return (double*)(ws + L.part); }
-    double* stats() { return (double*)(ws + L.stats); }
+    double* fgeo() { return (double*)(ws + L.fgeo); }
+    unsigned* list(int b) { return (unsigned*)(ws + L.list[b]); }
+    unsigned* count(int b) { return (unsigned*)(ws + L.counts) + b; }
+    double* part(int slot) { return (double*)(ws + L.part) + (size_t)slot * pcv::kPartialWidth * L.maxb; }
+    double* colsum() { return (double*)(ws + L.colsum); }
     unsigned int* flags() { return (unsigned int*)(ws + L.flags); }
     unsigned long long* maxbits() { return (unsigned long long*)(ws + L.flags + 8); }
 };
 
 namespace {
+
+hipEvent_t prof_event(pcvof_handle* h) {
+    if (!h->prof_pool.empty()) {
+        hipEvent_t e = h->prof_pool.back();
+        h->prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records the start event of a launch of class cls; returns the pending slot or -1.
+int prof_begin(pcvof_handle* h, int cls) {
+    if (!h->prof_on) return -1;
+    hipEvent_t a = prof_event(h), b = prof_event(h);
+    if (!a || !b) return -1;
+    hipEventRecord(a, h->stream);
+    h->prof_pending[cls].push_back({a, b});
+    return (int)h->prof_pending[cls].size() - 1;
+}
+
+void prof_end(pcvof_handle* h, int cls, int slot) {
+    if (slot < 0) return;
+    hipEventRecord(h->prof_pending[cls][slot].second, h->stream);
+}
+
+// Waits for the stream, folds the pending event pairs into the totals and recycles them.
+int prof_collect(pcvof_handle* h) {
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (int k = 0; k < PCVOF_PROF_CLASSES; ++k) {
+        for (auto& pr : h->prof_pending[k]) {
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+            h->prof_ms[k] += ms;
+            h->prof_n[k] += 1;
+            h->prof_pool.push_back(pr.first);
+            h->prof_pool.push_back(pr.second);
+        }
+        h->prof_pending[k].clear();
+    }
+    return PCVOF_OK;
+}
 
 int check_handle(pcvof_handle* h) {
     if (!h || !h->ws) return fail(PCVOF_ERR_ARG, "null or destroyed handle");
@@ -187,6 +253,16 @@ int check_field(pcvof_handle* h, const double* x, long n, int range, unsigned in
     return PCVOF_OK;
 }
 
+// The list of mixed cells of the current state, rebuilt after the fractions were set.
+int ensure_list(pcvof_handle* h) {
+    if (h->list_valid) return PCVOF_OK;
+    const int ps = prof_begin(h, PCVOF_PROF_CLASSIFY);
+    HIP_TRY(pcv::launch_classify(h->d, h->c(h->cur), h->list(h->lcur), h->count(h->lcur), h->stream));
+    prof_end(h, PCVOF_PROF_CLASSIFY, ps);
+    h->list_valid = true;
+    return PCVOF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -216,16 +292,30 @@ int pcvof_create(const pcvof_grid* grid, const pcvof_params* params, void* d_wor
     h->ws = (char*)d_workspace;
     h->stream = (hipStream_t)hip_stream;
     h->cur = 0;
+    h->lcur = 0;
+    h->list_valid = false;
     h->has_vof = h->has_energy = h->has_vel = h->has_mdot = false;
     h->umax[0] = h->umax[1] = h->umax[2] = 0.0;
     h->step = 0;
     h->in_step = false;
+    h->prof_on = false;
+    for (int k = 0; k < PCVOF_PROF_CLASSES; ++k) {
+        h->prof_ms[k] = 0.0;
+        h->prof_n[k] = 0;
+    }
     *out = h;
     return PCVOF_OK;
 }
 
 int pcvof_destroy(pcvof_handle* h) {
     if (!h) return fail(PCVOF_ERR_ARG, "null handle");
+    if (h->ws && h->prof_on) hipStreamSynchronize(h->stream);
+    for (int k = 0; k < PCVOF_PROF_CLASSES; ++k)
+        for (auto& pr : h->prof_pending[k]) {
+            hipEventDestroy(pr.first);
+            hipEventDestroy(pr.second);
+        }
+    for (hipEvent_t e : h->prof_pool) hipEventDestroy(e);
     h->ws = nullptr;
     delete h;
     return PCVOF_OK;
@@ -240,6 +330,7 @@ int pcvof_set_vof(pcvof_handle* h, const double* c, int mem) {
     if (f & 1u) return fail(PCVOF_ERR_NONFINITE, "volume fraction has NaN or Inf");
     if (f & 2u) return fail(PCVOF_ERR_BOUNDS, "volume fraction outside [0,1]");
     h->has_vof = true;
+    h->list_valid = false;
     return PCVOF_OK;
 }
 
@@ -315,10 +406,11 @@ int pcvof_set_mass_flux(pcvof_handle* h, const double* mdot, int mem) {
 int pcvof_begin_step(pcvof_handle* h) {
     if (int r = check_handle(h)) return r;
     if (!h->has_vof || !h->has_energy) return fail(PCVOF_ERR_STATE, "volume fraction and energy must be set");
-    HIP_TRY(pcv::launch_prologue(h->d, h->c(h->cur), h->e(h->cur), h->cc(), h->ec(), h->stream));
+    // the prologue (c_c, e_c) is fused into the first sweep of the step
     h->in_step = true;
+    h->first_pending = true;
     h->sweeps_done = 0;
-    h->slot_mask = 0;
+    for (int k = 0; k < pcv::kSlots; ++k) h->nb[k] = 0;
     h->last_slot = -1;
     h->step_cfl = 0.0;
     return PCVOF_OK;
@@ -337,13 +429,36 @@ int pcvof_sweep(pcvof_handle* h, int axis, double dt, double u_scale) {
         return fail(PCVOF_ERR_CFL, "axis %d: CFL %.6g above the limit %.6g", axis, cfl, h->p.cfl_max);
     if (cfl > h->step_cfl) h->step_cfl = cfl;
     const int slot = h->sweeps_done;
-    double* part = h->part() + (size_t)slot * h->L.nblocks * pcv::kPartialWidth;
     const int nxt = 1 - h->cur;
-    HIP_TRY(pcv::launch_sweep(h->d, axis, h->c(h->cur), h->e(h->cur), h->cc(), h->ec(), h->vel(axis), kfac,
-                              h->c(nxt), h->e(nxt), part, h->stream));
+    if (int r = ensure_list(h)) return r;
+    pcv::SweepIO io;
+    io.c = h->c(h->cur);
+    io.e = h->e(h->cur);
+    io.cc = h->cc();
+    io.ec = h->ec();
+    io.first = h->first_pending ? 1 : 0;
+    io.vel = h->vel(axis);
+    io.kfac = kfac;
+    io.fgeo = h->fgeo();
+    io.list_in = h->list(h->lcur);
+    io.count_in = h->count(h->lcur);
+    io.list_out = h->list(1 - h->lcur);
+    io.count_out = h->count(1 - h->lcur);
+    io.c_out = h->c(nxt);
+    io.e_out = h->e(nxt);
+    io.part = h->part(slot);
+    io.part_stride = h->L.maxb;
+    io.nblocks = &h->nb[slot];
+    int ps = prof_begin(h, PCVOF_PROF_GEOMETRY);
+    HIP_TRY(pcv::launch_geo(h->d, axis, io, h->stream));
+    prof_end(h, PCVOF_PROF_GEOMETRY, ps);
+    ps = prof_begin(h, PCVOF_PROF_SWEEP_X + axis);
+    HIP_TRY(pcv::launch_sweep(h->d, axis, io, h->stream));
+    prof_end(h, PCVOF_PROF_SWEEP_X + axis, ps);
+    h->first_pending = false;
     h->cur = nxt;
+    h->lcur = 1 - h->lcur;
     h->sweeps_done++;
-    h->slot_mask |= 1 << slot;
     h->last_slot = slot;
     return PCVOF_OK;
 }
@@ -354,12 +469,30 @@ int pcvof_phase_change(pcvof_handle* h, double dt) {
     if (!h->has_mdot) return fail(PCVOF_ERR_STATE, "mass flux not set");
     if (!isfinite(dt) || !(dt >= 0.0)) return fail(PCVOF_ERR_ARG, "bad dt");
     const int slot = 3;
-    double* part = h->part() + (size_t)slot * h->L.nblocks * pcv::kPartialWidth;
+    if (h->nb[slot]) return fail(PCVOF_ERR_STATE, "phase_change called twice in one step");
     const int nxt = 1 - h->cur;
-    HIP_TRY(pcv::launch_phase(h->d, h->c(h->cur), h->e(h->cur), h->mdot(), dt, h->g.h, h->rec(), h->c(nxt),
-                              h->e(nxt), part, h->stream));
+    if (int r = ensure_list(h)) return r;
+    pcv::PhaseIO io;
+    io.c = h->c(h->cur);
+    io.e = h->e(h->cur);
+    io.mdot = h->mdot();
+    io.dt = dt;
+    io.h = h->g.h;
+    io.rec = h->rec();
+    io.list_in = h->list(h->lcur);
+    io.count_in = h->count(h->lcur);
+    io.list_out = h->list(1 - h->lcur);
+    io.count_out = h->count(1 - h->lcur);
+    io.c_out = h->c(nxt);
+    io.e_out = h->e(nxt);
+    io.part = h->part(slot);
+    io.part_stride = h->L.maxb;
+    io.nblocks = &h->nb[slot];
+    const int ps = prof_begin(h, PCVOF_PROF_PHASE);
+    HIP_TRY(pcv::launch_phase(h->d, io, h->stream));
+    prof_end(h, PCVOF_PROF_PHASE, ps);
     h->cur = nxt;
-    h->slot_mask |= 1 << slot;
+    h->lcur = 1 - h->lcur;
     h->last_slot = slot;
     return PCVOF_OK;
 }
@@ -371,21 +504,30 @@ int pcvof_end_step(pcvof_handle* h, pcvof_stats* stats) {
     h->step++;
     if (h->last_slot < 0) return fail(PCVOF_ERR_STATE, "empty step");
     const double hv = h->g.ndim == 3 ? h->g.h * h->g.h * h->g.h : h->g.h * h->g.h;
-    HIP_TRY(pcv::launch_reduce(h->part(), h->L.nblocks, h->slot_mask, h->last_slot, hv, h->stats(), h->stream));
+    // column sums of the stage partials on the device, every step
+    const int ps = prof_begin(h, PCVOF_PROF_CHECKSUM);
+    HIP_TRY(pcv::launch_colsum(h->part(0), h->L.maxb, h->nb, h->colsum(), h->stream));
+    prof_end(h, PCVOF_PROF_CHECKSUM, ps);
     if (stats) {
-        double s[10];
-        HIP_TRY(hipMemcpyAsync(s, h->stats(), sizeof s, hipMemcpyDeviceToHost, h->stream));
+        constexpr int W = pcv::kPartialWidth;
+        double cs[pcv::kSlots * W];
+        HIP_TRY(hipMemcpyAsync(cs, h->colsum(), sizeof cs, hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
-        stats->vol = s[0];
-        stats->energy = s[1];
-        stats->vol_clip = s[2];
-        stats->energy_clip = s[3];
-        stats->vol_phase = s[4];
-        stats->energy_phase = s[5];
-        stats->vol_bnd_out = s[6];
-        stats->energy_bnd_out = s[7];
-        stats->vol_src = s[8];
-        stats->energy_src = s[9];
+        // sweeps: clip_v, clip_e, bnd_v, bnd_e, src_v, src_e, tot_v, tot_e; step 2: dc, de, .., tot
+        double q[6] = {0, 0, 0, 0, 0, 0};
+        for (int sl = 0; sl < 3; ++sl)
+            if (h->nb[sl])
+                for (int k = 0; k < 6; ++k) q[k] += cs[sl * W + k];
+        stats->vol = cs[h->last_slot * W + 6] * hv;
+        stats->energy = cs[h->last_slot * W + 7] * hv;
+        stats->vol_clip = q[0] * hv;
+        stats->energy_clip = q[1] * hv;
+        stats->vol_bnd_out = q[2] * hv;
+        stats->energy_bnd_out = q[3] * hv;
+        stats->vol_src = q[4] * hv;
+        stats->energy_src = q[5] * hv;
+        stats->vol_phase = h->nb[3] ? cs[3 * W + 0] * hv : 0.0;
+        stats->energy_phase = h->nb[3] ? cs[3 * W + 1] * hv : 0.0;
         stats->max_cfl = h->step_cfl;
     }
     return PCVOF_OK;
@@ -416,6 +558,40 @@ int pcvof_advect_step(pcvof_handle* h, double dt, double u_scale, pcvof_stats* s
         }
     }
     return pcvof_end_step(h, stats);
+}
+
+int pcvof_advect_steps(pcvof_handle* h, int nsteps, double dt, const double* u_scale, pcvof_stats* last) {
+    if (int r = check_handle(h)) return r;
+    if (nsteps < 0) return fail(PCVOF_ERR_ARG, "negative nsteps");
+    for (int k = 0; k < nsteps; ++k) {
+        const double s = u_scale ? u_scale[k] : 1.0;
+        if (int r = pcvof_advect_step(h, dt, s, k == nsteps - 1 ? last : nullptr)) return r;
+    }
+    return PCVOF_OK;
+}
+
+int pcvof_set_profiling(pcvof_handle* h, int enable) {
+    if (int r = check_handle(h)) return r;
+    if (enable) {
+        if (int r = prof_collect(h)) return r;
+        for (int k = 0; k < PCVOF_PROF_CLASSES; ++k) {
+            h->prof_ms[k] = 0.0;
+            h->prof_n[k] = 0;
+        }
+    }
+    h->prof_on = enable != 0;
+    return PCVOF_OK;
+}
+
+int pcvof_get_profile(pcvof_handle* h, pcvof_profile* out) {
+    if (int r = check_handle(h)) return r;
+    if (!out) return fail(PCVOF_ERR_ARG, "out is null");
+    if (int r = prof_collect(h)) return r;
+    for (int k = 0; k < PCVOF_PROF_CLASSES; ++k) {
+        out->ms[k] = h->prof_ms[k];
+        out->launches[k] = h->prof_n[k];
+    }
+    return PCVOF_OK;
 }
 
 int pcvof_get_vof(pcvof_handle* h, double* out, int mem) {

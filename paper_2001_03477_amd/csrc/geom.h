@@ -192,7 +192,8 @@ PCV_HD double weno5(double v0, double v1, double v2, double v3, double v4, doubl
 
 // Interface normal from the 3x3x3 fractions around a cell, c27[(dz+1)*9+(dy+1)*3+(dx+1)].
 // Every operation that feeds a decision is evaluated in a fixed order, without
-// contraction, so that identical inputs always give identical normals, and every
+// contraction (the rest of the library contracts multiply-adds into FMAs), so that
+// identical inputs always give identical normals, and every
 // decision uses the tie band kNormalTie (gradients up to it count as zero, candidates
 // within it as equal, lowest axis first), so that round-off differences of the inputs
 // cannot switch formulas; symmetric configurations produce exact ties.
@@ -212,21 +213,24 @@ struct Normal {
 constexpr double kNormalTie = 1e-12;
 
 PCV_HD double c27_at(const double* c27, int a, int oa, int t1, int o1, int t2, int o2) {
-    int off[3] = {0, 0, 0};
-    off[a] = oa;
-    off[t1] = o1;
-    off[t2] = o2;
-    return c27[(off[2] + 1) * 9 + (off[1] + 1) * 3 + (off[0] + 1)];
+    const int ox = a == 0 ? oa : (t1 == 0 ? o1 : o2);
+    const int oy = a == 1 ? oa : (t1 == 1 ? o1 : o2);
+    const int oz = a == 2 ? oa : (t1 == 2 ? o1 : o2);
+    return c27[(oz + 1) * 9 + (oy + 1) * 3 + (ox + 1)];
 }
 
 PCV_HD Normal normal27(const double* c27, int method) {
+#pragma clang fp contract(off)
     double g[3];
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int t1 = (a == 0) ? 1 : 0;
         const int t2 = (a == 2) ? 1 : 2;
         double acc = 0.0;
+#pragma unroll
         for (int o2 = -1; o2 <= 1; ++o2) {
             const double w2 = (o2 == 0) ? 2.0 : 1.0;
+#pragma unroll
             for (int o1 = -1; o1 <= 1; ++o1) {
                 const double w1 = (o1 == 0) ? 2.0 : 1.0;
                 const double d = c27_at(c27, a, 1, t1, o1, t2, o2) - c27_at(c27, a, -1, t1, o1, t2, o2);
@@ -247,11 +251,13 @@ PCV_HD Normal normal27(const double* c27, int method) {
     int best = -1;
     double best_own = 0.0, best_L = 1.0;
     double best_c[3] = {0.0, 0.0, 0.0};
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
         if (fabs(g[d]) <= kNormalTie) continue;
         const int t1 = (d == 0) ? 1 : 0;
         const int t2 = (d == 2) ? 1 : 2;
         double H[2][2];
+#pragma unroll
         for (int s = 0; s < 2; ++s) {
             const int o = s == 0 ? -1 : 1;
             H[0][s] = (c27_at(c27, d, -1, t1, o, t2, 0) + c27_at(c27, d, 0, t1, o, t2, 0)) +

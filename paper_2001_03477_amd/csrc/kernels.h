@@ -28,17 +28,57 @@ struct Launch {
 };
 Launch cell_launch(const Dom& d);
 
-hipError_t launch_prologue(const Dom& d, const double* c, const double* e, uint8_t* cc, double* ec,
-                           hipStream_t s);
-hipError_t launch_sweep(const Dom& d, int axis, const double* c, const double* e, const uint8_t* cc,
-                        const double* ec, const double* vel, double kfac, double* c_out,
-                        double* e_out, double* part, hipStream_t s);
-hipError_t launch_phase(const Dom& d, const double* c, const double* e, const double* mdot, double dt,
-                        double h, double* rec, double* c_out, double* e_out, double* part,
-                        hipStream_t s);
-// stats[0..9] = vol, energy, clip_v, clip_e, phase_v, phase_e, bnd_v, bnd_e, src_v, src_e
-hipError_t launch_reduce(const double* part, int nblocks, int slot_mask, int last_slot, double hv,
-                         double* stats, hipStream_t s);
+// Largest number of blocks of any stage kernel (rows of the partial tables).
+int max_partial_blocks(const Dom& d);
+
+// Mixed cells of c into list (count reset first).
+hipError_t launch_classify(const Dom& d, const double* c, unsigned* list, unsigned* count, hipStream_t s);
+
+struct SweepIO {
+    const double* c;
+    const double* e;
+    uint8_t* cc;
+    double* ec;
+    int first;                 // also freeze c_c and e_c of the step (the prologue)
+    const double* vel;
+    double kfac;               // lambda_f = vel_f * kfac
+    double* fgeo;              // face array for the liquid fluxes of mixed donors
+    const unsigned* list_in;   // mixed cells of c
+    const unsigned* count_in;
+    unsigned* list_out;        // mixed cells of c_out
+    unsigned* count_out;
+    double* c_out;
+    double* e_out;
+    double* part;              // partials: quantity q of block b at part[q * part_stride + b]
+    long part_stride;
+    int* nblocks;              // out: blocks of the sweep kernel
+};
+// A direction sweep is two launches: the geometry of the listed mixed donors (writes
+// io.fgeo and resets *io.count_out), then the sweep kernel.
+hipError_t launch_geo(const Dom& d, int axis, const SweepIO& io, hipStream_t s);
+hipError_t launch_sweep(const Dom& d, int axis, const SweepIO& io, hipStream_t s);
+
+struct PhaseIO {
+    const double* c;
+    const double* e;
+    const double* mdot;
+    double dt, h;
+    double* rec;
+    const unsigned* list_in;
+    const unsigned* count_in;
+    unsigned* list_out;
+    unsigned* count_out;
+    double* c_out;
+    double* e_out;
+    double* part;
+    long part_stride;
+    int* nblocks;
+};
+// Step 2: reconstruction of the listed moving cells, then the shift of every cell.
+hipError_t launch_phase(const Dom& d, const PhaseIO& io, hipStream_t s);
+
+// colsum[slot * 8 + q] = sum over the nb[slot] blocks of quantity q of slot.
+hipError_t launch_colsum(const double* part, long part_stride, const int* nb, double* colsum, hipStream_t s);
 
 hipError_t launch_energy_from_T(const Dom& d, const double* c, const double* T, double* e, hipStream_t s);
 hipError_t launch_T_from_energy(const Dom& d, const double* c, const double* e, double* T, hipStream_t s);

@@ -1,0 +1,604 @@
+// The advection step on gfx950: per-sweep geometry of the mixed donor cells, the
+// direction sweeps (section 3.3.1, with the conservative energy fluxes of section
+// 3.4.1) and step 2 with its latent correction (section 3.3.2, section 3.4.1).
+//
+// A sweep is two launches. The geometry kernel walks the compacted list of mixed
+// cells (written by the kernel that produced the current fractions) and, for each,
+// reconstructs the plane once and writes the liquid volume of every upwind face-flux
+// region the cell donates to into a face array. The sweep kernel then streams over
+// all cells: WENO5 face temperatures, face fluxes (the face array for mixed donors,
+// |lambda| c for pure ones), the cell update, the clip, and the list of mixed cells
+// of its output. All floating point is double precision.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "common.h"
+
+namespace pcv {
+
+namespace {
+
+struct SweepArgs {
+    const double* c;
+    const double* e;
+    uint8_t* cc;       // written by the first sweep of a step, read by the others
+    double* ec;
+    const double* vel;
+    double kfac;
+    const double* fgeo;  // liquid flux of mixed donors, face layout of vel
+    double* c_out;
+    double* e_out;
+    double* part;        // quantity-major partial table of this stage
+    long part_stride;
+    unsigned* list_out;  // mixed cells of the output
+    unsigned* count_out;
+    int first;
+};
+
+__global__ void k_zero_count(unsigned* count) { *count = 0u; }
+
+// Mixed cells of c into the list (after the fractions were set from outside).
+__global__ void __launch_bounds__(256) k_classify(Dom d, const double* __restrict__ c, unsigned* list,
+                                                  unsigned* count) {
+    const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool take = id < d.ncell && mixed(d, c[id]);
+    list_append(take, (unsigned)id, list, count);
+}
+
+// Liquid volume of the upwind region of the ghost cell beyond an outflow boundary
+// face (offset off = -1 or +1 along AX from the boundary cell at (x, y, z)): the ghost
+// copies the boundary cell's fraction cv and is reconstructed from its own (mapped)
+// 3x3x3 block.
+template <int AX>
+__device__ double ghost_fraction(const Dom& d, const double* __restrict__ c, int x, int y, int z, int off,
+                                 double cv, double lam) {
+    if (AX == 0) x += off;
+    else if (AX == 1) y += off;
+    else z += off;
+    double c27[27];
+    gather27(d, c, x, y, z, c27);
+    const Normal nm = normal27(c27, d.normal);
+    const double alpha = alpha_of(nm.m[0], nm.m[1], nm.m[2], cv);
+    return slab(nm.m[0], nm.m[1], nm.m[2], alpha, AX, lam);
+}
+
+// Geometry of the mixed donors of a sweep along AX. For each listed cell: the normal
+// from its 3x3x3 block, the plane constant matching its fraction, and the liquid
+// volume of the upwind region of each face it donates to (left face when lambda < 0,
+// right face when lambda > 0). A periodic axis also fills the identical wrapped face;
+// on an outflow boundary the ghost cell beyond the face (a copy of this cell) donates
+// to the inflow face with its own reconstruction.
+template <int AX>
+__global__ void __launch_bounds__(256)
+k_geo(Dom d, const double* __restrict__ c, const double* __restrict__ vel, double kfac,
+      const unsigned* __restrict__ list, const unsigned* __restrict__ count, double* __restrict__ fgeo,
+      unsigned* count_next) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *count_next = 0u;
+    const unsigned n = *count;
+    const int na = d.n[AX];
+    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const unsigned id = list[i];
+        int x, y, z;
+        cell_coords(d, id, x, y, z);
+        const int p = AX == 0 ? x : (AX == 1 ? y : z);
+        const double cv = c[id];
+        const long fl = face_at(d, AX, x, y, z, p);
+        const long fr = face_at(d, AX, x, y, z, p + 1);
+        const double lamL = vel[fl] * kfac;
+        const double lamR = vel[fr] * kfac;
+        const bool periodic = d.bc[AX] == 0;
+        if (lamL < 0.0 || lamR > 0.0) {
+            double c27[27];
+            gather27(d, c, x, y, z, c27);
+            const Normal nm = normal27(c27, d.normal);
+            const double alpha = alpha_of(nm.m[0], nm.m[1], nm.m[2], cv);
+            if (lamL < 0.0) {
+                const double F = slab(nm.m[0], nm.m[1], nm.m[2], alpha, AX, lamL);
+                fgeo[fl] = F;
+                if (periodic && p == 0) fgeo[face_at(d, AX, x, y, z, na)] = F;
+            }
+            if (lamR > 0.0) {
+                const double F = slab(nm.m[0], nm.m[1], nm.m[2], alpha, AX, lamR);
+                fgeo[fr] = F;
+                if (periodic && p == na - 1) fgeo[face_at(d, AX, x, y, z, 0)] = F;
+            }
+        }
+        if (!periodic) {
+            if (p == 0 && lamL > 0.0) fgeo[fl] = ghost_fraction<AX>(d, c, x, y, z, -1, cv, lamL);
+            if (p == na - 1 && lamR < 0.0) fgeo[fr] = ghost_fraction<AX>(d, c, x, y, z, 1, cv, lamR);
+        }
+    }
+}
+
+// Cell update of a sweep (section 3.3.1 with the split dilatation term, and the
+// conservative energy update of section 3.4.1), the clip into [0,1] keeping T, and the
+// step prologue when first: c_c = [c >= 1/2], e_c = C_p(c_c) T. Returns the new c.
+__device__ __forceinline__ double update_cell(const Dom& d, const SweepArgs& a, long id, double cv, double ev,
+                                              double Tv, double lamL, double lamR, double PhiL, double PhiR,
+                                              double EL, double ER, uint8_t cc_in, double ec_in,
+                                              double (&acc)[8]) {
+    double flag, ecv;
+    if (a.first) {
+        const bool liquid = cv >= 0.5;
+        flag = liquid ? 1.0 : 0.0;
+        ecv = (liquid ? d.cp_l : d.cp_g) * Tv;
+        a.cc[id] = liquid ? 1 : 0;
+        a.ec[id] = ecv;
+    } else {
+        flag = (double)cc_in;
+        ecv = ec_in;
+    }
+    const double dl = lamR - lamL;
+    double cn = cv - (PhiR - PhiL) + flag * dl;
+    double en = ev - (ER - EL) + ecv * dl;
+    acc[4] += flag * dl;
+    acc[5] += ecv * dl;
+    if (cn < 0.0 || cn > 1.0) {
+        const double T = en / cp_of(d, cn);
+        const double cl = cn < 0.0 ? 0.0 : 1.0;
+        const double el = en + (d.cp_l - d.cp_g) * (cl - cn) * T;
+        acc[0] += cl - cn;
+        acc[1] += el - en;
+        cn = cl;
+        en = el;
+    }
+    a.c_out[id] = cn;
+    a.e_out[id] = en;
+    acc[6] += cn;
+    acc[7] += en;
+    return cn;
+}
+
+// Volume and energy fluxes through a face with CFL number lam, given the liquid volume
+// F of the upwind region and the WENO5 face temperature Tf: Phi = sgn(lam) F and
+// E = sgn(lam) [C_pl F + C_pg (|lam| - F)] Tf (section 3.4.1).
+__device__ __forceinline__ void face_energy(const Dom& d, double lam, double F, double Tf, double& Phi,
+                                            double& E) {
+    const double L = fabs(lam);
+    const double sg = lam > 0.0 ? 1.0 : -1.0;
+    Phi = sg * F;
+    E = sg * ((d.cp_l * F + d.cp_g * (L - F)) * Tf);
+}
+
+// x sweep: each wavefront walks XRPW row segments of XC = 63 cells. A segment is
+// staged in the wavefront's own LDS row with a 3-cell halo on both sides (no block
+// barrier: a wavefront's LDS accesses complete in order); lane l computes the flux of
+// face x0 + l (64 faces for 63 cells) and cell l takes its right face from lane l + 1.
+// The next row's loads are issued before the current row is computed, and the
+// checksums are reduced once per wavefront.
+constexpr int XW = 64;
+constexpr int XC = XW - 1;
+constexpr int XWAVES = 4;
+constexpr int XRPW = 8;
+constexpr int XH = 3;
+// staged positions x0-3 .. x0+65 (LDS index 0 .. 68): the face of lane 63 (x0 + 63)
+// reads temperatures up to x0+65 and donors up to x0+63
+constexpr int XS = XW + 5;
+
+__global__ void __launch_bounds__(XW* XWAVES) k_sweep_x(Dom d, SweepArgs a) {
+    __shared__ double s_c[XWAVES][XS];
+    __shared__ double s_T[XWAVES][XS];
+    const int lane = threadIdx.x, wave = threadIdx.y;
+    const int x0 = blockIdx.x * XC;
+    const int z = blockIdx.z;
+    const int y0 = (blockIdx.y * XWAVES + wave) * XRPW;
+    const int x = x0 + lane;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int nrows = min(XRPW, d.n[1] - y0);  // uniform over the wavefront
+    const int xi0 = wrap(x0 - XH + lane, d.n[0], d.bc[0]);
+    const int xi1 = wrap(x0 - XH + lane + XW, d.n[0], d.bc[0]);
+    const bool two = lane + XW < XS;  // lanes 0..4 stage a second position (LDS 64 .. 68)
+    const bool own = lane < XC && x < d.n[0];
+    const bool face = x <= d.n[0];
+    double pc0 = 0, pe0 = 0, pc1 = 0, pe1 = 0, pev = 0, pu = 0, pec = 0;
+    uint8_t pcc = 0;
+    auto prefetch = [&](int y) {
+        const long rb = ((long)z * d.n[1] + y) * d.n[0];
+        const long fr = ((long)z * d.n[1] + y) * (d.n[0] + 1);
+        pc0 = a.c[rb + xi0];
+        pe0 = a.e[rb + xi0];
+        if (two) {
+            pc1 = a.c[rb + xi1];
+            pe1 = a.e[rb + xi1];
+        }
+        if (own) {
+            pev = a.e[rb + x];
+            if (!a.first) {
+                pcc = a.cc[rb + x];
+                pec = a.ec[rb + x];
+            }
+        }
+        if (face) pu = a.vel[fr + x];
+    };
+    if (nrows > 0) prefetch(y0);
+    for (int r = 0; r < nrows; ++r) {
+        const int y = y0 + r;
+        const long rowbase = ((long)z * d.n[1] + y) * d.n[0];
+        const long frow = ((long)z * d.n[1] + y) * (d.n[0] + 1);
+        const double c0 = pc0, e0 = pe0, c1 = pc1, e1 = pe1, ev_own = pev, u = pu, ec_own = pec;
+        const uint8_t cc_own = pcc;
+        if (r + 1 < nrows) prefetch(y + 1);
+        s_c[wave][lane] = c0;
+        s_T[wave][lane] = e0 / cp_of(d, c0);
+        if (two) {
+            s_c[wave][lane + XW] = c1;
+            s_T[wave][lane + XW] = e1 / cp_of(d, c1);
+        }
+        __builtin_amdgcn_wave_barrier();
+        double Phi = 0.0, E = 0.0, lam = 0.0;
+        if (face) {
+            lam = u * a.kfac;
+            if (lam != 0.0) {
+                const int q = lane;
+                const double cd = lam > 0.0 ? s_c[wave][q + XH - 1] : s_c[wave][q + XH];
+                const double Tf = lam > 0.0
+                                      ? weno5(s_T[wave][q], s_T[wave][q + 1], s_T[wave][q + 2],
+                                              s_T[wave][q + 3], s_T[wave][q + 4], d.weno_eps)
+                                      : weno5(s_T[wave][q + 5], s_T[wave][q + 4], s_T[wave][q + 3],
+                                              s_T[wave][q + 2], s_T[wave][q + 1], d.weno_eps);
+                const double F = mixed(d, cd) ? a.fgeo[frow + x] : fabs(lam) * cd;
+                face_energy(d, lam, F, Tf, Phi, E);
+            }
+        }
+        // the right face of cell l is the face of lane l + 1
+        const double PhiR = __shfl_down(Phi, 1, 64);
+        const double ER = __shfl_down(E, 1, 64);
+        const double lamR = __shfl_down(lam, 1, 64);
+        bool take = false;
+        if (own) {
+            const double cn = update_cell(d, a, rowbase + x, s_c[wave][lane + XH], ev_own, s_T[wave][lane + XH],
+                                          lam, lamR, Phi, PhiR, E, ER, cc_own, ec_own, acc);
+            take = mixed(d, cn);
+            if (d.bc[0] == 1) {
+                if (x == 0) {
+                    acc[2] -= Phi;
+                    acc[3] -= E;
+                }
+                if (x == d.n[0] - 1) {
+                    acc[2] += PhiR;
+                    acc[3] += ER;
+                }
+            }
+        }
+        list_append(take, (unsigned)(rowbase + x), a.list_out, a.count_out);
+        __builtin_amdgcn_wave_barrier();
+    }
+    const long blk = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    block_sum8<XWAVES>(acc, a.part + blk, a.part_stride);
+}
+
+// y and z sweeps: each thread owns one column along the sweep axis (x across the
+// wavefront, so every load is coalesced) and marches over a chunk of it, keeping the
+// fractions, energies and temperatures of cells f-3 .. f+2 in registers; each face
+// flux is computed once and used by both neighbours.
+template <int AX>
+__global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) {
+    constexpr int TA = AX == 1 ? 2 : 1;  // the transverse axis other than x
+    const int lane = threadIdx.x, tr = threadIdx.y;
+    const int x = blockIdx.x * 64 + lane;
+    const int t = blockIdx.y * 4 + tr;
+    const int nt = (d.ndim == 2 && TA == 2) ? 1 : d.n[TA];
+    const bool ok = x < d.n[0] && t < nt;
+    const int ns = d.n[AX];
+    const int s0 = blockIdx.z * chunk;
+    const int s1 = min(s0 + chunk, ns);
+    const long plane = (long)d.n[0] * d.n[1];
+    const long base = ok ? (AX == 1 ? (long)t * plane + x : (long)t * d.n[0] + x) : 0;
+    const long stride = AX == 1 ? d.n[0] : plane;
+    const long fbase = ok ? (AX == 1 ? (long)t * (d.n[1] + 1) * d.n[0] + x : (long)t * d.n[0] + x) : 0;
+    const long fstride = AX == 1 ? d.n[0] : plane;
+    // Register ring of cells f-3 .. f+4 in slots (k + j) % 8, where k counts the faces
+    // of the chunk and j = 0..7 the cells from f-3: cells f-3 .. f+2 are the WENO and
+    // update window, cells f+3, f+4 are loads in flight; at each face the load of cell
+    // f+5 is issued into the slot of cell f-3 (three faces ahead, so that many loads
+    // stay in flight per wavefront). Face velocities and the frozen fields of the cell
+    // to update use rings of four. The loop is unrolled eight times so that every slot
+    // is a compile-time register.
+    constexpr int R = 8;
+    double cr[R], er[R], Tw[R];
+    double vr[4], ecr[4];
+    uint8_t ccr[4];
+    auto cell_id = [&](int cell) { return base + (long)wrap(cell, ns, d.bc[AX]) * stride; };
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        cr[j] = 0.0;
+        er[j] = 0.0;
+        Tw[j] = 0.0;
+        if (ok) {
+            const long id = cell_id(s0 - 3 + j);
+            cr[j] = a.c[id];
+            er[j] = a.e[id];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        vr[j] = 0.0;
+        ecr[j] = 0.0;
+        ccr[j] = 0;
+        const int f = s0 + j;
+        if (ok && f <= s1) {
+            vr[j] = a.vel[fbase + (long)f * fstride];
+            // cell f-1 is updated at face f; the first face updates nothing
+            if (!a.first && j > 0) {
+                ccr[j] = a.cc[base + (long)(f - 1) * stride];
+                ecr[j] = a.ec[base + (long)(f - 1) * stride];
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 5; ++j) Tw[j] = ok ? er[j] / cp_of(d, cr[j]) : 0.0;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double PhiP = 0.0, EP = 0.0, lamP = 0.0;
+    auto step = [&](auto kc, int f) {
+        constexpr int K = decltype(kc)::value;
+        constexpr int J0 = K % R, J1 = (K + 1) % R, J2 = (K + 2) % R, J3 = (K + 3) % R, J4 = (K + 4) % R,
+                      J5 = (K + 5) % R;
+        constexpr int V = K % 4;
+        Tw[J5] = ok ? er[J5] / cp_of(d, cr[J5]) : 0.0;
+        const double lam = ok ? vr[V] * a.kfac : 0.0;
+        double Phi = 0.0, E = 0.0;
+        if (lam != 0.0) {
+            const double cd = lam > 0.0 ? cr[J2] : cr[J3];
+            const double F = mixed(d, cd) ? a.fgeo[fbase + (long)f * fstride] : fabs(lam) * cd;
+            const double Tf = lam > 0.0 ? weno5(Tw[J0], Tw[J1], Tw[J2], Tw[J3], Tw[J4], d.weno_eps)
+                                        : weno5(Tw[J5], Tw[J4], Tw[J3], Tw[J2], Tw[J1], d.weno_eps);
+            face_energy(d, lam, F, Tf, Phi, E);
+        }
+        bool take = false;
+        unsigned id_out = 0;
+        if (ok && f > s0) {
+            const int cell = f - 1;
+            const long id = base + (long)cell * stride;
+            const double cn = update_cell(d, a, id, cr[J2], er[J2], Tw[J2], lamP, lam, PhiP, Phi, EP, E,
+                                          ccr[V], ecr[V], acc);
+            take = mixed(d, cn);
+            id_out = (unsigned)id;
+            if (d.bc[AX] == 1) {
+                if (cell == 0) {
+                    acc[2] -= PhiP;
+                    acc[3] -= EP;
+                }
+                if (cell == ns - 1) {
+                    acc[2] += Phi;
+                    acc[3] += E;
+                }
+            }
+        }
+        list_append(take, id_out, a.list_out, a.count_out);
+        PhiP = Phi;
+        EP = E;
+        lamP = lam;
+        // loads three faces ahead into the slots just released
+        if (ok) {
+            if (f + 5 - 2 <= s1) {  // cell f+5 enters the window at face f+3
+                const long id = cell_id(f + 5);
+                cr[J0] = a.c[id];
+                er[J0] = a.e[id];
+            }
+            if (f + 4 <= s1) {
+                vr[V] = a.vel[fbase + (long)(f + 4) * fstride];
+                if (!a.first) {
+                    ccr[V] = a.cc[base + (long)(f + 3) * stride];
+                    ecr[V] = a.ec[base + (long)(f + 3) * stride];
+                }
+            }
+        }
+    };
+    using std::integral_constant;
+    for (int f = s0; f <= s1; f += R) {
+        step(integral_constant<int, 0>{}, f);
+        if (f + 1 > s1) break;
+        step(integral_constant<int, 1>{}, f + 1);
+        if (f + 2 > s1) break;
+        step(integral_constant<int, 2>{}, f + 2);
+        if (f + 3 > s1) break;
+        step(integral_constant<int, 3>{}, f + 3);
+        if (f + 4 > s1) break;
+        step(integral_constant<int, 4>{}, f + 4);
+        if (f + 5 > s1) break;
+        step(integral_constant<int, 5>{}, f + 5);
+        if (f + 6 > s1) break;
+        step(integral_constant<int, 6>{}, f + 6);
+        if (f + 7 > s1) break;
+        step(integral_constant<int, 7>{}, f + 7);
+    }
+    const long blk = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    block_sum8<4>(acc, a.part + blk, a.part_stride);
+}
+
+// Step 2, first pass (section 3.3.2), over the listed mixed cells of c~ with a non-zero
+// mass flux: the reconstruction and the moved plane constant, rec = (m, alpha~, alpha*)
+// with alpha* = alpha~ + |m|_2 Delta d and Delta d = -(m''/rho_l) dt / h.
+__global__ void __launch_bounds__(256)
+k_phase_recon(Dom d, const double* __restrict__ c, const double* __restrict__ mdot, double dt_h,
+              const unsigned* __restrict__ list, const unsigned* __restrict__ count, double* __restrict__ rec,
+              unsigned* count_next) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *count_next = 0u;
+    const unsigned n = *count;
+    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const unsigned id = list[i];
+        const double md = mdot[id];
+        if (md == 0.0) continue;
+        int x, y, z;
+        cell_coords(d, id, x, y, z);
+        double c27[27];
+        gather27(d, c, x, y, z, c27);
+        const Normal nm = normal27(c27, d.normal);
+        const double alpha = alpha_of(nm.m[0], nm.m[1], nm.m[2], c[id]);
+        const double dd = -(md / d.rho_l) * dt_h;
+        const double norm2 = sqrt(nm.m[0] * nm.m[0] + nm.m[1] * nm.m[1] + nm.m[2] * nm.m[2]);
+        double* r = rec + 5 * (long)id;
+        r[0] = nm.m[0];
+        r[1] = nm.m[1];
+        r[2] = nm.m[2];
+        r[3] = alpha;
+        r[4] = alpha + norm2 * dd;
+    }
+}
+
+// Step 2, second pass: a moving cell takes V(m, alpha*) (the motion capped at the cell
+// bounds); a pure cell that a neighbour's plane advances into (liquid for evaporation,
+// gas for condensation) takes the volume the extended plane sweeps in it, averaged over
+// those neighbours; then the latent correction Delta e = Delta c (C_pl - C_pg) T_Gamma
+// (section 3.4.1).
+__global__ void __launch_bounds__(256)
+k_phase_apply(Dom d, const double* __restrict__ c, const double* __restrict__ e,
+              const double* __restrict__ mdot, double dt_h, const double* __restrict__ rec,
+              double* __restrict__ c_out, double* __restrict__ e_out, double* __restrict__ part, long part_stride,
+              unsigned* list_out, unsigned* count_out) {
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    const int z = blockIdx.z;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    bool take = false;
+    long id = 0;
+    if (x < d.n[0] && y < d.n[1]) {
+        id = ((long)z * d.n[1] + y) * d.n[0] + x;
+        const double cj = c[id];
+        double cnew = cj;
+        if (mixed(d, cj)) {
+            if (mdot[id] != 0.0) {
+                const double* r = rec + 5 * id;
+                cnew = volume(r[0], r[1], r[2], r[4]);
+            }
+        } else {
+            const double want = cj >= 1.0 - d.eps ? -1.0 : 1.0;
+            double sum = 0.0;
+            int cnt = 0;
+            const int pos[3] = {x, y, z};
+            for (int k = 0; k < d.ndim; ++k)
+                for (int s = -1; s <= 1; s += 2) {
+                    int q[3] = {pos[0], pos[1], pos[2]};
+                    q[k] += s;
+                    if (d.bc[k] == 1 && (q[k] < 0 || q[k] >= d.n[k])) continue;
+                    const long nid = ((long)wrap(q[2], d.ndim == 2 ? 1 : d.n[2], d.bc[2]) * d.n[1] +
+                                      wrap(q[1], d.n[1], d.bc[1])) * d.n[0] + wrap(q[0], d.n[0], d.bc[0]);
+                    const double mdn = mdot[nid];
+                    if (mdn == 0.0 || !mixed(d, c[nid])) continue;
+                    const double dd = -(mdn / d.rho_l) * dt_h;
+                    const double motion = dd > 0.0 ? 1.0 : -1.0;
+                    if (motion != want) continue;
+                    const double* r = rec + 5 * nid;
+                    const double mo = -s * r[k];
+                    sum += volume(r[0], r[1], r[2], r[3] - mo) - volume(r[0], r[1], r[2], r[4] - mo);
+                    ++cnt;
+                }
+            if (cnt) cnew = cj - sum / cnt;
+        }
+        const double dc = cnew - cj;
+        const double de = (dc * (d.cp_l - d.cp_g)) * d.T_gamma;
+        const double enew = e[id] + de;
+        c_out[id] = cnew;
+        e_out[id] = enew;
+        acc[0] = dc;
+        acc[1] = de;
+        acc[6] = cnew;
+        acc[7] = enew;
+        take = mixed(d, cnew);
+    }
+    list_append(take, (unsigned)id, list_out, count_out);
+    const long blk = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    block_sum8<4>(acc, part + blk, part_stride);
+}
+
+// Blocks of the list kernels (grid-stride over a device-side count): enough to keep
+// every CU busy with long lists, few enough to launch quickly with short ones.
+int list_grid(const Dom& d) {
+    const long nb = (d.ncell + 255) / 256;
+    return (int)(nb < 1024 ? (nb < 1 ? 1 : nb) : 1024);
+}
+
+}  // namespace
+
+Launch cell_launch(const Dom& d) {
+    Launch L;
+    L.block = dim3(64, 4, 1);
+    L.grid = dim3((d.n[0] + 63) / 64, (d.n[1] + 3) / 4, d.ndim == 2 ? 1 : d.n[2]);
+    L.nblocks = (int)(L.grid.x * L.grid.y * L.grid.z);
+    return L;
+}
+
+// Launch shape of a sweep. x: XRPW row segments of 63 cells per wavefront, four
+// wavefronts per block. y, z: 64 x 4 columns per block marching over a chunk of the sweep axis; the
+// chunk is the longest of 64, 32, 16, 8 cells that still gives >= 2048 blocks.
+Launch sweep_launch(const Dom& d, int axis, int* chunk) {
+    Launch L;
+    L.block = dim3(64, 4, 1);
+    const int nz = d.ndim == 2 ? 1 : d.n[2];
+    if (axis == 0) {
+        L.grid = dim3((d.n[0] + XC - 1) / XC, (d.n[1] + XWAVES * XRPW - 1) / (XWAVES * XRPW), nz);
+        *chunk = 0;
+    } else {
+        const int nt = axis == 1 ? nz : d.n[1];
+        const long bxy = (long)((d.n[0] + 63) / 64) * ((nt + 3) / 4);
+        const int ns = d.n[axis];
+        int ch = 64;
+        while (ch > 8 && bxy * ((ns + ch - 1) / ch) < 2048) ch >>= 1;
+        *chunk = ch;
+        L.grid = dim3((d.n[0] + 63) / 64, (nt + 3) / 4, (ns + ch - 1) / ch);
+    }
+    L.nblocks = (int)(L.grid.x * L.grid.y * L.grid.z);
+    return L;
+}
+
+int max_partial_blocks(const Dom& d) {
+    int ch, m = cell_launch(d).nblocks;
+    for (int a = 0; a < d.ndim; ++a) {
+        const int nb = sweep_launch(d, a, &ch).nblocks;
+        if (nb > m) m = nb;
+    }
+    return m;
+}
+
+hipError_t launch_classify(const Dom& d, const double* c, unsigned* list, unsigned* count, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, count);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_classify, dim3((unsigned)((d.ncell + 255) / 256)), dim3(256), 0, s, d, c, list, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_geo(const Dom& d, int axis, const SweepIO& io, hipStream_t s) {
+    const int gg = list_grid(d);
+    if (axis == 0)
+        hipLaunchKernelGGL(k_geo<0>, dim3(gg), dim3(256), 0, s, d, io.c, io.vel, io.kfac, io.list_in, io.count_in,
+                           io.fgeo, io.count_out);
+    else if (axis == 1)
+        hipLaunchKernelGGL(k_geo<1>, dim3(gg), dim3(256), 0, s, d, io.c, io.vel, io.kfac, io.list_in, io.count_in,
+                           io.fgeo, io.count_out);
+    else
+        hipLaunchKernelGGL(k_geo<2>, dim3(gg), dim3(256), 0, s, d, io.c, io.vel, io.kfac, io.list_in, io.count_in,
+                           io.fgeo, io.count_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep(const Dom& d, int axis, const SweepIO& io, hipStream_t s) {
+    int chunk = 0;
+    const Launch L = sweep_launch(d, axis, &chunk);
+    SweepArgs a{io.c,      io.e,     io.cc,          io.ec,       io.vel,       io.kfac, io.fgeo,
+                io.c_out,  io.e_out, io.part,        io.part_stride, io.list_out, io.count_out, io.first};
+    if (axis == 0)
+        hipLaunchKernelGGL(k_sweep_x, L.grid, L.block, 0, s, d, a);
+    else if (axis == 1)
+        hipLaunchKernelGGL(k_sweep_t<1>, L.grid, L.block, 0, s, d, a, chunk);
+    else
+        hipLaunchKernelGGL(k_sweep_t<2>, L.grid, L.block, 0, s, d, a, chunk);
+    *io.nblocks = L.nblocks;
+    return hipGetLastError();
+}
+
+hipError_t launch_phase(const Dom& d, const PhaseIO& io, hipStream_t s) {
+    const double dt_h = io.dt / io.h;
+    hipLaunchKernelGGL(k_phase_recon, dim3(list_grid(d)), dim3(256), 0, s, d, io.c, io.mdot, dt_h, io.list_in,
+                       io.count_in, io.rec, io.count_out);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    const Launch L = cell_launch(d);
+    hipLaunchKernelGGL(k_phase_apply, L.grid, L.block, 0, s, d, io.c, io.e, io.mdot, dt_h, io.rec, io.c_out,
+                       io.e_out, io.part, io.part_stride, io.list_out, io.count_out);
+    *io.nblocks = L.nblocks;
+    return hipGetLastError();
+}
+
+}  // namespace pcv

@@ -28,8 +28,11 @@ EXPORTS = (
     "pcvof_begin_step", "pcvof_sweep", "pcvof_phase_change", "pcvof_end_step", "pcvof_get_vof",
     "pcvof_get_energy", "pcvof_get_temperature", "pcvof_get_step", "pcvof_set_step",
     "pcvof_last_error", "pcvof_geom_volume", "pcvof_geom_alpha", "pcvof_geom_slab",
-    "pcvof_geom_normal", "pcvof_geom_weno5",
+    "pcvof_geom_normal", "pcvof_geom_weno5", "pcvof_advect_steps", "pcvof_set_profiling",
+    "pcvof_get_profile",
 )
+
+PROF_NAMES = ("geometry", "sweep_x", "sweep_y", "sweep_z", "phase", "checksum", "classify")
 
 
 class PcvofError(RuntimeError):
@@ -58,6 +61,13 @@ class Stats(C.Structure):
 
     def as_dict(self):
         return {n: getattr(self, n) for n in STAT_NAMES}
+
+
+class Profile(C.Structure):
+    _fields_ = [("ms", C.c_double * len(PROF_NAMES)), ("launches", C.c_long * len(PROF_NAMES))]
+
+    def as_dict(self):
+        return {n: {"ms": self.ms[i], "launches": self.launches[i]} for i, n in enumerate(PROF_NAMES)}
 
 
 _lib = None
@@ -97,6 +107,9 @@ def lib():
         L.pcvof_geom_slab.argtypes = [C.c_int, _vp, _vp, _vp, _vp, _vp, _vp]
         L.pcvof_geom_normal.argtypes = [C.c_int, _vp, C.c_int, _vp, _vp]
         L.pcvof_geom_weno5.argtypes = [C.c_int, _vp, C.c_double, _vp, _vp]
+        L.pcvof_advect_steps.argtypes = [_vp, C.c_int, C.c_double, _vp, C.POINTER(Stats)]
+        L.pcvof_set_profiling.argtypes = [_vp, C.c_int]
+        L.pcvof_get_profile.argtypes = [_vp, C.POINTER(Profile)]
         for nm in EXPORTS:
             f = getattr(L, nm)
             if nm not in ("pcvof_workspace_bytes", "pcvof_last_error"):
@@ -228,6 +241,26 @@ class Domain:
         check(lib().pcvof_advect_step(self._h, float(dt), float(u_scale),
                                       C.byref(st) if st is not None else None))
         return st.as_dict() if st is not None else None
+
+    def steps(self, n: int, dt: float, u_scale=None, stats: bool = False):
+        """n steps from one host call; u_scale is None or a sequence of n scales."""
+        st = Stats() if stats else None
+        arr = None
+        if u_scale is not None:
+            arr = np.ascontiguousarray(np.asarray(u_scale, dtype=np.float64))
+            assert arr.shape == (n,)
+        check(lib().pcvof_advect_steps(self._h, int(n), float(dt),
+                                       arr.ctypes.data if arr is not None else None,
+                                       C.byref(st) if st is not None else None))
+        return st.as_dict() if st is not None else None
+
+    def set_profiling(self, on: bool):
+        check(lib().pcvof_set_profiling(self._h, 1 if on else 0))
+
+    def profile(self):
+        p = Profile()
+        check(lib().pcvof_get_profile(self._h, C.byref(p)))
+        return p.as_dict()
 
     def begin_step(self):
         check(lib().pcvof_begin_step(self._h))
