@@ -133,10 +133,14 @@ int pcvof_end_step(pcvof_handle* h, pcvof_stats* stats);
 int pcvof_advect_steps(pcvof_handle* h, int nsteps, double dt, const double* u_scale,
                        pcvof_stats* last);
 
-/* Kernel timing. While enabled, every launch of the library is bracketed by HIP events
-   recorded on the library's stream; pcvof_get_profile waits for the stream and returns
-   the accumulated device time per kernel class since profiling was (re)enabled.
-   Enabling resets the accumulators; disabling keeps them readable. */
+/* Kernel timing. pcvof_set_profiling takes a mask of kernel classes (bit k = class k,
+   PCVOF_PROF_ALL = every class, 0 = off). While a class is selected, each of its
+   launches is bracketed by two HIP events recorded on the library's stream (each
+   event adds a few microseconds of device time to the stream, so select only the
+   classes to be measured). pcvof_get_profile waits for the stream and returns the
+   accumulated device time per class since profiling was last enabled. A non-zero
+   mask resets the accumulators; 0 keeps them readable. Bits outside
+   PCVOF_PROF_ALL give PCVOF_ERR_ARG. */
 enum {
     PCVOF_PROF_GEOMETRY = 0,  /* reconstruction of the mixed donors of a sweep */
     PCVOF_PROF_SWEEP_X = 1,   /* sweep kernels, per axis */
@@ -145,13 +149,14 @@ enum {
     PCVOF_PROF_PHASE = 4,     /* step 2 (both of its kernels) */
     PCVOF_PROF_CHECKSUM = 5,  /* column sums of the checksums */
     PCVOF_PROF_CLASSIFY = 6,  /* mixed-cell list after the fractions were set */
-    PCVOF_PROF_CLASSES = 7
+    PCVOF_PROF_CLASSES = 7,
+    PCVOF_PROF_ALL = (1 << 7) - 1
 };
 typedef struct {
     double ms[PCVOF_PROF_CLASSES];     /* total device time, milliseconds */
     long launches[PCVOF_PROF_CLASSES];
 } pcvof_profile;
-int pcvof_set_profiling(pcvof_handle* h, int enable);
+int pcvof_set_profiling(pcvof_handle* h, int classes);
 int pcvof_get_profile(pcvof_handle* h, pcvof_profile* out);
 
 /* Field output (same layout as the input). */

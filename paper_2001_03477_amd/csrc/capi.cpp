@@ -155,7 +155,7 @@ struct pcvof_handle {
     int last_slot;
     double step_cfl;
     // kernel timing
-    bool prof_on;
+    int prof_mask;           // kernel classes timed (bit k = class k)
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending[PCVOF_PROF_CLASSES];
     std::vector<hipEvent_t> prof_pool;
     double prof_ms[PCVOF_PROF_CLASSES];
@@ -192,7 +192,7 @@ hipEvent_t prof_event(pcvof_handle* h) {
 
 // Records the start event of a launch of class cls; returns the pending slot or -1.
 int prof_begin(pcvof_handle* h, int cls) {
-    if (!h->prof_on) return -1;
+    if (!(h->prof_mask >> cls & 1)) return -1;
     hipEvent_t a = prof_event(h), b = prof_event(h);
     if (!a || !b) return -1;
     hipEventRecord(a, h->stream);
@@ -298,7 +298,7 @@ int pcvof_create(const pcvof_grid* grid, const pcvof_params* params, void* d_wor
     h->umax[0] = h->umax[1] = h->umax[2] = 0.0;
     h->step = 0;
     h->in_step = false;
-    h->prof_on = false;
+    h->prof_mask = 0;
     for (int k = 0; k < PCVOF_PROF_CLASSES; ++k) {
         h->prof_ms[k] = 0.0;
         h->prof_n[k] = 0;
@@ -309,7 +309,7 @@ int pcvof_create(const pcvof_grid* grid, const pcvof_params* params, void* d_wor
 
 int pcvof_destroy(pcvof_handle* h) {
     if (!h) return fail(PCVOF_ERR_ARG, "null handle");
-    if (h->ws && h->prof_on) hipStreamSynchronize(h->stream);
+    if (h->ws && h->prof_mask) hipStreamSynchronize(h->stream);
     for (int k = 0; k < PCVOF_PROF_CLASSES; ++k)
         for (auto& pr : h->prof_pending[k]) {
             hipEventDestroy(pr.first);
@@ -570,16 +570,17 @@ int pcvof_advect_steps(pcvof_handle* h, int nsteps, double dt, const double* u_s
     return PCVOF_OK;
 }
 
-int pcvof_set_profiling(pcvof_handle* h, int enable) {
+int pcvof_set_profiling(pcvof_handle* h, int classes) {
     if (int r = check_handle(h)) return r;
-    if (enable) {
+    if (classes & ~PCVOF_PROF_ALL) return fail(PCVOF_ERR_ARG, "bad profiling class mask 0x%x", classes);
+    if (classes) {
         if (int r = prof_collect(h)) return r;
         for (int k = 0; k < PCVOF_PROF_CLASSES; ++k) {
             h->prof_ms[k] = 0.0;
             h->prof_n[k] = 0;
         }
     }
-    h->prof_on = enable != 0;
+    h->prof_mask = classes;
     return PCVOF_OK;
 }
 

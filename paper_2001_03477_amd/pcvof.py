@@ -254,8 +254,18 @@ class Domain:
                                        C.byref(st) if st is not None else None))
         return st.as_dict() if st is not None else None
 
-    def set_profiling(self, on: bool):
-        check(lib().pcvof_set_profiling(self._h, 1 if on else 0))
+    def set_profiling(self, on=True):
+        """Times the kernels of the selected classes with HIP events: True = every class,
+        False = off, or an iterable of class names from PROF_NAMES."""
+        if on is True:
+            mask = (1 << len(PROF_NAMES)) - 1
+        elif on is False or on is None:
+            mask = 0
+        else:
+            mask = 0
+            for name in on:
+                mask |= 1 << PROF_NAMES.index(name)
+        check(lib().pcvof_set_profiling(self._h, mask))
 
     def profile(self):
         p = Profile()

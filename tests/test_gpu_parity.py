@@ -305,3 +305,25 @@ def test_temperature_round_trip(pc):
     cp = wl.cp_l * wl.c + wl.cp_g * (1 - wl.c)
     assert np.array_equal(d.energy().cpu().numpy(), cp * T)
     assert np.max(np.abs(d.temperature().cpu().numpy() - T)) <= 4e-16 * 3.0
+
+
+def test_profiling_times_the_selected_classes(pc):
+    wl = W.random_drops_3d(n=16, ndrops=3, seed=49, rmin=1.5, rmax=3.0)
+    spec, _ = _specs(pc, wl)
+    d = _domain(pc, spec, wl)
+    d.set_profiling(["sweep_x", "checksum"])
+    d.steps(3, wl.dt)
+    p = d.profile()
+    assert p["sweep_x"]["launches"] == 3 and p["checksum"]["launches"] == 3
+    assert all(p[k]["launches"] == 0 for k in ("geometry", "sweep_y", "sweep_z", "phase"))
+    assert p["sweep_x"]["ms"] > 0.0
+    d.set_profiling(True)
+    d.steps(2, wl.dt)
+    p = d.profile()
+    assert p["geometry"]["launches"] == 6 and p["sweep_y"]["launches"] == 2
+    d.set_profiling(False)
+    d.step(wl.dt)
+    assert d.profile()["sweep_z"]["launches"] == 2  # kept, not accumulated
+    with pytest.raises(pc.PcvofError) as ex:
+        pc.check(pc.lib().pcvof_set_profiling(d._h, 1 << 7))
+    assert ex.value.code == -1
