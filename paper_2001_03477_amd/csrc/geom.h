@@ -82,16 +82,28 @@ PCV_HD double volume(double mx, double my, double mz, double alpha) {
     return 1.0 - vol_lower(s, S - a);
 }
 
+// Cube root of x > 0: a single-precision estimate refined by one Halley step in double
+// precision (cubic convergence takes the ~1e-7 relative error of the estimate below
+// rounding). Arguments outside the single-precision normal range use the library cbrt.
+PCV_HD double cbrt_pos(double x) {
+    if (!(x > 1e-36 && x < 1e36)) return cbrt(x);
+    const double r = (double)cbrtf((float)x);
+    const double r3 = r * r * r;
+    return r * (r3 + 2.0 * x) / (2.0 * r3 + x);
+}
+
 // Inverse of vol_lower for 0 < v <= 1/2: closed forms in the tetrahedron,
-// truncated-tetrahedron and four-edge regimes; safeguarded Newton iterations on the
-// cubic regimes, started from the chord between the regime's end points.
+// truncated-tetrahedron and four-edge regimes; Halley iterations (cubic convergence)
+// on the cubic regimes, started from the chord between the regime's end points and
+// kept inside the regime's bracket. A step below 1e-8 of the bracket leaves an error
+// far below rounding, so at most three iterations run (six are allowed).
 PCV_HD double alpha_lower(const Sorted3& s, double v) {
     const double m1 = s.m1, m2 = s.m2, m3 = s.m3;
     const double m12 = m1 + m2;
     const double d6 = 6.0 * m2 * m3;
     if (m1 > 0.0) {
         const double v1 = m1 * m1 / d6;
-        if (v < v1) return cbrt(6.0 * m1 * m2 * m3 * v);
+        if (v < v1) return cbrt_pos(6.0 * m1 * m2 * m3 * v);
     }
     if (m2 > 0.0) {
         const double v2 = (3.0 * m2 * m2 - 3.0 * m2 * m1 + m1 * m1) / d6;
@@ -123,22 +135,26 @@ PCV_HD double alpha_lower(const Sorted3& s, double v) {
     const double inv_d2 = 1.0 / (2.0 * m2 * m3);
     const double vlo = vol_lower(s, lo), vhi = vol_lower(s, hi);
     double a = (vhi > vlo) ? lo + (hi - lo) * ((v - vlo) / (vhi - vlo)) : lo;
-    for (int it = 0; it < 8; ++it) {
+    const double tol = 1e-8 * (hi - lo);
+    for (int it = 0; it < 6; ++it) {
+        // f = V(a) - v and its first two derivatives (V is cubic in the regime)
         const double t2 = a - m2;
         const double q = 3.0 * a * a - 3.0 * a * m1 + m1 * m1;
-        double cub = t2 * t2 * t2, sq = t2 * t2;
+        double cub = t2 * t2 * t2, sq = t2 * t2, lin = t2;
         if (three) {
             const double t3 = a - m3;
             cub += t3 * t3 * t3;
             sq += t3 * t3;
+            lin += t3;
         }
         const double f = (q - cub * inv_m1) * (inv_d2 / 3.0) - v;
         const double fp = ((2.0 * a - m1) - sq * inv_m1) * inv_d2;
-        double an = a - f / fp;
+        const double fpp = (2.0 - 2.0 * lin * inv_m1) * inv_d2;
+        double an = a - 2.0 * f * fp / (2.0 * fp * fp - f * fpp);
         an = fmin(fmax(an, lo), hi);
         const double step = an - a;
         a = an;
-        if (fabs(step) <= 1e-17 * (1.0 + a)) break;
+        if (fabs(step) <= tol) break;
     }
     return a;
 }
