@@ -19,11 +19,15 @@ import numpy as np
 # --------------------------------------------------------------------------- shapes
 
 
-def sphere_fraction(shape, h, centres, radii, inside_liquid=True, sub=8, nd=3):
+def sphere_fraction(shape, h, centres, radii, inside_liquid=True, sub=8, nd=3, disjoint=False):
     """Volume fraction of the union of spheres (discs when nd == 2) sampled with
     sub^nd points per cell, only in cells whose centre lies within the half cell
     diagonal of a sphere surface; other cells are 0 or 1. With inside_liquid=False
-    the spheres are gas (bubbles) in a liquid."""
+    the spheres are gas (bubbles) in a liquid. disjoint=True promises that the
+    spheres' surfaces are more than a cell diagonal apart, so that every sampled cell
+    is sampled against its own sphere only (much faster for many spheres)."""
+    if disjoint:
+        return _disjoint_sphere_fraction(shape, h, centres, radii, inside_liquid, sub, nd)
     nz, ny, nx = shape
     centres = np.atleast_2d(np.asarray(centres, dtype=float))
     radii = np.atleast_1d(np.asarray(radii, dtype=float))
@@ -80,6 +84,53 @@ def sphere_fraction(shape, h, centres, radii, inside_liquid=True, sub=8, nd=3):
                               dzz ** 2) <= r * r
             frac[blk[:, 0], blk[:, 1], blk[:, 2]] = hit.mean(axis=1)
     frac[inside] = 1.0
+    return frac if inside_liquid else 1.0 - frac
+
+
+def _disjoint_sphere_fraction(shape, h, centres, radii, inside_liquid, sub, nd):
+    import torch  # multithreaded sampling on the host
+    nz, ny, nx = shape
+    frac = np.zeros(shape)
+    half_diag = 0.5 * h * math.sqrt(nd) * 1.0000001
+    cells, owner = [], []
+    for j, (cen, r) in enumerate(zip(np.atleast_2d(centres), np.atleast_1d(radii))):
+        lo = np.floor((cen - r) / h - 1).astype(int)
+        hi = np.ceil((cen + r) / h + 1).astype(int)
+        xs = np.arange(max(lo[0], 0), min(hi[0], nx))
+        ys = np.arange(max(lo[1], 0), min(hi[1], ny))
+        zs = np.arange(max(lo[2], 0), min(hi[2], nz)) if nd == 3 else np.array([0])
+        if len(xs) == 0 or len(ys) == 0 or len(zs) == 0:
+            continue
+        Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+        dz = ((Z + 0.5) * h - cen[2]) if nd == 3 else 0.0
+        d = np.sqrt(((X + 0.5) * h - cen[0]) ** 2 + ((Y + 0.5) * h - cen[1]) ** 2 + dz ** 2) - r
+        ins = d <= -half_diag
+        frac[Z[ins], Y[ins], X[ins]] = 1.0
+        near = np.abs(d) < half_diag
+        cells.append(np.stack([Z[near], Y[near], X[near]], axis=1))
+        owner.append(np.full(int(near.sum()), j))
+    if cells:
+        cells = np.concatenate(cells)
+        owner = np.concatenate(owner)
+        cen = np.atleast_2d(centres)[owner]
+        rad = np.atleast_1d(radii)[owner]
+        s = torch.from_numpy((np.arange(sub) + 0.5) / sub * h)
+        for b in range(0, len(cells), 65536):
+            blk = torch.from_numpy(cells[b:b + 65536])
+            cb = torch.from_numpy(cen[b:b + 65536])
+            rb = torch.from_numpy(rad[b:b + 65536])
+            # offsets of the sample points from the sphere centre, per axis
+            dx = (blk[:, 2:3] * h + s[None, :]) - cb[:, 0:1]
+            dy = (blk[:, 1:2] * h + s[None, :]) - cb[:, 1:2]
+            if nd == 3:
+                dz = (blk[:, 0:1] * h + s[None, :]) - cb[:, 2:3]
+                d2 = (dz * dz)[:, :, None, None] + (dy * dy)[:, None, :, None] + (dx * dx)[:, None, None, :]
+            else:
+                d2 = (dy * dy)[:, :, None] + (dx * dx)[:, None, :]
+            hit = (d2 <= (rb * rb).reshape([-1] + [1] * (d2.dim() - 1))).to(torch.float64)
+            f = hit.reshape(hit.shape[0], -1).mean(dim=1).numpy()
+            cc = cells[b:b + 65536]
+            frac[cc[:, 0], cc[:, 1], cc[:, 2]] = f
     return frac if inside_liquid else 1.0 - frac
 
 
@@ -208,6 +259,77 @@ def fourier_potential(rng, nmodes=8, kmax=4, nd=3) -> EdgePotential:
     return EdgePotential(line(0, 0), line(1, 1), line(2, 2))
 
 
+def fourier_modes(rng, nmodes=8, kmax=4, nd=3):
+    """Integer wave vectors k_j in [-kmax, kmax]^3 \\ {0}, amplitudes a_j ~ N(0, I) and
+    phases phi_j ~ U[0, 2 pi) of A = sum_j a_j sin(2 pi k_j.x + phi_j) (drawn in the
+    same order as fourier_potential)."""
+    ks, amps, phis = [], [], []
+    while len(ks) < nmodes:
+        k = rng.integers(-kmax, kmax + 1, size=3)
+        if nd == 2:
+            k[2] = 0
+        if not np.any(k):
+            continue
+        ks.append(k.astype(float))
+        a = rng.normal(size=3)
+        if nd == 2:
+            a[:2] = 0.0
+        amps.append(a)
+        phis.append(rng.uniform(0, 2 * math.pi))
+    return ks, amps, phis
+
+
+def fourier_mac_velocity(ks, amps, phis, shape, h):
+    """3D periodic MAC velocities of curl A for A = sum_j a_j sin(2 pi k_j.x + phi_j),
+    like mac_velocity(fourier_potential(...)) but with the edge integrals evaluated
+    separably: the integral of sin(2 pi k.x + phi) along an edge of length h in
+    direction d is h sinc(k_d h) sin(2 pi k.x_mid + phi) with x_mid the edge midpoint,
+    and sin(a + b + c) over the grid is built from 1D factors, so a 512^3 field takes
+    seconds. Node coordinates wrap (the last node is at 0), so the two boundary faces
+    of every axis are bitwise equal."""
+    nz, ny, nx = shape
+    tp = 2.0 * math.pi
+
+    def coords(n, mid):
+        idx = np.arange(n if mid else n + 1)
+        if mid:
+            return (idx + 0.5) * h
+        return (idx % n) * h
+
+    import torch  # multithreaded elementwise products on the host
+
+    def edge_integral(comp, axis):
+        # the grid of edges along `axis`: midpoints along it, nodes across
+        zc = coords(nz, axis == 2)
+        yc = coords(ny, axis == 1)
+        xc = coords(nx, axis == 0)
+        out = torch.zeros((len(zc), len(yc), len(xc)), dtype=torch.float64)
+        for k, a, ph in zip(ks, amps, phis):
+            if a[comp] == 0.0:
+                continue
+            kd = k[axis]
+            fac = h if kd == 0.0 else math.sin(math.pi * kd * h) / (math.pi * kd)
+            ax = tp * k[0] * xc
+            bc = (tp * k[1] * yc)[None, :] + (tp * k[2] * zc + ph)[:, None]
+            sbc = torch.from_numpy((a[comp] * fac) * np.sin(bc))[:, :, None]
+            cbc = torch.from_numpy((a[comp] * fac) * np.cos(bc))[:, :, None]
+            ca = torch.from_numpy(np.cos(ax))[None, None, :]
+            sa = torch.from_numpy(np.sin(ax))[None, None, :]
+            out.addcmul_(sbc, ca)
+            out.addcmul_(cbc, sa)
+        return out
+
+    Ex = edge_integral(0, 0)  # [nz+1][ny+1][nx]
+    Ey = edge_integral(1, 1)  # [nz+1][ny][nx+1]
+    Ez = edge_integral(2, 2)  # [nz][ny+1][nx+1]
+    h2 = h * h
+    u = ((Ey[:-1, :, :] + Ez[:, 1:, :]) - (Ey[1:, :, :] + Ez[:, :-1, :])) / h2
+    v = ((Ez[:, :, :-1] + Ex[1:, :, :]) - (Ez[:, :, 1:] + Ex[:-1, :, :])) / h2
+    w = ((Ex[:, :-1, :] + Ey[:, :, 1:]) - (Ex[:, 1:, :] + Ey[:, :, :-1])) / h2
+    return (np.ascontiguousarray(u.numpy()), np.ascontiguousarray(v.numpy()),
+            np.ascontiguousarray(w.numpy()))
+
+
 def max_abs_face(u, v, w=None) -> float:
     m = max(float(np.max(np.abs(u))), float(np.max(np.abs(v))))
     if w is not None:
@@ -328,3 +450,140 @@ def random_drops_3d(n=32, ndrops=6, seed=3, cfl=0.3, rmin=2.0, rmax=5.0, cp=(403
     md = None if mdot is None else np.full(shape, float(mdot))
     return Workload(f"drops{nd}d_{n}", shape, h, nd, (0, 0, 0), cp_l, cp_g, 1.0, 1.0, c, e, u, v,
                     w, md, dt, 10)
+
+
+def periodic_drops(rng, n, ndrops, rmin, rmax, gap, max_tries=1000000):
+    """Rejection-placed spheres in the periodic unit cube: radii uniform in
+    [rmin, rmax] cells, surfaces at least `gap` cells apart in the minimum-image
+    distance. Returns (centres [k, 3], radii [k]) in domain units."""
+    h = 1.0 / n
+    cen = np.zeros((ndrops, 3))
+    rad = np.zeros(ndrops)
+    k = 0
+    tries = 0
+    r = rng.uniform(rmin, rmax) * h  # each radius is drawn once, positions are retried
+    while k < ndrops and tries < max_tries:
+        tries += 1
+        p = rng.uniform(0.0, 1.0, size=3)
+        if k:
+            d = p[None, :] - cen[:k]
+            d -= np.round(d)
+            dist = np.sqrt(np.sum(d * d, axis=1))
+            if np.any(dist < r + rad[:k] + gap * h):
+                continue
+        cen[k] = p
+        rad[k] = r
+        k += 1
+        r = rng.uniform(rmin, rmax) * h
+    return cen[:k], rad[:k]
+
+
+def periodic_images(centres, radii):
+    """The spheres plus their periodic images that reach into the unit cube."""
+    out_c, out_r = [], []
+    for p, r in zip(centres, radii):
+        shifts = [[0.0] if (p[a] - r > 0.0 and p[a] + r < 1.0) else [-1.0, 0.0, 1.0] for a in range(3)]
+        for sx in shifts[0]:
+            for sy in shifts[1]:
+                for sz in shifts[2]:
+                    q = p + np.array([sx, sy, sz])
+                    if np.all(q + r > 0.0) and np.all(q - r < 1.0):
+                        out_c.append(q)
+                        out_r.append(r)
+    return np.array(out_c), np.array(out_r)
+
+
+def droplets_3d(n=512, ndrops=2000, seed=4, cfl=0.3, rmin=4.0, rmax=16.0, gap=2.0, nmodes=8,
+                kmax=4, cp=(4.039e6, 1.248e3)) -> Workload:
+    """3D n^3 periodic box with `ndrops` seeded droplets (radii uniform in [rmin, rmax]
+    cells, surfaces at least `gap` cells apart in the periodic distance), a random
+    divergence-free Fourier velocity (nmodes modes with integer wave vectors in
+    [-kmax, kmax]^3) scaled so that the largest face velocity is 1, dt = 0.3 h, random
+    per-phase temperatures, water-like volumetric heat capacities, m'' = 0."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    shape = (n, n, n)
+    centres, radii = periodic_drops(rng, n, ndrops, rmin, rmax, gap)
+    ic, ir = periodic_images(centres, radii)
+    c = sphere_fraction(shape, h, ic, ir, sub=8, nd=3, disjoint=True)
+    cp_l, cp_g = cp
+    T_l = rng.uniform(0.0, 1.0, size=shape)
+    T_g = rng.uniform(0.0, 1.0, size=shape)
+    e = energy_from_phase_temperatures(c, T_l, T_g, cp_l, cp_g)
+    del T_l, T_g
+    ks, amps, phis = fourier_modes(rng, nmodes, kmax, 3)
+    u, v, w = fourier_mac_velocity(ks, amps, phis, shape, h)
+    s = 1.0 / max_abs_face(u, v, w)
+    u *= s
+    v *= s
+    w *= s
+    dt = cfl * h
+    return Workload(f"droplets3d_{n}", shape, h, 3, (0, 0, 0), cp_l, cp_g, 1.0, 1.0, c, e, u, v, w,
+                    None, dt, 10)
+
+
+def rect_solid_angle(x0, y1, y2, z1, z2):
+    """Signed solid angle of the rectangle {x = x0, y in [y1, y2], z in [z1, z2]} seen
+    from the origin, positive when x0 > 0 (the flux of the unit point source
+    r / (4 pi |r|^3) through it in +x, times 4 pi)."""
+    def F(y, z):
+        return np.arctan(y * z / (x0 * np.sqrt(x0 * x0 + y * y + z * z)))
+    return F(y2, z2) - F(y1, z2) - F(y2, z1) + F(y1, z1)
+
+
+def bubble_3d(n=256, R=0.1, u0=0.05, smooth=0.8, cfl=0.3, rho_l=2.5, cp_l=6.25, cp_g=0.25,
+              k_l=0.07, h_fg=100.0, T_sat=1.0, T_inf=3.0, delta_T=0.05) -> Workload:
+    """3D n^3 expanding vapour bubble: a vapour sphere of radius R at the box centre in
+    liquid, outflow on all axes. Outside the ball r < smooth R the velocity is the
+    point source u = u0 R^2 / r^2 r^, whose face fluxes are exact (u0 R^2 times the
+    face's solid angle), so every cell outside the ball is discretely divergence-free;
+    inside the ball (pure vapour) u = u0 R^2 r / R_s^3 at the face centres, a source
+    the step reports. T = T_sat inside the bubble and a linear ramp to T_inf over
+    delta_T outside; m'' = k_l (T_inf - T_sat) / (delta_T h_fg) in every cell (applied
+    in mixed cells); properties of the paper's bubble case. CFL 0.3 on the largest
+    face velocity."""
+    h = 1.0 / n
+    shape = (n, n, n)
+    ctr = 0.5
+    c = sphere_fraction(shape, h, [[ctr, ctr, ctr]], [R], inside_liquid=False, sub=8, nd=3)
+    # temperature at the cell centres
+    xc = (np.arange(n) + 0.5) * h - ctr
+    r = np.sqrt(xc[:, None, None] ** 2 + xc[None, :, None] ** 2 + xc[None, None, :] ** 2)
+    T = np.clip(T_sat + (T_inf - T_sat) * (r - R) / delta_T, T_sat, T_inf)
+    del r
+    e = energy_from_phase_temperatures(c, T, T, cp_l, cp_g)
+    # face velocities
+    Rs = smooth * R
+    q = u0 * R * R
+    xf = np.arange(n + 1) * h - ctr     # face positions
+    xlo = np.arange(n) * h - ctr        # cell lower corners
+    xhi = xlo + h
+    xm = xlo + 0.5 * h                  # cell centres
+
+    def axis_faces(axis):
+        # face grid [nz][ny][nx] with the sweep axis extended by one
+        a = xf[:, None, None]           # face coordinate along axis
+        b1, b2, bm = xlo[None, :, None], xhi[None, :, None], xm[None, :, None]
+        c1, c2, cm = xlo[None, None, :], xhi[None, None, :], xm[None, None, :]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            om = rect_solid_angle(a, b1, b2, c1, c2)
+        flux = q * om / (h * h)
+        rf = np.sqrt(a * a + bm * bm + cm * cm)
+        lin = q * a / Rs ** 3
+        vel = np.where(rf >= Rs, flux, lin)
+        vel = np.where(a == 0.0, 0.0, vel)
+        # vel is indexed [axis][t1][t2]; move the axis to its MAC position
+        if axis == 0:      # [x][y][z] -> [z][y][x]
+            return np.ascontiguousarray(np.transpose(vel, (2, 1, 0)))
+        if axis == 1:      # [y][x][z] -> [z][y][x]
+            return np.ascontiguousarray(np.transpose(vel, (2, 0, 1)))
+        return np.ascontiguousarray(vel)  # [z][y][x]
+
+    u = axis_faces(0)
+    v = axis_faces(1)
+    w = axis_faces(2)
+    umax = max_abs_face(u, v, w)
+    dt = cfl * h / umax
+    mdot = np.full(shape, k_l * (T_inf - T_sat) / (delta_T * h_fg))
+    return Workload(f"bubble3d_{n}", shape, h, 3, (1, 1, 1), cp_l, cp_g, rho_l, T_sat, c, e, u, v, w,
+                    mdot, dt, 10)
