@@ -142,15 +142,13 @@ int pcvof_advect_steps(pcvof_handle* h, int nsteps, double dt, const double* u_s
    mask resets the accumulators; 0 keeps them readable. Bits outside
    PCVOF_PROF_ALL give PCVOF_ERR_ARG. */
 enum {
-    PCVOF_PROF_GEOMETRY = 0,  /* reconstruction of the mixed donors of a sweep */
-    PCVOF_PROF_SWEEP_X = 1,   /* sweep kernels, per axis */
-    PCVOF_PROF_SWEEP_Y = 2,
-    PCVOF_PROF_SWEEP_Z = 3,
-    PCVOF_PROF_PHASE = 4,     /* step 2 (both of its kernels) */
-    PCVOF_PROF_CHECKSUM = 5,  /* column sums of the checksums */
-    PCVOF_PROF_CLASSIFY = 6,  /* mixed-cell list after the fractions were set */
-    PCVOF_PROF_CLASSES = 7,
-    PCVOF_PROF_ALL = (1 << 7) - 1
+    PCVOF_PROF_SWEEP_X = 0,   /* sweep kernels, per axis (each includes the geometry of */
+    PCVOF_PROF_SWEEP_Y = 1,   /* the mixed donors of its tiles) */
+    PCVOF_PROF_SWEEP_Z = 2,
+    PCVOF_PROF_PHASE = 3,     /* step 2 (both of its kernels) */
+    PCVOF_PROF_CHECKSUM = 4,  /* column sums of the checksums */
+    PCVOF_PROF_CLASSES = 5,
+    PCVOF_PROF_ALL = (1 << 5) - 1
 };
 typedef struct {
     double ms[PCVOF_PROF_CLASSES];     /* total device time, milliseconds */

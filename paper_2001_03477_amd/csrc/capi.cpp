@@ -51,7 +51,7 @@ long face_count(const pcvof_grid& g, int a) {
 
 // Workspace layout (offsets in bytes, each 256-byte aligned).
 struct Layout {
-    size_t c[2], e[2], ec, cc, vel[3], fgeo, mdot, rec, list[2], counts, part, colsum, flags, total;
+    size_t c[2], e[2], ec, cc, vel[3], mdot, rec, part, colsum, flags, total;
     int maxb;  // rows of each partial table
 };
 
@@ -113,18 +113,12 @@ Layout make_layout(const pcvof_grid& g, const pcvof_params& p) {
     }
     L.ec = take(n * dbl);
     L.cc = take(n);
-    size_t maxf = 1;
     for (int a = 0; a < 3; ++a) {
         const size_t nf = a < g.ndim ? (size_t)face_count(g, a) : 1;
         L.vel[a] = take(nf * dbl);
-        if (nf > maxf) maxf = nf;
     }
-    L.fgeo = take(maxf * dbl);
     L.mdot = take(n * dbl);
     L.rec = take(5 * n * dbl);
-    L.list[0] = take(n * sizeof(unsigned));
-    L.list[1] = take(n * sizeof(unsigned));
-    L.counts = take(2 * sizeof(unsigned));
     L.maxb = pcv::max_partial_blocks(d);
     L.part = take((size_t)pcv::kSlots * pcv::kPartialWidth * L.maxb * dbl);
     L.colsum = take((size_t)pcv::kSlots * pcv::kPartialWidth * dbl);
@@ -143,8 +137,6 @@ struct pcvof_handle {
     char* ws;
     hipStream_t stream;
     int cur;                 // index of the current state buffer
-    int lcur;                // index of the list holding the mixed cells of the current state
-    bool list_valid;
     bool has_vof, has_energy, has_vel, has_mdot;
     double umax[3];          // max |u_f| per axis, from set_velocity
     long step;
@@ -168,9 +160,6 @@ struct pcvof_handle {
     double* vel(int a) { return (double*)(ws + L.vel[a]); }
     double* mdot() { return (double*)(ws + L.mdot); }
     double* rec() { return (double*)(ws + L.rec); }
-    double* fgeo() { return (double*)(ws + L.fgeo); }
-    unsigned* list(int b) { return (unsigned*)(ws + L.list[b]); }
-    unsigned* count(int b) { return (unsigned*)(ws + L.counts) + b; }
     double* part(int slot) { return (double*)(ws + L.part) + (size_t)slot * pcv::kPartialWidth * L.maxb; }
     double* colsum() { return (double*)(ws + L.colsum); }
     unsigned int* flags() { return (unsigned int*)(ws + L.flags); }
@@ -253,16 +242,6 @@ int check_field(pcvof_handle* h, const double* x, long n, int range, unsigned in
     return PCVOF_OK;
 }
 
-// The list of mixed cells of the current state, rebuilt after the fractions were set.
-int ensure_list(pcvof_handle* h) {
-    if (h->list_valid) return PCVOF_OK;
-    const int ps = prof_begin(h, PCVOF_PROF_CLASSIFY);
-    HIP_TRY(pcv::launch_classify(h->d, h->c(h->cur), h->list(h->lcur), h->count(h->lcur), h->stream));
-    prof_end(h, PCVOF_PROF_CLASSIFY, ps);
-    h->list_valid = true;
-    return PCVOF_OK;
-}
-
 }  // namespace
 
 extern "C" {
@@ -292,8 +271,6 @@ int pcvof_create(const pcvof_grid* grid, const pcvof_params* params, void* d_wor
     h->ws = (char*)d_workspace;
     h->stream = (hipStream_t)hip_stream;
     h->cur = 0;
-    h->lcur = 0;
-    h->list_valid = false;
     h->has_vof = h->has_energy = h->has_vel = h->has_mdot = false;
     h->umax[0] = h->umax[1] = h->umax[2] = 0.0;
     h->step = 0;
@@ -330,7 +307,6 @@ int pcvof_set_vof(pcvof_handle* h, const double* c, int mem) {
     if (f & 1u) return fail(PCVOF_ERR_NONFINITE, "volume fraction has NaN or Inf");
     if (f & 2u) return fail(PCVOF_ERR_BOUNDS, "volume fraction outside [0,1]");
     h->has_vof = true;
-    h->list_valid = false;
     return PCVOF_OK;
 }
 
@@ -430,7 +406,6 @@ int pcvof_sweep(pcvof_handle* h, int axis, double dt, double u_scale) {
     if (cfl > h->step_cfl) h->step_cfl = cfl;
     const int slot = h->sweeps_done;
     const int nxt = 1 - h->cur;
-    if (int r = ensure_list(h)) return r;
     pcv::SweepIO io;
     io.c = h->c(h->cur);
     io.e = h->e(h->cur);
@@ -439,25 +414,16 @@ int pcvof_sweep(pcvof_handle* h, int axis, double dt, double u_scale) {
     io.first = h->first_pending ? 1 : 0;
     io.vel = h->vel(axis);
     io.kfac = kfac;
-    io.fgeo = h->fgeo();
-    io.list_in = h->list(h->lcur);
-    io.count_in = h->count(h->lcur);
-    io.list_out = h->list(1 - h->lcur);
-    io.count_out = h->count(1 - h->lcur);
     io.c_out = h->c(nxt);
     io.e_out = h->e(nxt);
     io.part = h->part(slot);
     io.part_stride = h->L.maxb;
     io.nblocks = &h->nb[slot];
-    int ps = prof_begin(h, PCVOF_PROF_GEOMETRY);
-    HIP_TRY(pcv::launch_geo(h->d, axis, io, h->stream));
-    prof_end(h, PCVOF_PROF_GEOMETRY, ps);
-    ps = prof_begin(h, PCVOF_PROF_SWEEP_X + axis);
+    const int ps = prof_begin(h, PCVOF_PROF_SWEEP_X + axis);
     HIP_TRY(pcv::launch_sweep(h->d, axis, io, h->stream));
     prof_end(h, PCVOF_PROF_SWEEP_X + axis, ps);
     h->first_pending = false;
     h->cur = nxt;
-    h->lcur = 1 - h->lcur;
     h->sweeps_done++;
     h->last_slot = slot;
     return PCVOF_OK;
@@ -471,7 +437,6 @@ int pcvof_phase_change(pcvof_handle* h, double dt) {
     const int slot = 3;
     if (h->nb[slot]) return fail(PCVOF_ERR_STATE, "phase_change called twice in one step");
     const int nxt = 1 - h->cur;
-    if (int r = ensure_list(h)) return r;
     pcv::PhaseIO io;
     io.c = h->c(h->cur);
     io.e = h->e(h->cur);
@@ -479,10 +444,6 @@ int pcvof_phase_change(pcvof_handle* h, double dt) {
     io.dt = dt;
     io.h = h->g.h;
     io.rec = h->rec();
-    io.list_in = h->list(h->lcur);
-    io.count_in = h->count(h->lcur);
-    io.list_out = h->list(1 - h->lcur);
-    io.count_out = h->count(1 - h->lcur);
     io.c_out = h->c(nxt);
     io.e_out = h->e(nxt);
     io.part = h->part(slot);
@@ -492,7 +453,6 @@ int pcvof_phase_change(pcvof_handle* h, double dt) {
     HIP_TRY(pcv::launch_phase(h->d, io, h->stream));
     prof_end(h, PCVOF_PROF_PHASE, ps);
     h->cur = nxt;
-    h->lcur = 1 - h->lcur;
     h->last_slot = slot;
     return PCVOF_OK;
 }

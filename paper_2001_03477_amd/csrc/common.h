@@ -1,6 +1,5 @@
 // Device helpers shared by the kernels: ghost-cell index mapping, the one-fluid heat
-// capacity, the mixed-cell test, the 3x3x3 gather, deterministic block sums and the
-// wave-aggregated append to the list of mixed cells.
+// capacity, the mixed-cell test, the 3x3x3 gather and deterministic block sums.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -89,28 +88,6 @@ __device__ __forceinline__ void block_sum8(const double (&v)[8], double* out, lo
         for (int w = 1; w < NWAVES; ++w) s += red[tid][w];
         out[tid * stride] = s;
     }
-}
-
-// Appends id to the list when take is true, one atomic per wavefront. The order of the
-// entries is arbitrary; every consumer treats them independently.
-__device__ __forceinline__ void list_append(bool take, unsigned id, unsigned* list, unsigned* count) {
-    const unsigned long long ballot = __ballot(take);
-    if (!ballot) return;
-    const int lane = __lane_id();
-    const int leader = __ffsll((long long)ballot) - 1;
-    unsigned base = 0;
-    if (lane == leader) base = atomicAdd(count, (unsigned)__popcll(ballot));
-    base = __shfl(base, leader, 64);
-    if (take) list[base + __popcll(ballot & __lanemask_lt())] = id;
-}
-
-// Linear cell index -> coordinates.
-__device__ __forceinline__ void cell_coords(const Dom& d, unsigned id, int& x, int& y, int& z) {
-    const unsigned plane = (unsigned)d.n[0] * (unsigned)d.n[1];
-    z = (int)(id / plane);
-    const unsigned r = id - (unsigned)z * plane;
-    y = (int)(r / (unsigned)d.n[0]);
-    x = (int)(r - (unsigned)y * (unsigned)d.n[0]);
 }
 
 // Index of face f along axis of the face row through transverse cell coordinates.

@@ -31,9 +31,6 @@ Launch cell_launch(const Dom& d);
 // Largest number of blocks of any stage kernel (rows of the partial tables).
 int max_partial_blocks(const Dom& d);
 
-// Mixed cells of c into list (count reset first).
-hipError_t launch_classify(const Dom& d, const double* c, unsigned* list, unsigned* count, hipStream_t s);
-
 struct SweepIO {
     const double* c;
     const double* e;
@@ -42,20 +39,13 @@ struct SweepIO {
     int first;                 // also freeze c_c and e_c of the step (the prologue)
     const double* vel;
     double kfac;               // lambda_f = vel_f * kfac
-    double* fgeo;              // face array for the liquid fluxes of mixed donors
-    const unsigned* list_in;   // mixed cells of c
-    const unsigned* count_in;
-    unsigned* list_out;        // mixed cells of c_out
-    unsigned* count_out;
     double* c_out;
     double* e_out;
     double* part;              // partials: quantity q of block b at part[q * part_stride + b]
     long part_stride;
     int* nblocks;              // out: blocks of the sweep kernel
 };
-// A direction sweep is two launches: the geometry of the listed mixed donors (writes
-// io.fgeo and resets *io.count_out), then the sweep kernel.
-hipError_t launch_geo(const Dom& d, int axis, const SweepIO& io, hipStream_t s);
+// A direction sweep is one launch (geometry of the mixed donors inside each tile).
 hipError_t launch_sweep(const Dom& d, int axis, const SweepIO& io, hipStream_t s);
 
 struct PhaseIO {
@@ -64,17 +54,13 @@ struct PhaseIO {
     const double* mdot;
     double dt, h;
     double* rec;
-    const unsigned* list_in;
-    const unsigned* count_in;
-    unsigned* list_out;
-    unsigned* count_out;
     double* c_out;
     double* e_out;
     double* part;
     long part_stride;
     int* nblocks;
 };
-// Step 2: reconstruction of the listed moving cells, then the shift of every cell.
+// Step 2: reconstruction of the moving cells, then the shift of every cell.
 hipError_t launch_phase(const Dom& d, const PhaseIO& io, hipStream_t s);
 
 // colsum[slot * 8 + q] = sum over the nb[slot] blocks of quantity q of slot.

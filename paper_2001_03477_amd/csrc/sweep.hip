@@ -1,14 +1,15 @@
-// The advection step on gfx950: per-sweep geometry of the mixed donor cells, the
-// direction sweeps (section 3.3.1, with the conservative energy fluxes of section
-// 3.4.1) and step 2 with its latent correction (section 3.3.2, section 3.4.1).
+// The advection step on gfx950: the direction sweeps (section 3.3.1, with the
+// conservative energy fluxes of section 3.4.1) and step 2 with its latent correction
+// (section 3.3.2, section 3.4.1).
 //
-// A sweep is two launches. The geometry kernel walks the compacted list of mixed
-// cells (written by the kernel that produced the current fractions) and, for each,
-// reconstructs the plane once and writes the liquid volume of every upwind face-flux
-// region the cell donates to into a face array. The sweep kernel then streams over
-// all cells: WENO5 face temperatures, face fluxes (the face array for mixed donors,
-// |lambda| c for pure ones), the cell update, the clip, and the list of mixed cells
-// of its output. All floating point is double precision.
+// A sweep is one launch over tiles of faces. Each block first finds the faces of its
+// tile whose upwind donor is a mixed cell, then reconstructs those donors with all of
+// its threads (normal, plane constant, liquid volume of the upwind face-flux region)
+// into a table in LDS, and then streams over its cells: WENO5 face temperatures, face
+// fluxes (the table for mixed donors, |lambda| c for pure ones), the cell update, the
+// clip and the checksum partials. The geometry of one block overlaps with the
+// streaming of the other blocks resident on the same CU. All floating point is double
+// precision.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -26,89 +27,39 @@ struct SweepArgs {
     double* ec;
     const double* vel;
     double kfac;
-    const double* fgeo;  // liquid flux of mixed donors, face layout of vel
     double* c_out;
     double* e_out;
     double* part;        // quantity-major partial table of this stage
     long part_stride;
-    unsigned* list_out;  // mixed cells of the output
-    unsigned* count_out;
     int first;
 };
 
-__global__ void k_zero_count(unsigned* count) { *count = 0u; }
-
-// Mixed cells of c into the list (after the fractions were set from outside).
-__global__ void __launch_bounds__(256) k_classify(Dom d, const double* __restrict__ c, unsigned* list,
-                                                  unsigned* count) {
-    const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool take = id < d.ncell && mixed(d, c[id]);
-    list_append(take, (unsigned)id, list, count);
-}
-
-// Liquid volume of the upwind region of the ghost cell beyond an outflow boundary
-// face (offset off = -1 or +1 along AX from the boundary cell at (x, y, z)): the ghost
-// copies the boundary cell's fraction cv and is reconstructed from its own (mapped)
-// 3x3x3 block.
+// Liquid volume, in cell units, of the upwind region of the donor cell at (x, y, z)
+// (ghost positions allowed: they map like every other read) crossing a face of a
+// sweep along AX with CFL number lam; cd is the donor's fraction (mixed). The plane is
+// reconstructed from the donor's own 3x3x3 block, so a periodic face computed from
+// either side, or a ghost donor beyond an outflow boundary, gives the same value.
 template <int AX>
-__device__ double ghost_fraction(const Dom& d, const double* __restrict__ c, int x, int y, int z, int off,
-                                 double cv, double lam) {
-    if (AX == 0) x += off;
-    else if (AX == 1) y += off;
-    else z += off;
+__device__ double donor_fraction(const Dom& d, const double* __restrict__ c, int x, int y, int z, double cd,
+                                 double lam) {
     double c27[27];
     gather27(d, c, x, y, z, c27);
     const Normal nm = normal27(c27, d.normal);
-    const double alpha = alpha_of(nm.m[0], nm.m[1], nm.m[2], cv);
+    const double alpha = alpha_of(nm.m[0], nm.m[1], nm.m[2], cd);
     return slab(nm.m[0], nm.m[1], nm.m[2], alpha, AX, lam);
 }
 
-// Geometry of the mixed donors of a sweep along AX. For each listed cell: the normal
-// from its 3x3x3 block, the plane constant matching its fraction, and the liquid
-// volume of the upwind region of each face it donates to (left face when lambda < 0,
-// right face when lambda > 0). A periodic axis also fills the identical wrapped face;
-// on an outflow boundary the ghost cell beyond the face (a copy of this cell) donates
-// to the inflow face with its own reconstruction.
-template <int AX>
-__global__ void __launch_bounds__(256)
-k_geo(Dom d, const double* __restrict__ c, const double* __restrict__ vel, double kfac,
-      const unsigned* __restrict__ list, const unsigned* __restrict__ count, double* __restrict__ fgeo,
-      unsigned* count_next) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *count_next = 0u;
-    const unsigned n = *count;
-    const int na = d.n[AX];
-    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const unsigned id = list[i];
-        int x, y, z;
-        cell_coords(d, id, x, y, z);
-        const int p = AX == 0 ? x : (AX == 1 ? y : z);
-        const double cv = c[id];
-        const long fl = face_at(d, AX, x, y, z, p);
-        const long fr = face_at(d, AX, x, y, z, p + 1);
-        const double lamL = vel[fl] * kfac;
-        const double lamR = vel[fr] * kfac;
-        const bool periodic = d.bc[AX] == 0;
-        if (lamL < 0.0 || lamR > 0.0) {
-            double c27[27];
-            gather27(d, c, x, y, z, c27);
-            const Normal nm = normal27(c27, d.normal);
-            const double alpha = alpha_of(nm.m[0], nm.m[1], nm.m[2], cv);
-            if (lamL < 0.0) {
-                const double F = slab(nm.m[0], nm.m[1], nm.m[2], alpha, AX, lamL);
-                fgeo[fl] = F;
-                if (periodic && p == 0) fgeo[face_at(d, AX, x, y, z, na)] = F;
-            }
-            if (lamR > 0.0) {
-                const double F = slab(nm.m[0], nm.m[1], nm.m[2], alpha, AX, lamR);
-                fgeo[fr] = F;
-                if (periodic && p == na - 1) fgeo[face_at(d, AX, x, y, z, 0)] = F;
-            }
-        }
-        if (!periodic) {
-            if (p == 0 && lamL > 0.0) fgeo[fl] = ghost_fraction<AX>(d, c, x, y, z, -1, cv, lamL);
-            if (p == na - 1 && lamR < 0.0) fgeo[fr] = ghost_fraction<AX>(d, c, x, y, z, 1, cv, lamR);
-        }
-    }
+// Appends item to a block's work list in LDS when take is true (one LDS atomic per
+// wavefront).
+__device__ __forceinline__ void work_append(bool take, unsigned short item, unsigned short* work, unsigned* n) {
+    const unsigned long long ballot = __ballot(take);
+    if (!ballot) return;
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)ballot) - 1;
+    unsigned base = 0;
+    if (lane == leader) base = atomicAdd(n, (unsigned)__popcll(ballot));
+    base = __shfl(base, leader, 64);
+    if (take) work[base + __popcll(ballot & __lanemask_lt())] = item;
 }
 
 // Cell update of a sweep (section 3.3.1 with the split dilatation term, and the
@@ -176,21 +127,76 @@ constexpr int XH = 3;
 // reads temperatures up to x0+65 and donors up to x0+63
 constexpr int XS = XW + 5;
 
+// Longest column chunk of the y and z sweeps (sizes their LDS flux table).
+constexpr int TCH = 16;
+
 __global__ void __launch_bounds__(XW* XWAVES) k_sweep_x(Dom d, SweepArgs a) {
     __shared__ double s_c[XWAVES][XS];
     __shared__ double s_T[XWAVES][XS];
+    __shared__ double s_F[XWAVES][XRPW][XW];                 // liquid flux of mixed donors
+    __shared__ unsigned short s_work[XWAVES * XRPW * XW];   // faces with a mixed donor
+    __shared__ unsigned s_nwork;
     const int lane = threadIdx.x, wave = threadIdx.y;
+    const int tid = wave * XW + lane;
     const int x0 = blockIdx.x * XC;
     const int z = blockIdx.z;
     const int y0 = (blockIdx.y * XWAVES + wave) * XRPW;
     const int x = x0 + lane;
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const int nrows = min(XRPW, d.n[1] - y0);  // uniform over the wavefront
+    const int nrows = max(0, min(XRPW, d.n[1] - y0));  // uniform over the wavefront
     const int xi0 = wrap(x0 - XH + lane, d.n[0], d.bc[0]);
     const int xi1 = wrap(x0 - XH + lane + XW, d.n[0], d.bc[0]);
     const bool two = lane + XW < XS;  // lanes 0..4 stage a second position (LDS 64 .. 68)
     const bool own = lane < XC && x < d.n[0];
     const bool face = x <= d.n[0];
+    auto row_at = [&](int y) { return ((long)z * d.n[1] + y) * d.n[0]; };
+    auto face_row_at = [&](int y) { return ((long)z * d.n[1] + y) * (d.n[0] + 1); };
+
+    // Geometry, first pass: the faces x0 .. x0+63 of the wavefront's rows whose upwind
+    // donor is mixed (lane = face offset, item = wave:row:lane).
+    // All loads are issued first (both candidate donors of each face: cell x-1 in this
+    // lane, cell x from the next lane), so that they overlap.
+    if (tid == 0) s_nwork = 0u;
+    {
+        const int xl = wrap(x - 1, d.n[0], d.bc[0]);
+        const int xr = wrap(x0 + XW - 1, d.n[0], d.bc[0]);  // lane 63's right cell
+        double g_lam[XRPW], g_cl[XRPW], g_cr[XRPW];
+#pragma unroll
+        for (int r = 0; r < XRPW; ++r) {
+            g_lam[r] = 0.0;
+            g_cl[r] = 0.0;
+            g_cr[r] = 0.0;
+            if (r < nrows) {
+                const int y = y0 + r;
+                if (face) g_lam[r] = a.vel[face_row_at(y) + x];
+                g_cl[r] = a.c[row_at(y) + xl];
+                if (lane == XW - 1) g_cr[r] = a.c[row_at(y) + xr];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < XRPW; ++r) {
+            const double right = __shfl_down(g_cl[r], 1, 64);  // cell x of lane l is cell x-1 of lane l+1
+            const double cr = lane == XW - 1 ? g_cr[r] : right;
+            const double lam = g_lam[r] * a.kfac;
+            const bool need = r < nrows && face && lam != 0.0 && mixed(d, lam > 0.0 ? g_cl[r] : cr);
+            work_append(need, (unsigned short)((wave << 9) | (r << 6) | lane), s_work, &s_nwork);
+        }
+    }
+    __syncthreads();
+    // Second pass: every thread of the block takes listed faces.
+    const unsigned nwork = s_nwork;
+    for (unsigned i = tid; i < nwork; i += XW * XWAVES) {
+        const unsigned it = s_work[i];
+        const int w = it >> 9, r = (it >> 6) & (XRPW - 1), l = it & (XW - 1);
+        const int y = (blockIdx.y * XWAVES + w) * XRPW + r;
+        const int xf = x0 + l;
+        const double lam = a.vel[face_row_at(y) + xf] * a.kfac;
+        const int xd = lam > 0.0 ? xf - 1 : xf;
+        const double cd = a.c[row_at(y) + wrap(xd, d.n[0], d.bc[0])];
+        s_F[w][r][l] = donor_fraction<0>(d, a.c, xd, y, z, cd, lam);
+    }
+    __syncthreads();
     double pc0 = 0, pe0 = 0, pc1 = 0, pe1 = 0, pev = 0, pu = 0, pec = 0;
     uint8_t pcc = 0;
     auto prefetch = [&](int y) {
@@ -214,8 +220,7 @@ __global__ void __launch_bounds__(XW* XWAVES) k_sweep_x(Dom d, SweepArgs a) {
     if (nrows > 0) prefetch(y0);
     for (int r = 0; r < nrows; ++r) {
         const int y = y0 + r;
-        const long rowbase = ((long)z * d.n[1] + y) * d.n[0];
-        const long frow = ((long)z * d.n[1] + y) * (d.n[0] + 1);
+        const long rowbase = row_at(y);
         const double c0 = pc0, e0 = pe0, c1 = pc1, e1 = pe1, ev_own = pev, u = pu, ec_own = pec;
         const uint8_t cc_own = pcc;
         if (r + 1 < nrows) prefetch(y + 1);
@@ -237,7 +242,7 @@ __global__ void __launch_bounds__(XW* XWAVES) k_sweep_x(Dom d, SweepArgs a) {
                                               s_T[wave][q + 3], s_T[wave][q + 4], d.weno_eps)
                                       : weno5(s_T[wave][q + 5], s_T[wave][q + 4], s_T[wave][q + 3],
                                               s_T[wave][q + 2], s_T[wave][q + 1], d.weno_eps);
-                const double F = mixed(d, cd) ? a.fgeo[frow + x] : fabs(lam) * cd;
+                const double F = mixed(d, cd) ? s_F[wave][r][lane] : fabs(lam) * cd;
                 face_energy(d, lam, F, Tf, Phi, E);
             }
         }
@@ -245,11 +250,9 @@ __global__ void __launch_bounds__(XW* XWAVES) k_sweep_x(Dom d, SweepArgs a) {
         const double PhiR = __shfl_down(Phi, 1, 64);
         const double ER = __shfl_down(E, 1, 64);
         const double lamR = __shfl_down(lam, 1, 64);
-        bool take = false;
         if (own) {
-            const double cn = update_cell(d, a, rowbase + x, s_c[wave][lane + XH], ev_own, s_T[wave][lane + XH],
-                                          lam, lamR, Phi, PhiR, E, ER, cc_own, ec_own, acc);
-            take = mixed(d, cn);
+            update_cell(d, a, rowbase + x, s_c[wave][lane + XH], ev_own, s_T[wave][lane + XH], lam, lamR, Phi,
+                        PhiR, E, ER, cc_own, ec_own, acc);
             if (d.bc[0] == 1) {
                 if (x == 0) {
                     acc[2] -= Phi;
@@ -261,7 +264,6 @@ __global__ void __launch_bounds__(XW* XWAVES) k_sweep_x(Dom d, SweepArgs a) {
                 }
             }
         }
-        list_append(take, (unsigned)(rowbase + x), a.list_out, a.count_out);
         __builtin_amdgcn_wave_barrier();
     }
     const long blk = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
@@ -275,7 +277,11 @@ __global__ void __launch_bounds__(XW* XWAVES) k_sweep_x(Dom d, SweepArgs a) {
 template <int AX>
 __global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) {
     constexpr int TA = AX == 1 ? 2 : 1;  // the transverse axis other than x
+    __shared__ double s_F[4][TCH + 1][64];              // liquid flux of mixed donors
+    __shared__ unsigned short s_work[4 * (TCH + 1) * 64];  // faces with a mixed donor
+    __shared__ unsigned s_nwork;
     const int lane = threadIdx.x, tr = threadIdx.y;
+    const int tid = tr * 64 + lane;
     const int x = blockIdx.x * 64 + lane;
     const int t = blockIdx.y * 4 + tr;
     const int nt = (d.ndim == 2 && TA == 2) ? 1 : d.n[TA];
@@ -288,6 +294,53 @@ __global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) 
     const long stride = AX == 1 ? d.n[0] : plane;
     const long fbase = ok ? (AX == 1 ? (long)t * (d.n[1] + 1) * d.n[0] + x : (long)t * d.n[0] + x) : 0;
     const long fstride = AX == 1 ? d.n[0] : plane;
+    auto cell_id = [&](int cell) { return base + (long)wrap(cell, ns, d.bc[AX]) * stride; };
+
+    // Geometry, first pass: the faces s0 .. s1 of the block's columns whose upwind
+    // donor is mixed (item = row:face offset:lane).
+    // All loads are issued first (faces s0 .. s1 and cells s0-1 .. s1), so that they
+    // overlap.
+    if (tid == 0) s_nwork = 0u;
+    {
+        double g_lam[TCH + 1], g_c[TCH + 2];
+#pragma unroll
+        for (int j = 0; j < TCH + 2; ++j) {
+            g_c[j] = 0.0;
+            if (j <= TCH) g_lam[j] = 0.0;
+            if (ok && s0 - 1 + j <= s1) {
+                g_c[j] = a.c[cell_id(s0 - 1 + j)];
+                if (j <= TCH && s0 + j <= s1) g_lam[j] = a.vel[fbase + (long)(s0 + j) * fstride];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j <= TCH; ++j) {
+            if (s0 + j <= s1) {  // uniform over the block
+                const double lam = g_lam[j] * a.kfac;
+                const bool need = ok && lam != 0.0 && mixed(d, lam > 0.0 ? g_c[j] : g_c[j + 1]);
+                work_append(need, (unsigned short)((tr << 11) | (j << 6) | lane), s_work, &s_nwork);
+            }
+        }
+    }
+    __syncthreads();
+    // Second pass: every thread of the block takes listed faces.
+    {
+        const unsigned nwork = s_nwork;
+        for (unsigned i = tid; i < nwork; i += 256) {
+            const unsigned it = s_work[i];
+            const int w = it >> 11, fl = (it >> 6) & 31, l = it & 63;
+            const int xw = blockIdx.x * 64 + l, tw = blockIdx.y * 4 + w;
+            const long bw = AX == 1 ? (long)tw * plane + xw : (long)tw * d.n[0] + xw;
+            const long fw = AX == 1 ? (long)tw * (d.n[1] + 1) * d.n[0] + xw : (long)tw * d.n[0] + xw;
+            const int f = s0 + fl;
+            const double lam = a.vel[fw + (long)f * fstride] * a.kfac;
+            const int sd = lam > 0.0 ? f - 1 : f;
+            const double cd = a.c[bw + (long)wrap(sd, ns, d.bc[AX]) * stride];
+            s_F[w][fl][l] = AX == 1 ? donor_fraction<1>(d, a.c, xw, sd, tw, cd, lam)
+                                    : donor_fraction<2>(d, a.c, xw, tw, sd, cd, lam);
+        }
+    }
+    __syncthreads();
     // Register ring of cells f-3 .. f+4 in slots (k + j) % 8, where k counts the faces
     // of the chunk and j = 0..7 the cells from f-3: cells f-3 .. f+2 are the WENO and
     // update window, cells f+3, f+4 are loads in flight; at each face the load of cell
@@ -299,7 +352,6 @@ __global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) 
     double cr[R], er[R], Tw[R];
     double vr[4], ecr[4];
     uint8_t ccr[4];
-    auto cell_id = [&](int cell) { return base + (long)wrap(cell, ns, d.bc[AX]) * stride; };
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         cr[j] = 0.0;
@@ -340,20 +392,15 @@ __global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) 
         double Phi = 0.0, E = 0.0;
         if (lam != 0.0) {
             const double cd = lam > 0.0 ? cr[J2] : cr[J3];
-            const double F = mixed(d, cd) ? a.fgeo[fbase + (long)f * fstride] : fabs(lam) * cd;
+            const double F = mixed(d, cd) ? s_F[tr][f - s0][lane] : fabs(lam) * cd;
             const double Tf = lam > 0.0 ? weno5(Tw[J0], Tw[J1], Tw[J2], Tw[J3], Tw[J4], d.weno_eps)
                                         : weno5(Tw[J5], Tw[J4], Tw[J3], Tw[J2], Tw[J1], d.weno_eps);
             face_energy(d, lam, F, Tf, Phi, E);
         }
-        bool take = false;
-        unsigned id_out = 0;
         if (ok && f > s0) {
             const int cell = f - 1;
             const long id = base + (long)cell * stride;
-            const double cn = update_cell(d, a, id, cr[J2], er[J2], Tw[J2], lamP, lam, PhiP, Phi, EP, E,
-                                          ccr[V], ecr[V], acc);
-            take = mixed(d, cn);
-            id_out = (unsigned)id;
+            update_cell(d, a, id, cr[J2], er[J2], Tw[J2], lamP, lam, PhiP, Phi, EP, E, ccr[V], ecr[V], acc);
             if (d.bc[AX] == 1) {
                 if (cell == 0) {
                     acc[2] -= PhiP;
@@ -365,7 +412,6 @@ __global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) 
                 }
             }
         }
-        list_append(take, id_out, a.list_out, a.count_out);
         PhiP = Phi;
         EP = E;
         lamP = lam;
@@ -407,34 +453,32 @@ __global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) 
     block_sum8<4>(acc, a.part + blk, a.part_stride);
 }
 
-// Step 2, first pass (section 3.3.2), over the listed mixed cells of c~ with a non-zero
-// mass flux: the reconstruction and the moved plane constant, rec = (m, alpha~, alpha*)
+// Step 2, first pass (section 3.3.2), over every mixed cell of c~ with a non-zero mass
+// flux: the reconstruction and the moved plane constant, rec = (m, alpha~, alpha*)
 // with alpha* = alpha~ + |m|_2 Delta d and Delta d = -(m''/rho_l) dt / h.
 __global__ void __launch_bounds__(256)
 k_phase_recon(Dom d, const double* __restrict__ c, const double* __restrict__ mdot, double dt_h,
-              const unsigned* __restrict__ list, const unsigned* __restrict__ count, double* __restrict__ rec,
-              unsigned* count_next) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *count_next = 0u;
-    const unsigned n = *count;
-    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const unsigned id = list[i];
-        const double md = mdot[id];
-        if (md == 0.0) continue;
-        int x, y, z;
-        cell_coords(d, id, x, y, z);
-        double c27[27];
-        gather27(d, c, x, y, z, c27);
-        const Normal nm = normal27(c27, d.normal);
-        const double alpha = alpha_of(nm.m[0], nm.m[1], nm.m[2], c[id]);
-        const double dd = -(md / d.rho_l) * dt_h;
-        const double norm2 = sqrt(nm.m[0] * nm.m[0] + nm.m[1] * nm.m[1] + nm.m[2] * nm.m[2]);
-        double* r = rec + 5 * (long)id;
-        r[0] = nm.m[0];
-        r[1] = nm.m[1];
-        r[2] = nm.m[2];
-        r[3] = alpha;
-        r[4] = alpha + norm2 * dd;
-    }
+              double* __restrict__ rec) {
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= d.n[0] || y >= d.n[1]) return;
+    const long id = ((long)z * d.n[1] + y) * d.n[0] + x;
+    const double md = mdot[id];
+    const double cv = c[id];
+    if (md == 0.0 || !mixed(d, cv)) return;
+    double c27[27];
+    gather27(d, c, x, y, z, c27);
+    const Normal nm = normal27(c27, d.normal);
+    const double alpha = alpha_of(nm.m[0], nm.m[1], nm.m[2], cv);
+    const double dd = -(md / d.rho_l) * dt_h;
+    const double norm2 = sqrt(nm.m[0] * nm.m[0] + nm.m[1] * nm.m[1] + nm.m[2] * nm.m[2]);
+    double* r = rec + 5 * id;
+    r[0] = nm.m[0];
+    r[1] = nm.m[1];
+    r[2] = nm.m[2];
+    r[3] = alpha;
+    r[4] = alpha + norm2 * dd;
 }
 
 // Step 2, second pass: a moving cell takes V(m, alpha*) (the motion capped at the cell
@@ -445,16 +489,13 @@ k_phase_recon(Dom d, const double* __restrict__ c, const double* __restrict__ md
 __global__ void __launch_bounds__(256)
 k_phase_apply(Dom d, const double* __restrict__ c, const double* __restrict__ e,
               const double* __restrict__ mdot, double dt_h, const double* __restrict__ rec,
-              double* __restrict__ c_out, double* __restrict__ e_out, double* __restrict__ part, long part_stride,
-              unsigned* list_out, unsigned* count_out) {
+              double* __restrict__ c_out, double* __restrict__ e_out, double* __restrict__ part, long part_stride) {
     const int x = blockIdx.x * 64 + threadIdx.x;
     const int y = blockIdx.y * 4 + threadIdx.y;
     const int z = blockIdx.z;
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    bool take = false;
-    long id = 0;
     if (x < d.n[0] && y < d.n[1]) {
-        id = ((long)z * d.n[1] + y) * d.n[0] + x;
+        const long id = ((long)z * d.n[1] + y) * d.n[0] + x;
         const double cj = c[id];
         double cnew = cj;
         if (mixed(d, cj)) {
@@ -495,18 +536,9 @@ k_phase_apply(Dom d, const double* __restrict__ c, const double* __restrict__ e,
         acc[1] = de;
         acc[6] = cnew;
         acc[7] = enew;
-        take = mixed(d, cnew);
     }
-    list_append(take, (unsigned)id, list_out, count_out);
     const long blk = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
     block_sum8<4>(acc, part + blk, part_stride);
-}
-
-// Blocks of the list kernels (grid-stride over a device-side count): enough to keep
-// every CU busy with long lists, few enough to launch quickly with short ones.
-int list_grid(const Dom& d) {
-    const long nb = (d.ncell + 255) / 256;
-    return (int)(nb < 1024 ? (nb < 1 ? 1 : nb) : 1024);
 }
 
 }  // namespace
@@ -520,8 +552,9 @@ Launch cell_launch(const Dom& d) {
 }
 
 // Launch shape of a sweep. x: XRPW row segments of 63 cells per wavefront, four
-// wavefronts per block. y, z: 64 x 4 columns per block marching over a chunk of the sweep axis; the
-// chunk is the longest of 64, 32, 16, 8 cells that still gives >= 2048 blocks.
+// wavefronts per block. y, z: 64 x 4 columns per block marching over a chunk of the
+// sweep axis; the chunk is the longest of TCH, TCH / 2, ... 8 cells that still gives
+// >= 2048 blocks.
 Launch sweep_launch(const Dom& d, int axis, int* chunk) {
     Launch L;
     L.block = dim3(64, 4, 1);
@@ -533,7 +566,7 @@ Launch sweep_launch(const Dom& d, int axis, int* chunk) {
         const int nt = axis == 1 ? nz : d.n[1];
         const long bxy = (long)((d.n[0] + 63) / 64) * ((nt + 3) / 4);
         const int ns = d.n[axis];
-        int ch = 64;
+        int ch = TCH;
         while (ch > 8 && bxy * ((ns + ch - 1) / ch) < 2048) ch >>= 1;
         *chunk = ch;
         L.grid = dim3((d.n[0] + 63) / 64, (nt + 3) / 4, (ns + ch - 1) / ch);
@@ -551,33 +584,10 @@ int max_partial_blocks(const Dom& d) {
     return m;
 }
 
-hipError_t launch_classify(const Dom& d, const double* c, unsigned* list, unsigned* count, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, count);
-    hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k_classify, dim3((unsigned)((d.ncell + 255) / 256)), dim3(256), 0, s, d, c, list, count);
-    return hipGetLastError();
-}
-
-hipError_t launch_geo(const Dom& d, int axis, const SweepIO& io, hipStream_t s) {
-    const int gg = list_grid(d);
-    if (axis == 0)
-        hipLaunchKernelGGL(k_geo<0>, dim3(gg), dim3(256), 0, s, d, io.c, io.vel, io.kfac, io.list_in, io.count_in,
-                           io.fgeo, io.count_out);
-    else if (axis == 1)
-        hipLaunchKernelGGL(k_geo<1>, dim3(gg), dim3(256), 0, s, d, io.c, io.vel, io.kfac, io.list_in, io.count_in,
-                           io.fgeo, io.count_out);
-    else
-        hipLaunchKernelGGL(k_geo<2>, dim3(gg), dim3(256), 0, s, d, io.c, io.vel, io.kfac, io.list_in, io.count_in,
-                           io.fgeo, io.count_out);
-    return hipGetLastError();
-}
-
 hipError_t launch_sweep(const Dom& d, int axis, const SweepIO& io, hipStream_t s) {
     int chunk = 0;
     const Launch L = sweep_launch(d, axis, &chunk);
-    SweepArgs a{io.c,      io.e,     io.cc,          io.ec,       io.vel,       io.kfac, io.fgeo,
-                io.c_out,  io.e_out, io.part,        io.part_stride, io.list_out, io.count_out, io.first};
+    SweepArgs a{io.c, io.e, io.cc, io.ec, io.vel, io.kfac, io.c_out, io.e_out, io.part, io.part_stride, io.first};
     if (axis == 0)
         hipLaunchKernelGGL(k_sweep_x, L.grid, L.block, 0, s, d, a);
     else if (axis == 1)
@@ -590,13 +600,12 @@ hipError_t launch_sweep(const Dom& d, int axis, const SweepIO& io, hipStream_t s
 
 hipError_t launch_phase(const Dom& d, const PhaseIO& io, hipStream_t s) {
     const double dt_h = io.dt / io.h;
-    hipLaunchKernelGGL(k_phase_recon, dim3(list_grid(d)), dim3(256), 0, s, d, io.c, io.mdot, dt_h, io.list_in,
-                       io.count_in, io.rec, io.count_out);
+    const Launch L = cell_launch(d);
+    hipLaunchKernelGGL(k_phase_recon, L.grid, L.block, 0, s, d, io.c, io.mdot, dt_h, io.rec);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    const Launch L = cell_launch(d);
     hipLaunchKernelGGL(k_phase_apply, L.grid, L.block, 0, s, d, io.c, io.e, io.mdot, dt_h, io.rec, io.c_out,
-                       io.e_out, io.part, io.part_stride, io.list_out, io.count_out);
+                       io.e_out, io.part, io.part_stride);
     *io.nblocks = L.nblocks;
     return hipGetLastError();
 }

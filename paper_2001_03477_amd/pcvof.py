@@ -32,7 +32,7 @@ EXPORTS = (
     "pcvof_get_profile",
 )
 
-PROF_NAMES = ("geometry", "sweep_x", "sweep_y", "sweep_z", "phase", "checksum", "classify")
+PROF_NAMES = ("sweep_x", "sweep_y", "sweep_z", "phase", "checksum")
 
 
 class PcvofError(RuntimeError):
