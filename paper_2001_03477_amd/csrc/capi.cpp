@@ -51,7 +51,7 @@ long face_count(const pcvof_grid& g, int a) {
 
 // Workspace layout (offsets in bytes, each 256-byte aligned).
 struct Layout {
-    size_t c[2], e[2], ec, cc, vel[3], mdot, rec, part, colsum, flags, total;
+    size_t c[2], e[2], mask[2], ec, cc, vel[3], mdot, rec, part, colsum, flags, total;
     int maxb;  // rows of each partial table
 };
 
@@ -93,6 +93,7 @@ pcv::Dom make_dom(const pcvof_grid& g, const pcvof_params& p) {
     d.eps = p.eps_mixed;
     d.weno_eps = p.weno_eps;
     d.normal = p.normal;
+    d.wpr = (g.nx + pcv::kMaskCpwX - 1) / pcv::kMaskCpwX;
     return d;
 }
 
@@ -111,6 +112,8 @@ Layout make_layout(const pcvof_grid& g, const pcvof_params& p) {
         L.c[b] = take(n * dbl);
         L.e[b] = take(n * dbl);
     }
+    const size_t mask_words = (size_t)g.nz * g.ny * d.wpr;
+    for (int b = 0; b < 2; ++b) L.mask[b] = take(mask_words * sizeof(uint64_t));
     L.ec = take(n * dbl);
     L.cc = take(n);
     for (int a = 0; a < 3; ++a) {
@@ -136,7 +139,8 @@ struct pcvof_handle {
     Layout L;
     char* ws;
     hipStream_t stream;
-    int cur;                 // index of the current state buffer
+    int cur;                 // index of the current state buffer (fractions, energies, mask)
+    int mask_cpw;            // cells per word of the current mask
     bool has_vof, has_energy, has_vel, has_mdot;
     double umax[3];          // max |u_f| per axis, from set_velocity
     long step;
@@ -155,6 +159,7 @@ struct pcvof_handle {
 
     double* c(int b) { return (double*)(ws + L.c[b]); }
     double* e(int b) { return (double*)(ws + L.e[b]); }
+    uint64_t* mask(int b) { return (uint64_t*)(ws + L.mask[b]); }
     double* ec() { return (double*)(ws + L.ec); }
     uint8_t* cc() { return (uint8_t*)(ws + L.cc); }
     double* vel(int a) { return (double*)(ws + L.vel[a]); }
@@ -271,6 +276,7 @@ int pcvof_create(const pcvof_grid* grid, const pcvof_params* params, void* d_wor
     h->ws = (char*)d_workspace;
     h->stream = (hipStream_t)hip_stream;
     h->cur = 0;
+    h->mask_cpw = pcv::kMaskCpw;
     h->has_vof = h->has_energy = h->has_vel = h->has_mdot = false;
     h->umax[0] = h->umax[1] = h->umax[2] = 0.0;
     h->step = 0;
@@ -306,6 +312,8 @@ int pcvof_set_vof(pcvof_handle* h, const double* c, int mem) {
     if (int r = check_field(h, h->c(h->cur), h->d.ncell, 1, &f)) return r;
     if (f & 1u) return fail(PCVOF_ERR_NONFINITE, "volume fraction has NaN or Inf");
     if (f & 2u) return fail(PCVOF_ERR_BOUNDS, "volume fraction outside [0,1]");
+    HIP_TRY(pcv::launch_classify(h->d, h->c(h->cur), h->mask(h->cur), h->stream));
+    h->mask_cpw = pcv::kMaskCpw;
     h->has_vof = true;
     return PCVOF_OK;
 }
@@ -409,6 +417,9 @@ int pcvof_sweep(pcvof_handle* h, int axis, double dt, double u_scale) {
     pcv::SweepIO io;
     io.c = h->c(h->cur);
     io.e = h->e(h->cur);
+    io.mask = h->mask(h->cur);
+    io.mask_cpw = h->mask_cpw;
+    io.mask_out = h->mask(nxt);
     io.cc = h->cc();
     io.ec = h->ec();
     io.first = h->first_pending ? 1 : 0;
@@ -424,6 +435,7 @@ int pcvof_sweep(pcvof_handle* h, int axis, double dt, double u_scale) {
     prof_end(h, PCVOF_PROF_SWEEP_X + axis, ps);
     h->first_pending = false;
     h->cur = nxt;
+    h->mask_cpw = axis == 0 ? pcv::kMaskCpwX : pcv::kMaskCpw;
     h->sweeps_done++;
     h->last_slot = slot;
     return PCVOF_OK;
@@ -440,6 +452,7 @@ int pcvof_phase_change(pcvof_handle* h, double dt) {
     pcv::PhaseIO io;
     io.c = h->c(h->cur);
     io.e = h->e(h->cur);
+    io.mask_out = h->mask(nxt);
     io.mdot = h->mdot();
     io.dt = dt;
     io.h = h->g.h;
@@ -453,6 +466,7 @@ int pcvof_phase_change(pcvof_handle* h, double dt) {
     HIP_TRY(pcv::launch_phase(h->d, io, h->stream));
     prof_end(h, PCVOF_PROF_PHASE, ps);
     h->cur = nxt;
+    h->mask_cpw = pcv::kMaskCpw;
     h->last_slot = slot;
     return PCVOF_OK;
 }

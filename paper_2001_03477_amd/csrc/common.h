@@ -90,6 +90,13 @@ __device__ __forceinline__ void block_sum8(const double (&v)[8], double* out, lo
     }
 }
 
+// Bit of the mixed-cell mask (cells per word cpw) for cell x of the row starting at
+// word rowword.
+__device__ __forceinline__ bool mask_bit(const uint64_t* __restrict__ mask, long rowword, int x, int cpw) {
+    const int k = x / cpw;
+    return (mask[rowword + k] >> (x - k * cpw)) & 1ull;
+}
+
 // Index of face f along axis of the face row through transverse cell coordinates.
 __device__ __forceinline__ long face_at(const Dom& d, int axis, int x, int y, int z, int f) {
     if (axis == 0) return ((long)z * d.n[1] + y) * (d.n[0] + 1) + f;

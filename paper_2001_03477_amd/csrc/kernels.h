@@ -14,7 +14,14 @@ struct Dom {
     long ncell;
     double cp_l, cp_g, rho_l, T_gamma, eps, weno_eps;
     int normal;
+    int wpr;       // words per row of the mixed-cell masks: ceil(n[0] / 63)
 };
+
+// Mixed-cell mask of a state: one bit per cell, rows of wpr 64-bit words, word k of a
+// row holding cells k*cpw .. k*cpw + cpw - 1 (bit = offset). The x sweep writes masks
+// with cpw = 63 (one word per 63-cell row segment), every other kernel with cpw = 64.
+constexpr int kMaskCpwX = 63;
+constexpr int kMaskCpw = 64;
 
 // Per-block partial sums written by every stage kernel: 8 doubles per block.
 // Sweeps: clip_v, clip_e, bnd_v, bnd_e, src_v, src_e, tot_v, tot_e.
@@ -34,6 +41,9 @@ int max_partial_blocks(const Dom& d);
 struct SweepIO {
     const double* c;
     const double* e;
+    const uint64_t* mask;      // mixed cells of c, cells per word mask_cpw
+    int mask_cpw;
+    uint64_t* mask_out;        // mixed cells of c_out (cpw kMaskCpwX for axis 0, else kMaskCpw)
     uint8_t* cc;
     double* ec;
     int first;                 // also freeze c_c and e_c of the step (the prologue)
@@ -45,12 +55,16 @@ struct SweepIO {
     long part_stride;
     int* nblocks;              // out: blocks of the sweep kernel
 };
+// Mask of the mixed cells of c (cpw kMaskCpw), after the fractions were set.
+hipError_t launch_classify(const Dom& d, const double* c, uint64_t* mask, hipStream_t s);
+
 // A direction sweep is one launch (geometry of the mixed donors inside each tile).
 hipError_t launch_sweep(const Dom& d, int axis, const SweepIO& io, hipStream_t s);
 
 struct PhaseIO {
     const double* c;
     const double* e;
+    uint64_t* mask_out;        // mixed cells of c_out (cpw kMaskCpw)
     const double* mdot;
     double dt, h;
     double* rec;

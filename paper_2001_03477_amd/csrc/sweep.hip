@@ -23,6 +23,9 @@ namespace {
 struct SweepArgs {
     const double* c;
     const double* e;
+    const uint64_t* mask;  // mixed cells of c
+    int mask_cpw;
+    uint64_t* mask_out;    // mixed cells of c_out
     uint8_t* cc;       // written by the first sweep of a step, read by the others
     double* ec;
     const double* vel;
@@ -33,6 +36,16 @@ struct SweepArgs {
     long part_stride;
     int first;
 };
+
+// Mask of the mixed cells of c (cpw = 64), after the fractions were set from outside.
+__global__ void __launch_bounds__(256) k_classify(Dom d, const double* __restrict__ c, uint64_t* __restrict__ mask) {
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    const int z = blockIdx.z;
+    const bool mx = x < d.n[0] && y < d.n[1] && mixed(d, c[((long)z * d.n[1] + y) * d.n[0] + x]);
+    const unsigned long long bits = __ballot(mx);
+    if (threadIdx.x == 0 && y < d.n[1]) mask[((long)z * d.n[1] + y) * d.wpr + blockIdx.x] = bits;
+}
 
 // Liquid volume, in cell units, of the upwind region of the donor cell at (x, y, z)
 // (ghost positions allowed: they map like every other read) crossing a face of a
@@ -60,6 +73,11 @@ __device__ __forceinline__ void work_append(bool take, unsigned short item, unsi
     if (lane == leader) base = atomicAdd(n, (unsigned)__popcll(ballot));
     base = __shfl(base, leader, 64);
     if (take) work[base + __popcll(ballot & __lanemask_lt())] = item;
+}
+
+// Linear index of the block (row of the partial tables).
+__device__ __forceinline__ int block_linear() {
+    return (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
 }
 
 // Cell update of a sweep (section 3.3.1 with the split dilatation term, and the
@@ -138,9 +156,9 @@ __global__ void __launch_bounds__(XW* XWAVES) k_sweep_x(Dom d, SweepArgs a) {
     __shared__ unsigned s_nwork;
     const int lane = threadIdx.x, wave = threadIdx.y;
     const int tid = wave * XW + lane;
-    const int x0 = blockIdx.x * XC;
-    const int z = blockIdx.z;
-    const int y0 = (blockIdx.y * XWAVES + wave) * XRPW;
+    const int bx = blockIdx.x, by = blockIdx.y, z = blockIdx.z;
+    const int x0 = bx * XC;
+    const int y0 = (by * XWAVES + wave) * XRPW;
     const int x = x0 + lane;
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     const int nrows = max(0, min(XRPW, d.n[1] - y0));  // uniform over the wavefront
@@ -154,32 +172,34 @@ __global__ void __launch_bounds__(XW* XWAVES) k_sweep_x(Dom d, SweepArgs a) {
 
     // Geometry, first pass: the faces x0 .. x0+63 of the wavefront's rows whose upwind
     // donor is mixed (lane = face offset, item = wave:row:lane).
-    // All loads are issued first (both candidate donors of each face: cell x-1 in this
-    // lane, cell x from the next lane), so that they overlap.
+    // The candidates are the faces with a mixed cell on either side, read from the mask
+    // of the input (cell x-1 in this lane, cell x from the next lane); the mask words of
+    // all rows are loaded first, so that the loads overlap.
     if (tid == 0) s_nwork = 0u;
     {
+        const int cpw = a.mask_cpw;
         const int xl = wrap(x - 1, d.n[0], d.bc[0]);
         const int xr = wrap(x0 + XW - 1, d.n[0], d.bc[0]);  // lane 63's right cell
-        double g_lam[XRPW], g_cl[XRPW], g_cr[XRPW];
+        const int kl = xl / cpw, bl = xl - kl * cpw;
+        const int kr = xr / cpw, br = xr - kr * cpw;
+        uint64_t g_wl[XRPW], g_wr[XRPW];
 #pragma unroll
         for (int r = 0; r < XRPW; ++r) {
-            g_lam[r] = 0.0;
-            g_cl[r] = 0.0;
-            g_cr[r] = 0.0;
+            g_wl[r] = 0ull;
+            g_wr[r] = 0ull;
             if (r < nrows) {
-                const int y = y0 + r;
-                if (face) g_lam[r] = a.vel[face_row_at(y) + x];
-                g_cl[r] = a.c[row_at(y) + xl];
-                if (lane == XW - 1) g_cr[r] = a.c[row_at(y) + xr];
+                const long rw = ((long)z * d.n[1] + y0 + r) * d.wpr;
+                g_wl[r] = a.mask[rw + kl];
+                if (lane == XW - 1) g_wr[r] = a.mask[rw + kr];
             }
         }
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < XRPW; ++r) {
-            const double right = __shfl_down(g_cl[r], 1, 64);  // cell x of lane l is cell x-1 of lane l+1
-            const double cr = lane == XW - 1 ? g_cr[r] : right;
-            const double lam = g_lam[r] * a.kfac;
-            const bool need = r < nrows && face && lam != 0.0 && mixed(d, lam > 0.0 ? g_cl[r] : cr);
+            const int ml = (int)((g_wl[r] >> bl) & 1ull);
+            const int right = __shfl_down(ml, 1, 64);  // cell x of lane l is cell x-1 of lane l+1
+            const int mr = lane == XW - 1 ? (int)((g_wr[r] >> br) & 1ull) : right;
+            const bool need = r < nrows && face && (ml | mr);
             work_append(need, (unsigned short)((wave << 9) | (r << 6) | lane), s_work, &s_nwork);
         }
     }
@@ -189,11 +209,13 @@ __global__ void __launch_bounds__(XW* XWAVES) k_sweep_x(Dom d, SweepArgs a) {
     for (unsigned i = tid; i < nwork; i += XW * XWAVES) {
         const unsigned it = s_work[i];
         const int w = it >> 9, r = (it >> 6) & (XRPW - 1), l = it & (XW - 1);
-        const int y = (blockIdx.y * XWAVES + w) * XRPW + r;
+        const int y = (by * XWAVES + w) * XRPW + r;
         const int xf = x0 + l;
         const double lam = a.vel[face_row_at(y) + xf] * a.kfac;
+        if (lam == 0.0) continue;
         const int xd = lam > 0.0 ? xf - 1 : xf;
         const double cd = a.c[row_at(y) + wrap(xd, d.n[0], d.bc[0])];
+        if (!mixed(d, cd)) continue;
         s_F[w][r][l] = donor_fraction<0>(d, a.c, xd, y, z, cd, lam);
     }
     __syncthreads();
@@ -250,9 +272,11 @@ __global__ void __launch_bounds__(XW* XWAVES) k_sweep_x(Dom d, SweepArgs a) {
         const double PhiR = __shfl_down(Phi, 1, 64);
         const double ER = __shfl_down(E, 1, 64);
         const double lamR = __shfl_down(lam, 1, 64);
+        bool mx = false;
         if (own) {
-            update_cell(d, a, rowbase + x, s_c[wave][lane + XH], ev_own, s_T[wave][lane + XH], lam, lamR, Phi,
-                        PhiR, E, ER, cc_own, ec_own, acc);
+            const double cn = update_cell(d, a, rowbase + x, s_c[wave][lane + XH], ev_own, s_T[wave][lane + XH],
+                                          lam, lamR, Phi, PhiR, E, ER, cc_own, ec_own, acc);
+            mx = mixed(d, cn);
             if (d.bc[0] == 1) {
                 if (x == 0) {
                     acc[2] -= Phi;
@@ -264,10 +288,12 @@ __global__ void __launch_bounds__(XW* XWAVES) k_sweep_x(Dom d, SweepArgs a) {
                 }
             }
         }
+        // mask of the output: the segment's 63 cells are one word (cpw = 63)
+        const unsigned long long bits = __ballot(mx);
+        if (lane == 0) a.mask_out[((long)z * d.n[1] + y) * d.wpr + bx] = bits;
         __builtin_amdgcn_wave_barrier();
     }
-    const long blk = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    block_sum8<XWAVES>(acc, a.part + blk, a.part_stride);
+    block_sum8<XWAVES>(acc, a.part + block_linear(), a.part_stride);
 }
 
 // y and z sweeps: each thread owns one column along the sweep axis (x across the
@@ -282,12 +308,13 @@ __global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) 
     __shared__ unsigned s_nwork;
     const int lane = threadIdx.x, tr = threadIdx.y;
     const int tid = tr * 64 + lane;
-    const int x = blockIdx.x * 64 + lane;
-    const int t = blockIdx.y * 4 + tr;
+    const int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+    const int x = bx * 64 + lane;
+    const int t = by * 4 + tr;
     const int nt = (d.ndim == 2 && TA == 2) ? 1 : d.n[TA];
     const bool ok = x < d.n[0] && t < nt;
     const int ns = d.n[AX];
-    const int s0 = blockIdx.z * chunk;
+    const int s0 = bz * chunk;
     const int s1 = min(s0 + chunk, ns);
     const long plane = (long)d.n[0] * d.n[1];
     const long base = ok ? (AX == 1 ? (long)t * plane + x : (long)t * d.n[0] + x) : 0;
@@ -298,26 +325,28 @@ __global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) 
 
     // Geometry, first pass: the faces s0 .. s1 of the block's columns whose upwind
     // donor is mixed (item = row:face offset:lane).
-    // All loads are issued first (faces s0 .. s1 and cells s0-1 .. s1), so that they
-    // overlap.
+    // The candidates are the faces with a mixed cell on either side, read from the mask
+    // of the input (cells s0-1 .. s1 of the column); the mask words are loaded first, so
+    // that the loads overlap.
     if (tid == 0) s_nwork = 0u;
     {
-        double g_lam[TCH + 1], g_c[TCH + 2];
+        const int cpw = a.mask_cpw;
+        const int kx = x / cpw, bx = x - kx * cpw;
+        uint64_t g_w[TCH + 2];
 #pragma unroll
         for (int j = 0; j < TCH + 2; ++j) {
-            g_c[j] = 0.0;
-            if (j <= TCH) g_lam[j] = 0.0;
+            g_w[j] = 0ull;
             if (ok && s0 - 1 + j <= s1) {
-                g_c[j] = a.c[cell_id(s0 - 1 + j)];
-                if (j <= TCH && s0 + j <= s1) g_lam[j] = a.vel[fbase + (long)(s0 + j) * fstride];
+                const int cell = wrap(s0 - 1 + j, ns, d.bc[AX]);
+                const long row = AX == 1 ? (long)t * d.n[1] + cell : (long)cell * d.n[1] + t;
+                g_w[j] = a.mask[row * d.wpr + kx];
             }
         }
         __syncthreads();
 #pragma unroll
         for (int j = 0; j <= TCH; ++j) {
             if (s0 + j <= s1) {  // uniform over the block
-                const double lam = g_lam[j] * a.kfac;
-                const bool need = ok && lam != 0.0 && mixed(d, lam > 0.0 ? g_c[j] : g_c[j + 1]);
+                const bool need = ok && (((g_w[j] | g_w[j + 1]) >> bx) & 1ull);
                 work_append(need, (unsigned short)((tr << 11) | (j << 6) | lane), s_work, &s_nwork);
             }
         }
@@ -329,13 +358,15 @@ __global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) 
         for (unsigned i = tid; i < nwork; i += 256) {
             const unsigned it = s_work[i];
             const int w = it >> 11, fl = (it >> 6) & 31, l = it & 63;
-            const int xw = blockIdx.x * 64 + l, tw = blockIdx.y * 4 + w;
+            const int xw = bx * 64 + l, tw = by * 4 + w;
             const long bw = AX == 1 ? (long)tw * plane + xw : (long)tw * d.n[0] + xw;
             const long fw = AX == 1 ? (long)tw * (d.n[1] + 1) * d.n[0] + xw : (long)tw * d.n[0] + xw;
             const int f = s0 + fl;
             const double lam = a.vel[fw + (long)f * fstride] * a.kfac;
+            if (lam == 0.0) continue;
             const int sd = lam > 0.0 ? f - 1 : f;
             const double cd = a.c[bw + (long)wrap(sd, ns, d.bc[AX]) * stride];
+            if (!mixed(d, cd)) continue;
             s_F[w][fl][l] = AX == 1 ? donor_fraction<1>(d, a.c, xw, sd, tw, cd, lam)
                                     : donor_fraction<2>(d, a.c, xw, tw, sd, cd, lam);
         }
@@ -397,10 +428,13 @@ __global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) 
                                         : weno5(Tw[J5], Tw[J4], Tw[J3], Tw[J2], Tw[J1], d.weno_eps);
             face_energy(d, lam, F, Tf, Phi, E);
         }
+        bool mx = false;
         if (ok && f > s0) {
             const int cell = f - 1;
             const long id = base + (long)cell * stride;
-            update_cell(d, a, id, cr[J2], er[J2], Tw[J2], lamP, lam, PhiP, Phi, EP, E, ccr[V], ecr[V], acc);
+            const double cn =
+                update_cell(d, a, id, cr[J2], er[J2], Tw[J2], lamP, lam, PhiP, Phi, EP, E, ccr[V], ecr[V], acc);
+            mx = mixed(d, cn);
             if (d.bc[AX] == 1) {
                 if (cell == 0) {
                     acc[2] -= PhiP;
@@ -410,6 +444,13 @@ __global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) 
                     acc[2] += Phi;
                     acc[3] += E;
                 }
+            }
+        }
+        if (f > s0) {  // mask of the output: the wavefront's 64 cells are one word (cpw = 64)
+            const unsigned long long bits = __ballot(mx);
+            if (lane == 0 && t < nt) {
+                const long row = AX == 1 ? (long)t * d.n[1] + (f - 1) : (long)(f - 1) * d.n[1] + t;
+                a.mask_out[row * d.wpr + bx] = bits;
             }
         }
         PhiP = Phi;
@@ -449,8 +490,7 @@ __global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) 
         if (f + 7 > s1) break;
         step(integral_constant<int, 7>{}, f + 7);
     }
-    const long blk = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    block_sum8<4>(acc, a.part + blk, a.part_stride);
+    block_sum8<4>(acc, a.part + block_linear(), a.part_stride);
 }
 
 // Step 2, first pass (section 3.3.2), over every mixed cell of c~ with a non-zero mass
@@ -489,11 +529,13 @@ k_phase_recon(Dom d, const double* __restrict__ c, const double* __restrict__ md
 __global__ void __launch_bounds__(256)
 k_phase_apply(Dom d, const double* __restrict__ c, const double* __restrict__ e,
               const double* __restrict__ mdot, double dt_h, const double* __restrict__ rec,
-              double* __restrict__ c_out, double* __restrict__ e_out, double* __restrict__ part, long part_stride) {
+              double* __restrict__ c_out, double* __restrict__ e_out, uint64_t* __restrict__ mask_out,
+              double* __restrict__ part, long part_stride) {
     const int x = blockIdx.x * 64 + threadIdx.x;
     const int y = blockIdx.y * 4 + threadIdx.y;
     const int z = blockIdx.z;
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    bool mx = false;
     if (x < d.n[0] && y < d.n[1]) {
         const long id = ((long)z * d.n[1] + y) * d.n[0] + x;
         const double cj = c[id];
@@ -536,7 +578,10 @@ k_phase_apply(Dom d, const double* __restrict__ c, const double* __restrict__ e,
         acc[1] = de;
         acc[6] = cnew;
         acc[7] = enew;
+        mx = mixed(d, cnew);
     }
+    const unsigned long long bits = __ballot(mx);
+    if (threadIdx.x == 0 && y < d.n[1]) mask_out[((long)z * d.n[1] + y) * d.wpr + blockIdx.x] = bits;
     const long blk = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
     block_sum8<4>(acc, part + blk, part_stride);
 }
@@ -584,10 +629,17 @@ int max_partial_blocks(const Dom& d) {
     return m;
 }
 
+hipError_t launch_classify(const Dom& d, const double* c, uint64_t* mask, hipStream_t s) {
+    const Launch L = cell_launch(d);
+    hipLaunchKernelGGL(k_classify, L.grid, L.block, 0, s, d, c, mask);
+    return hipGetLastError();
+}
+
 hipError_t launch_sweep(const Dom& d, int axis, const SweepIO& io, hipStream_t s) {
     int chunk = 0;
     const Launch L = sweep_launch(d, axis, &chunk);
-    SweepArgs a{io.c, io.e, io.cc, io.ec, io.vel, io.kfac, io.c_out, io.e_out, io.part, io.part_stride, io.first};
+    SweepArgs a{io.c,     io.e,     io.mask, io.mask_cpw,    io.mask_out, io.cc,   io.ec,
+                io.vel,   io.kfac,  io.c_out, io.e_out,       io.part,     io.part_stride, io.first};
     if (axis == 0)
         hipLaunchKernelGGL(k_sweep_x, L.grid, L.block, 0, s, d, a);
     else if (axis == 1)
@@ -605,7 +657,7 @@ hipError_t launch_phase(const Dom& d, const PhaseIO& io, hipStream_t s) {
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(k_phase_apply, L.grid, L.block, 0, s, d, io.c, io.e, io.mdot, dt_h, io.rec, io.c_out,
-                       io.e_out, io.part, io.part_stride);
+                       io.e_out, io.mask_out, io.part, io.part_stride);
     *io.nblocks = L.nblocks;
     return hipGetLastError();
 }
