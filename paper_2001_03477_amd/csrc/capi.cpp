@@ -51,7 +51,7 @@ long face_count(const pcvof_grid& g, int a) {
 
 // Workspace layout (offsets in bytes, each 256-byte aligned).
 struct Layout {
-    size_t c[2], e[2], mask[2], ec, cc, vel[3], mdot, rec, part, colsum, flags, total;
+    size_t c[2], e[2], mask[2], ec, cc, vel[3], fgeo, mdot, rec, part, colsum, flags, total;
     int maxb;  // rows of each partial table
 };
 
@@ -116,10 +116,13 @@ Layout make_layout(const pcvof_grid& g, const pcvof_params& p) {
     for (int b = 0; b < 2; ++b) L.mask[b] = take(mask_words * sizeof(uint64_t));
     L.ec = take(n * dbl);
     L.cc = take(n);
+    size_t maxf = 1;
     for (int a = 0; a < 3; ++a) {
         const size_t nf = a < g.ndim ? (size_t)face_count(g, a) : 1;
         L.vel[a] = take(nf * dbl);
+        if (nf > maxf) maxf = nf;
     }
+    L.fgeo = take(maxf * dbl);
     L.mdot = take(n * dbl);
     L.rec = take(5 * n * dbl);
     L.maxb = pcv::max_partial_blocks(d);
@@ -160,6 +163,7 @@ struct pcvof_handle {
     double* c(int b) { return (double*)(ws + L.c[b]); }
     double* e(int b) { return (double*)(ws + L.e[b]); }
     uint64_t* mask(int b) { return (uint64_t*)(ws + L.mask[b]); }
+    double* fgeo() { return (double*)(ws + L.fgeo); }
     double* ec() { return (double*)(ws + L.ec); }
     uint8_t* cc() { return (uint8_t*)(ws + L.cc); }
     double* vel(int a) { return (double*)(ws + L.vel[a]); }
@@ -425,6 +429,7 @@ int pcvof_sweep(pcvof_handle* h, int axis, double dt, double u_scale) {
     io.first = h->first_pending ? 1 : 0;
     io.vel = h->vel(axis);
     io.kfac = kfac;
+    io.fgeo = h->fgeo();
     io.c_out = h->c(nxt);
     io.e_out = h->e(nxt);
     io.part = h->part(slot);

@@ -49,6 +49,7 @@ struct SweepIO {
     int first;                 // also freeze c_c and e_c of the step (the prologue)
     const double* vel;
     double kfac;               // lambda_f = vel_f * kfac
+    double* fgeo;              // face array (layout of vel) for donor fluxes beyond the LDS tables
     double* c_out;
     double* e_out;
     double* part;              // partials: quantity q of block b at part[q * part_stride + b]

@@ -2,14 +2,15 @@
 // conservative energy fluxes of section 3.4.1) and step 2 with its latent correction
 // (section 3.3.2, section 3.4.1).
 //
-// A sweep is one launch over tiles of faces. Each block first finds the faces of its
-// tile whose upwind donor is a mixed cell, then reconstructs those donors with all of
-// its threads (normal, plane constant, liquid volume of the upwind face-flux region)
-// into a table in LDS, and then streams over its cells: WENO5 face temperatures, face
-// fluxes (the table for mixed donors, |lambda| c for pure ones), the cell update, the
-// clip and the checksum partials. The geometry of one block overlaps with the
-// streaming of the other blocks resident on the same CU. All floating point is double
-// precision.
+// A sweep is one launch over tiles of faces. Each wavefront first finds the faces of
+// its rows (x sweep) or columns (y, z sweeps) with a mixed cell on either side, from
+// the mixed-cell mask of the input, then reconstructs the mixed upwind donors of those
+// faces with all of its lanes (normal, plane constant, liquid volume of the upwind
+// face-flux region) into a table in LDS, and then streams over its cells: WENO5 face
+// temperatures, face fluxes (the table for mixed donors, |lambda| c for pure ones),
+// the cell update, the clip, the checksum partials and the mask of the output. The
+// geometry of one wavefront overlaps with the streaming of the others on the same
+// SIMD. All floating point is double precision.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -30,6 +31,7 @@ struct SweepArgs {
     double* ec;
     const double* vel;
     double kfac;
+    double* fgeo;          // overflow of the y / z blocks' LDS flux tables, face layout of vel
     double* c_out;
     double* e_out;
     double* part;        // quantity-major partial table of this stage
@@ -62,17 +64,14 @@ __device__ double donor_fraction(const Dom& d, const double* __restrict__ c, int
     return slab(nm.m[0], nm.m[1], nm.m[2], alpha, AX, lam);
 }
 
-// Appends item to a block's work list in LDS when take is true (one LDS atomic per
-// wavefront).
-__device__ __forceinline__ void work_append(bool take, unsigned short item, unsigned short* work, unsigned* n) {
+// Appends item to a wavefront's work list in LDS where take is true; n is the
+// wavefront-uniform length of the list. Returns the item's position.
+__device__ __forceinline__ unsigned work_append(bool take, unsigned short item, unsigned short* work, unsigned& n) {
     const unsigned long long ballot = __ballot(take);
-    if (!ballot) return;
-    const int lane = __lane_id();
-    const int leader = __ffsll((long long)ballot) - 1;
-    unsigned base = 0;
-    if (lane == leader) base = atomicAdd(n, (unsigned)__popcll(ballot));
-    base = __shfl(base, leader, 64);
-    if (take) work[base + __popcll(ballot & __lanemask_lt())] = item;
+    const unsigned pos = n + (unsigned)__popcll(ballot & __lanemask_lt());
+    if (take) work[pos] = item;
+    n += (unsigned)__popcll(ballot);
+    return pos;
 }
 
 // Linear index of the block (row of the partial tables).
@@ -145,17 +144,19 @@ constexpr int XH = 3;
 // reads temperatures up to x0+65 and donors up to x0+63
 constexpr int XS = XW + 5;
 
-// Longest column chunk of the y and z sweeps (sizes their LDS flux table).
-constexpr int TCH = 16;
+// Longest column chunk of the y and z sweeps, and the number of donor fluxes a y / z
+// wavefront keeps in LDS (fluxes beyond it go to a face array in global memory,
+// written and read back by the same wavefront).
+constexpr int TCH = 32;
+constexpr int TFCAP = 256;
+static_assert(TCH < 64 && (TCH + 1) * 64 <= 65536, "work items and positions fit 16 bits");
 
 __global__ void __launch_bounds__(XW* XWAVES) k_sweep_x(Dom d, SweepArgs a) {
     __shared__ double s_c[XWAVES][XS];
     __shared__ double s_T[XWAVES][XS];
     __shared__ double s_F[XWAVES][XRPW][XW];                 // liquid flux of mixed donors
-    __shared__ unsigned short s_work[XWAVES * XRPW * XW];   // faces with a mixed donor
-    __shared__ unsigned s_nwork;
+    __shared__ unsigned short s_work[XWAVES][XRPW * XW];    // candidate faces (row:lane)
     const int lane = threadIdx.x, wave = threadIdx.y;
-    const int tid = wave * XW + lane;
     const int bx = blockIdx.x, by = blockIdx.y, z = blockIdx.z;
     const int x0 = bx * XC;
     const int y0 = (by * XWAVES + wave) * XRPW;
@@ -170,12 +171,11 @@ __global__ void __launch_bounds__(XW* XWAVES) k_sweep_x(Dom d, SweepArgs a) {
     auto row_at = [&](int y) { return ((long)z * d.n[1] + y) * d.n[0]; };
     auto face_row_at = [&](int y) { return ((long)z * d.n[1] + y) * (d.n[0] + 1); };
 
-    // Geometry, first pass: the faces x0 .. x0+63 of the wavefront's rows whose upwind
-    // donor is mixed (lane = face offset, item = wave:row:lane).
-    // The candidates are the faces with a mixed cell on either side, read from the mask
-    // of the input (cell x-1 in this lane, cell x from the next lane); the mask words of
+    // Geometry, first pass: the faces x0 .. x0+63 of the wavefront's rows with a mixed
+    // cell on either side (lane = face offset, item = row:lane), read from the mask of
+    // the input (cell x-1 in this lane, cell x from the next lane); the mask words of
     // all rows are loaded first, so that the loads overlap.
-    if (tid == 0) s_nwork = 0u;
+    unsigned nwork = 0;
     {
         const int cpw = a.mask_cpw;
         const int xl = wrap(x - 1, d.n[0], d.bc[0]);
@@ -193,32 +193,30 @@ __global__ void __launch_bounds__(XW* XWAVES) k_sweep_x(Dom d, SweepArgs a) {
                 if (lane == XW - 1) g_wr[r] = a.mask[rw + kr];
             }
         }
-        __syncthreads();
 #pragma unroll
         for (int r = 0; r < XRPW; ++r) {
             const int ml = (int)((g_wl[r] >> bl) & 1ull);
             const int right = __shfl_down(ml, 1, 64);  // cell x of lane l is cell x-1 of lane l+1
             const int mr = lane == XW - 1 ? (int)((g_wr[r] >> br) & 1ull) : right;
             const bool need = r < nrows && face && (ml | mr);
-            work_append(need, (unsigned short)((wave << 9) | (r << 6) | lane), s_work, &s_nwork);
+            work_append(need, (unsigned short)((r << 6) | lane), s_work[wave], nwork);
         }
     }
-    __syncthreads();
-    // Second pass: every thread of the block takes listed faces.
-    const unsigned nwork = s_nwork;
-    for (unsigned i = tid; i < nwork; i += XW * XWAVES) {
-        const unsigned it = s_work[i];
-        const int w = it >> 9, r = (it >> 6) & (XRPW - 1), l = it & (XW - 1);
-        const int y = (by * XWAVES + w) * XRPW + r;
+    __builtin_amdgcn_wave_barrier();
+    // Second pass: the lanes take the listed faces whose donor is mixed.
+    for (unsigned i = lane; i < nwork; i += XW) {
+        const unsigned it = s_work[wave][i];
+        const int r = it >> 6, l = it & (XW - 1);
+        const int y = y0 + r;
         const int xf = x0 + l;
         const double lam = a.vel[face_row_at(y) + xf] * a.kfac;
         if (lam == 0.0) continue;
         const int xd = lam > 0.0 ? xf - 1 : xf;
         const double cd = a.c[row_at(y) + wrap(xd, d.n[0], d.bc[0])];
         if (!mixed(d, cd)) continue;
-        s_F[w][r][l] = donor_fraction<0>(d, a.c, xd, y, z, cd, lam);
+        s_F[wave][r][l] = donor_fraction<0>(d, a.c, xd, y, z, cd, lam);
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
     double pc0 = 0, pe0 = 0, pc1 = 0, pe1 = 0, pev = 0, pu = 0, pec = 0;
     uint8_t pcc = 0;
     auto prefetch = [&](int y) {
@@ -303,11 +301,10 @@ __global__ void __launch_bounds__(XW* XWAVES) k_sweep_x(Dom d, SweepArgs a) {
 template <int AX>
 __global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) {
     constexpr int TA = AX == 1 ? 2 : 1;  // the transverse axis other than x
-    __shared__ double s_F[4][TCH + 1][64];              // liquid flux of mixed donors
-    __shared__ unsigned short s_work[4 * (TCH + 1) * 64];  // faces with a mixed donor
-    __shared__ unsigned s_nwork;
+    __shared__ unsigned short s_idx[4][TCH + 1][64];     // work position of each candidate face
+    __shared__ unsigned short s_work[4][(TCH + 1) * 64];  // candidate faces (face offset:lane)
+    __shared__ double s_F[4][TFCAP];                      // liquid flux of mixed donors, by position
     const int lane = threadIdx.x, tr = threadIdx.y;
-    const int tid = tr * 64 + lane;
     const int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
     const int x = bx * 64 + lane;
     const int t = by * 4 + tr;
@@ -323,15 +320,14 @@ __global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) 
     const long fstride = AX == 1 ? d.n[0] : plane;
     auto cell_id = [&](int cell) { return base + (long)wrap(cell, ns, d.bc[AX]) * stride; };
 
-    // Geometry, first pass: the faces s0 .. s1 of the block's columns whose upwind
-    // donor is mixed (item = row:face offset:lane).
-    // The candidates are the faces with a mixed cell on either side, read from the mask
-    // of the input (cells s0-1 .. s1 of the column); the mask words are loaded first, so
-    // that the loads overlap.
-    if (tid == 0) s_nwork = 0u;
+    // Geometry, first pass: the faces s0 .. s1 of the wavefront's columns with a mixed
+    // cell on either side (item = face offset:lane), read from the mask of the input
+    // (cells s0-1 .. s1 of the column); the mask words are loaded first, so that the
+    // loads overlap.
+    unsigned nwork = 0;
     {
         const int cpw = a.mask_cpw;
-        const int kx = x / cpw, bx = x - kx * cpw;
+        const int kw = x / cpw, kb = x - kw * cpw;
         uint64_t g_w[TCH + 2];
 #pragma unroll
         for (int j = 0; j < TCH + 2; ++j) {
@@ -339,39 +335,40 @@ __global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) 
             if (ok && s0 - 1 + j <= s1) {
                 const int cell = wrap(s0 - 1 + j, ns, d.bc[AX]);
                 const long row = AX == 1 ? (long)t * d.n[1] + cell : (long)cell * d.n[1] + t;
-                g_w[j] = a.mask[row * d.wpr + kx];
+                g_w[j] = a.mask[row * d.wpr + kw];
             }
         }
-        __syncthreads();
 #pragma unroll
         for (int j = 0; j <= TCH; ++j) {
             if (s0 + j <= s1) {  // uniform over the block
-                const bool need = ok && (((g_w[j] | g_w[j + 1]) >> bx) & 1ull);
-                work_append(need, (unsigned short)((tr << 11) | (j << 6) | lane), s_work, &s_nwork);
+                const bool need = ok && (((g_w[j] | g_w[j + 1]) >> kb) & 1ull);
+                const unsigned pos = work_append(need, (unsigned short)((j << 6) | lane), s_work[tr], nwork);
+                if (need) s_idx[tr][j][lane] = (unsigned short)pos;
             }
         }
     }
-    __syncthreads();
-    // Second pass: every thread of the block takes listed faces.
-    {
-        const unsigned nwork = s_nwork;
-        for (unsigned i = tid; i < nwork; i += 256) {
-            const unsigned it = s_work[i];
-            const int w = it >> 11, fl = (it >> 6) & 31, l = it & 63;
-            const int xw = bx * 64 + l, tw = by * 4 + w;
-            const long bw = AX == 1 ? (long)tw * plane + xw : (long)tw * d.n[0] + xw;
-            const long fw = AX == 1 ? (long)tw * (d.n[1] + 1) * d.n[0] + xw : (long)tw * d.n[0] + xw;
-            const int f = s0 + fl;
-            const double lam = a.vel[fw + (long)f * fstride] * a.kfac;
-            if (lam == 0.0) continue;
-            const int sd = lam > 0.0 ? f - 1 : f;
-            const double cd = a.c[bw + (long)wrap(sd, ns, d.bc[AX]) * stride];
-            if (!mixed(d, cd)) continue;
-            s_F[w][fl][l] = AX == 1 ? donor_fraction<1>(d, a.c, xw, sd, tw, cd, lam)
-                                    : donor_fraction<2>(d, a.c, xw, tw, sd, cd, lam);
-        }
+    __builtin_amdgcn_wave_barrier();
+    // Second pass: the lanes take the listed faces whose donor is mixed.
+    for (unsigned i = lane; i < nwork; i += 64) {
+        const unsigned it = s_work[tr][i];
+        const int fl = it >> 6, l = it & 63;
+        const int xw = bx * 64 + l;
+        const long bw = AX == 1 ? (long)t * plane + xw : (long)t * d.n[0] + xw;
+        const long fw = AX == 1 ? (long)t * (d.n[1] + 1) * d.n[0] + xw : (long)t * d.n[0] + xw;
+        const int f = s0 + fl;
+        const double lam = a.vel[fw + (long)f * fstride] * a.kfac;
+        if (lam == 0.0) continue;
+        const int sd = lam > 0.0 ? f - 1 : f;
+        const double cd = a.c[bw + (long)wrap(sd, ns, d.bc[AX]) * stride];
+        if (!mixed(d, cd)) continue;
+        const double F = AX == 1 ? donor_fraction<1>(d, a.c, xw, sd, t, cd, lam)
+                                 : donor_fraction<2>(d, a.c, xw, t, sd, cd, lam);
+        if (i < TFCAP) s_F[tr][i] = F;
+        else a.fgeo[fw + (long)f * fstride] = F;
     }
-    __syncthreads();
+    // the overflow fluxes are read back by other lanes of this wavefront
+    if (nwork > TFCAP) __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
     // Register ring of cells f-3 .. f+4 in slots (k + j) % 8, where k counts the faces
     // of the chunk and j = 0..7 the cells from f-3: cells f-3 .. f+2 are the WENO and
     // update window, cells f+3, f+4 are loads in flight; at each face the load of cell
@@ -423,7 +420,11 @@ __global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) 
         double Phi = 0.0, E = 0.0;
         if (lam != 0.0) {
             const double cd = lam > 0.0 ? cr[J2] : cr[J3];
-            const double F = mixed(d, cd) ? s_F[tr][f - s0][lane] : fabs(lam) * cd;
+            double F = fabs(lam) * cd;
+            if (mixed(d, cd)) {
+                const unsigned idx = s_idx[tr][f - s0][lane];
+                F = idx < TFCAP ? s_F[tr][idx] : a.fgeo[fbase + (long)f * fstride];
+            }
             const double Tf = lam > 0.0 ? weno5(Tw[J0], Tw[J1], Tw[J2], Tw[J3], Tw[J4], d.weno_eps)
                                         : weno5(Tw[J5], Tw[J4], Tw[J3], Tw[J2], Tw[J1], d.weno_eps);
             face_energy(d, lam, F, Tf, Phi, E);
@@ -638,8 +639,8 @@ hipError_t launch_classify(const Dom& d, const double* c, uint64_t* mask, hipStr
 hipError_t launch_sweep(const Dom& d, int axis, const SweepIO& io, hipStream_t s) {
     int chunk = 0;
     const Launch L = sweep_launch(d, axis, &chunk);
-    SweepArgs a{io.c,     io.e,     io.mask, io.mask_cpw,    io.mask_out, io.cc,   io.ec,
-                io.vel,   io.kfac,  io.c_out, io.e_out,       io.part,     io.part_stride, io.first};
+    SweepArgs a{io.c,   io.e,    io.mask, io.mask_cpw, io.mask_out, io.cc,   io.ec,          io.vel,
+                io.kfac, io.fgeo, io.c_out, io.e_out,   io.part,     io.part_stride, io.first};
     if (axis == 0)
         hipLaunchKernelGGL(k_sweep_x, L.grid, L.block, 0, s, d, a);
     else if (axis == 1)

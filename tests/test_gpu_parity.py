@@ -327,3 +327,22 @@ def test_profiling_times_the_selected_classes(pc):
     with pytest.raises(pc.PcvofError) as ex:
         pc.check(pc.lib().pcvof_set_profiling(d._h, 1 << 5))
     assert ex.value.code == -1
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 1)])
+def test_every_cell_mixed(pc, bc):
+    """A field where every cell is mixed: every face needs the donor geometry, which
+    overflows the sweep blocks' LDS flux tables into the global face array."""
+    rng = np.random.default_rng(51)
+    wl = W.random_drops_3d(n=40, ndrops=3, seed=52, rmin=2.0, rmax=4.0)
+    wl.bc = bc
+    wl.c = rng.uniform(0.05, 0.95, size=wl.shape)
+    wl.e = wl.c * wl.cp_l * 0.7 + (1 - wl.c) * wl.cp_g * 0.3
+    spec, cfg = _specs(pc, wl)
+    d = _domain(pc, spec, wl)
+    c, e = wl.c, wl.e
+    for k in range(2):
+        d.step(wl.dt)
+        c, e, _ = oracle.step(cfg, c, e, wl.u, wl.v, wl.w, None, wl.dt, 1.0, k)
+    _assert_close(d.vof().cpu().numpy(), c, 1.0, "c")
+    _assert_close(d.energy().cpu().numpy(), e, float(np.max(np.abs(wl.e))), "e")
