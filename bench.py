@@ -5,10 +5,12 @@ Workload (default): the 3D 128^3 LeVeque deformation of a sphere R = 0.15 at
 m'' = 0, FP64. A step is the whole hot path: prologue, three direction sweeps
 (geometric VOF fluxes + conservative WENO5 energy fluxes), checksums.
 
-Prints one JSON line: whole-job cell-updates/s over the timed steps (inputs already
-resident in HBM), the roofline of the dominant kernel (the sweep; algorithmic bytes
-per launch over its average duration measured with HIP events on the library's
-stream), and the oracle timed on the host on a bounded sample.
+Prints one JSON line: whole-job cell-updates/s of the FP64 path over the timed steps
+(inputs already resident in HBM), the roofline of the dominant kernel (the sweep;
+algorithmic bytes per launch over its average duration measured with HIP events on
+the library's stream), the same run in the mixed-precision mode (rate, speedup,
+roofline, volume drift and difference from the FP64 fractions), and the oracle timed
+on the host on a bounded sample.
 """
 import argparse
 import json
@@ -29,6 +31,9 @@ HBM_PEAK_GBS = 8000.0
 # first sweep of a step writes c_c and e_c instead of reading them (same count).
 SWEEP_BYTES_PER_CELL = 8 + 8 + 8 + 1 + 8 + 8
 SWEEP_BYTES_PER_FACE = 8
+# mixed precision: e_c (4) and the face velocity (4) in single precision
+SWEEP_BYTES_PER_CELL_MIXED = 8 + 8 + 4 + 1 + 8 + 8
+SWEEP_BYTES_PER_FACE_MIXED = 4
 
 
 def workload(name):
@@ -51,9 +56,11 @@ def W_max_face(wl):
     return W.max_abs_face(wl.u, wl.v, wl.w)
 
 
-def sweep_bytes(wl, axis):
+def sweep_bytes(wl, axis, mixed=False):
     nz, ny, nx = wl.shape
     faces = [nz * ny * (nx + 1), nz * (ny + 1) * nx, (nz + 1) * ny * nx][axis]
+    if mixed:
+        return SWEEP_BYTES_PER_CELL_MIXED * wl.ncells + SWEEP_BYTES_PER_FACE_MIXED * faces
     return SWEEP_BYTES_PER_CELL * wl.ncells + SWEEP_BYTES_PER_FACE * faces
 
 
@@ -75,6 +82,51 @@ def recorded_traffic(wl, sweep_n):
     per_axis = rec["bytes_per_launch"]
     tot = sum(per_axis[a] * sweep_n[a] for a in range(wl.ndim))
     return float(tot / sweep_n.sum())
+
+
+def run(pcvof, torch, wl, precision, steps, warmup, scales):
+    """warmup + steps steps of the workload in the given precision: the timed steps
+    bracketed by events on the stream, the sweep kernels timed by the library's events,
+    the relative change of the total volume over the run and the final volume
+    fraction."""
+    spec = pcvof.DomainSpec(shape=wl.shape, h=wl.h, ndim=wl.ndim, bc=wl.bc, cp_l=wl.cp_l,
+                            cp_g=wl.cp_g, rho_l=wl.rho_l, T_gamma=wl.T_gamma, normal=wl.normal,
+                            precision=precision)
+    stream = torch.cuda.current_stream()
+    dom = pcvof.Domain(spec, stream=stream)
+    dom.set_vof(wl.c)
+    dom.set_energy(wl.e)
+    dom.set_velocity(wl.u, wl.v, wl.w)
+    if wl.mdot is not None:
+        dom.set_mass_flux(wl.mdot)
+    hv = wl.h ** wl.ndim
+    vol0 = float(dom.vof().sum()) * hv
+    dom.steps(warmup, wl.dt, scales[:warmup])
+    torch.cuda.synchronize()
+    # sweep kernel durations: HIP events recorded by the library around each sweep
+    # launch, on the stream the kernels run on, over the timed steps
+    dom.set_profiling(["sweep_x", "sweep_y", "sweep_z"][:wl.ndim])
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    t_start.record(stream)
+    dom.steps(steps, wl.dt, scales[warmup:])
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_end)
+    prof = dom.profile()
+    dom.set_profiling(False)
+    sweep_ms = np.array([prof[f"sweep_{a}"]["ms"] for a in "xyz"[:wl.ndim]])
+    sweep_n = np.array([prof[f"sweep_{a}"]["launches"] for a in "xyz"[:wl.ndim]])
+    mixed = precision == "mixed"
+    sweep_b = sum(sweep_bytes(wl, a, mixed) * sweep_n[a] for a in range(wl.ndim))
+    # one untimed step with checksums for the bookkeeping terms of the drift
+    st = dom.step(wl.dt, wl.u_scale(warmup + steps), stats=True)
+    vol1 = st["vol"]
+    c_final = dom.vof().cpu().numpy()
+    del dom
+    torch.cuda.empty_cache()
+    return {"total_ms": total_ms, "sweep_ms": sweep_ms, "sweep_n": sweep_n, "prof": prof,
+            "sweep_bytes": sweep_b, "volume_drift": abs(vol1 - vol0) / vol0, "c_final": c_final}
 
 
 def cpu_baseline(wl, budget_s=15.0, max_side=128):
@@ -114,6 +166,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="leveque128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp64-only", action="store_true", help="skip the mixed-precision run")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="first copy this many MiB device to device, a kernel of known traffic "
                          "for scaling the HBM byte counters of a profiler run")
@@ -135,39 +188,14 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     wl = workload(args.workload)
-    spec = pcvof.DomainSpec(shape=wl.shape, h=wl.h, ndim=wl.ndim, bc=wl.bc, cp_l=wl.cp_l,
-                            cp_g=wl.cp_g, rho_l=wl.rho_l, T_gamma=wl.T_gamma, normal=wl.normal)
-    stream = torch.cuda.current_stream()
-    dom = pcvof.Domain(spec, stream=stream)
-    dom.set_vof(wl.c)
-    dom.set_energy(wl.e)
-    dom.set_velocity(wl.u, wl.v, wl.w)
-    if wl.mdot is not None:
-        dom.set_mass_flux(wl.mdot)
-    vol0 = float(dom.vof().sum()) * wl.h ** wl.ndim
-
     scales = np.array([wl.u_scale(k) for k in range(args.warmup + args.steps)])
-    dom.steps(args.warmup, wl.dt, scales[:args.warmup])
+    r64 = run(pcvof, torch, wl, "fp64", args.steps, args.warmup, scales)
+    c64 = r64.pop("c_final")
     torch.cuda.synchronize()
-    # sweep kernel durations: HIP events recorded by the library around each sweep
-    # launch, on the stream the kernels run on, over the timed steps
-    dom.set_profiling(["sweep_x", "sweep_y", "sweep_z"][:wl.ndim])
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    t_start.record(stream)
-    dom.steps(args.steps, wl.dt, scales[args.warmup:])
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    total_ms = t_start.elapsed_time(t_end)
-    prof = dom.profile()
-    dom.set_profiling(False)
-    sweep_ms = np.array([prof[f"sweep_{a}"]["ms"] for a in "xyz"[:wl.ndim]])
-    sweep_n = np.array([prof[f"sweep_{a}"]["launches"] for a in "xyz"[:wl.ndim]])
-    sweep_bytes_tot = sum(sweep_bytes(wl, a) * sweep_n[a] for a in range(wl.ndim))
+    rmx = run(pcvof, torch, wl, "mixed", args.steps, args.warmup, scales) if not args.fp64_only else None
+    total_ms, sweep_ms, sweep_n, prof = r64["total_ms"], r64["sweep_ms"], r64["sweep_n"], r64["prof"]
     avg_sweep_ms = float(sweep_ms.sum() / sweep_n.sum())
-    achieved = sweep_bytes_tot / (sweep_ms.sum() * 1e-3) / 1e9
-    vol1 = float(dom.vof().sum()) * wl.h ** wl.ndim
-
+    achieved = r64["sweep_bytes"] / (sweep_ms.sum() * 1e-3) / 1e9
     value = wl.ncells * args.steps / (total_ms * 1e-3)
     out = {
         "metric": METRIC,
@@ -193,8 +221,23 @@ def main():
                      "per_axis_ms": [float(t / n) for t, n in zip(sweep_ms, sweep_n)],
                      "bytes_per_cell": SWEEP_BYTES_PER_CELL + SWEEP_BYTES_PER_FACE},
         "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items() if v["launches"]},
-        "volume_drift": abs(vol1 - vol0) / vol0,
+        "volume_drift": r64["volume_drift"],
     }
+    if rmx is not None:
+        cmx = rmx.pop("c_final")
+        dc = np.abs(cmx - c64)
+        mx_value = wl.ncells * args.steps / (rmx["total_ms"] * 1e-3)
+        mx_achieved = rmx["sweep_bytes"] / (rmx["sweep_ms"].sum() * 1e-3) / 1e9
+        out["mixed"] = {
+            "value": mx_value, "unit": "cell-updates/s", "ms_per_step": rmx["total_ms"] / args.steps,
+            "speedup_vs_fp64": mx_value / value, "dtype": "f64 state, f32 geometry and storage",
+            "per_axis_ms": [float(t / n) for t, n in zip(rmx["sweep_ms"], rmx["sweep_n"])],
+            "roofline": {"bound": "hbm", "achieved": mx_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": mx_achieved / HBM_PEAK_GBS,
+                         "bytes_per_cell": SWEEP_BYTES_PER_CELL_MIXED + SWEEP_BYTES_PER_FACE_MIXED},
+            "volume_drift": rmx["volume_drift"],
+            "c_vs_fp64": {"max_abs": float(dc.max()), "l1_rel": float(dc.sum() / np.abs(c64).sum())},
+        }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

@@ -55,6 +55,17 @@ enum {
 enum { PCVOF_MEM_HOST = 0, PCVOF_MEM_DEVICE = 1 };
 enum { PCVOF_BC_PERIODIC = 0, PCVOF_BC_OUTFLOW = 1 };
 enum { PCVOF_NORMAL_YOUNGS = 0, PCVOF_NORMAL_MYC = 1, PCVOF_NORMAL_CC = 2 };
+/* Arithmetic of the advection step. FP64: everything in double precision. MIXED: the
+   face velocities and the frozen energy coefficient e_c are stored in single
+   precision (velocities are converted when set), and the interface normal, plane
+   constant and upwind slab volume of mixed donors are evaluated in single precision,
+   except that the plane constant and slab volume stay in double precision for
+   fractions within 1e-3 of 0 or 1; fluxes are kept within the bounds of an exact slab
+   volume. Volume fractions, energies, flux differences, clipping, step 2 and all
+   checksums stay in double precision, so volume and energy remain conserved to
+   round-off; the fractions differ from the FP64 result at the level of single
+   precision rounding of the geometry. */
+enum { PCVOF_PREC_FP64 = 0, PCVOF_PREC_MIXED = 1 };
 
 typedef struct {
     int ndim;        /* 2 or 3 */
@@ -72,7 +83,7 @@ typedef struct {
     double weno_eps;    /* epsilon of the WENO5 nonlinear weights (1e-6) */
     double cfl_max;     /* largest admissible face CFL number (0.5) */
     int normal;         /* PCVOF_NORMAL_*: interface normal estimator (MYC per section 3.2) */
-    int reserved;       /* must be 0 */
+    int precision;      /* PCVOF_PREC_* */
 } pcvof_params;
 
 /* Checksums of one step (cell volume hv = h^ndim). The change of total volume obeys

@@ -74,7 +74,8 @@ bool params_ok(const pcvof_params* p) {
     if (!(p->eps_mixed >= 0.0 && p->eps_mixed < 0.5)) return false;
     if (!(p->weno_eps > 0.0) || !isfinite(p->weno_eps)) return false;
     if (!(p->cfl_max > 0.0 && p->cfl_max <= 1.0)) return false;
-    if (p->normal < 0 || p->normal > 2 || p->reserved != 0) return false;
+    if (p->normal < 0 || p->normal > 2) return false;
+    if (p->precision != PCVOF_PREC_FP64 && p->precision != PCVOF_PREC_MIXED) return false;
     return true;
 }
 
@@ -114,12 +115,13 @@ Layout make_layout(const pcvof_grid& g, const pcvof_params& p) {
     }
     const size_t mask_words = (size_t)g.nz * g.ny * d.wpr;
     for (int b = 0; b < 2; ++b) L.mask[b] = take(mask_words * sizeof(uint64_t));
-    L.ec = take(n * dbl);
+    const size_t real = p.precision == PCVOF_PREC_MIXED ? sizeof(float) : dbl;  // stored e_c, velocities
+    L.ec = take(n * real);
     L.cc = take(n);
     size_t maxf = 1;
     for (int a = 0; a < 3; ++a) {
         const size_t nf = a < g.ndim ? (size_t)face_count(g, a) : 1;
-        L.vel[a] = take(nf * dbl);
+        L.vel[a] = take(nf * real);
         if (nf > maxf) maxf = nf;
     }
     L.fgeo = take(maxf * dbl);
@@ -164,9 +166,10 @@ struct pcvof_handle {
     double* e(int b) { return (double*)(ws + L.e[b]); }
     uint64_t* mask(int b) { return (uint64_t*)(ws + L.mask[b]); }
     double* fgeo() { return (double*)(ws + L.fgeo); }
-    double* ec() { return (double*)(ws + L.ec); }
+    void* ec() { return (void*)(ws + L.ec); }
     uint8_t* cc() { return (uint8_t*)(ws + L.cc); }
-    double* vel(int a) { return (double*)(ws + L.vel[a]); }
+    void* vel(int a) { return (void*)(ws + L.vel[a]); }
+    bool mixed() const { return p.precision == PCVOF_PREC_MIXED; }
     double* mdot() { return (double*)(ws + L.mdot); }
     double* rec() { return (double*)(ws + L.rec); }
     double* part(int slot) { return (double*)(ws + L.part) + (size_t)slot * pcv::kPartialWidth * L.maxb; }
@@ -355,13 +358,16 @@ int pcvof_set_velocity(pcvof_handle* h, const double* u, const double* v, const 
         if (!src[a]) return fail(PCVOF_ERR_ARG, "velocity component %d is null", a);
     for (int a = 0; a < h->g.ndim; ++a) {
         const long nf = face_count(h->g, a);
-        if (int r = copy_in(h, h->vel(a), src[a], nf, mem)) return r;
+        // the double input is checked where it lands: in the velocity array itself, or
+        // (mixed precision) in the face scratch array before conversion
+        double* vd = h->mixed() ? h->fgeo() : (double*)h->vel(a);
+        if (int r = copy_in(h, vd, src[a], nf, mem)) return r;
         unsigned int f = 0;
         HIP_TRY(hipMemsetAsync(h->flags(), 0, 16, h->stream));
-        HIP_TRY(pcv::launch_check(h->vel(a), nf, 0, h->flags(), h->stream));
-        HIP_TRY(pcv::launch_maxabs(h->vel(a), nf, h->maxbits(), h->stream));
-        if (h->g.bc[a] == PCVOF_BC_PERIODIC)
-            HIP_TRY(pcv::launch_periodic_faces(h->d, a, h->vel(a), h->flags(), h->stream));
+        HIP_TRY(pcv::launch_check(vd, nf, 0, h->flags(), h->stream));
+        HIP_TRY(pcv::launch_maxabs(vd, nf, h->maxbits(), h->stream));
+        if (h->g.bc[a] == PCVOF_BC_PERIODIC) HIP_TRY(pcv::launch_periodic_faces(h->d, a, vd, h->flags(), h->stream));
+        if (h->mixed()) HIP_TRY(pcv::launch_to_float(nf, vd, (float*)h->vel(a), h->stream));
         unsigned long long mb = 0;
         HIP_TRY(hipMemcpyAsync(&f, h->flags(), sizeof f, hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(hipMemcpyAsync(&mb, h->maxbits(), sizeof mb, hipMemcpyDeviceToHost, h->stream));
@@ -427,6 +433,7 @@ int pcvof_sweep(pcvof_handle* h, int axis, double dt, double u_scale) {
     io.cc = h->cc();
     io.ec = h->ec();
     io.first = h->first_pending ? 1 : 0;
+    io.mixed = h->mixed() ? 1 : 0;
     io.vel = h->vel(axis);
     io.kfac = kfac;
     io.fgeo = h->fgeo();

@@ -45,9 +45,10 @@ struct SweepIO {
     int mask_cpw;
     uint64_t* mask_out;        // mixed cells of c_out (cpw kMaskCpwX for axis 0, else kMaskCpw)
     uint8_t* cc;
-    double* ec;
+    void* ec;                  // double, or float when mixed
     int first;                 // also freeze c_c and e_c of the step (the prologue)
-    const double* vel;
+    int mixed;                 // mixed-precision mode (single-precision geometry and storage)
+    const void* vel;           // double, or float when mixed
     double kfac;               // lambda_f = vel_f * kfac
     double* fgeo;              // face array (layout of vel) for donor fluxes beyond the LDS tables
     double* c_out;
@@ -97,5 +98,7 @@ hipError_t launch_geom_slab(int n, const double* m, const double* a, const int* 
                             double* out, hipStream_t s);
 hipError_t launch_geom_normal(int n, const double* c27, int method, double* m, hipStream_t s);
 hipError_t launch_geom_weno5(int n, const double* v, double eps, double* out, hipStream_t s);
+// out[i] = (float)in[i]
+hipError_t launch_to_float(long n, const double* in, float* out, hipStream_t s);
 
 }  // namespace pcv

@@ -58,13 +58,24 @@ __global__ void k_check(const double* __restrict__ x, long n, int check_range, u
     if (f) atomicOr(flags, f);
 }
 
-__global__ void k_maxabs(const double* __restrict__ x, long n, unsigned long long* maxbits) {
+// max |x| over the block first, then one atomic per block
+__global__ void __launch_bounds__(256) k_maxabs(const double* __restrict__ x, long n, unsigned long long* maxbits) {
+    __shared__ double sm[4];
     double m = 0.0;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
         m = fmax(m, fabs(x[i]));
     for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
-    if ((threadIdx.x & 63) == 0 && m > 0.0)
-        atomicMax(maxbits, (unsigned long long)__double_as_longlong(m));
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m = fmax(fmax(sm[0], sm[1]), fmax(sm[2], sm[3]));
+        if (m > 0.0) atomicMax(maxbits, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+__global__ void k_to_float(long n, const double* __restrict__ in, float* __restrict__ out) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        out[i] = (float)in[i];
 }
 
 __global__ void k_periodic_faces(Dom d, int axis, const double* __restrict__ vel, unsigned int* flags) {
@@ -142,9 +153,17 @@ hipError_t launch_check(const double* x, long n, int check_range, unsigned int* 
 
 hipError_t launch_maxabs(const double* x, long n, unsigned long long* maxbits, hipStream_t s) {
     long nb = (n + 255) / 256;
-    if (nb > 4096) nb = 4096;
+    if (nb > 1024) nb = 1024;
     if (nb < 1) nb = 1;
     hipLaunchKernelGGL(k_maxabs, dim3((unsigned)nb), dim3(256), 0, s, x, n, maxbits);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_float(long n, const double* in, float* out, hipStream_t s) {
+    long nb = (n + 255) / 256;
+    if (nb > 8192) nb = 8192;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_to_float, dim3((unsigned)nb), dim3(256), 0, s, n, in, out);
     return hipGetLastError();
 }
 

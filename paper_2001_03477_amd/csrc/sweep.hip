@@ -16,6 +16,7 @@
 #include <type_traits>
 
 #include "common.h"
+#include "geom32.h"
 
 namespace pcv {
 
@@ -28,8 +29,8 @@ struct SweepArgs {
     int mask_cpw;
     uint64_t* mask_out;    // mixed cells of c_out
     uint8_t* cc;       // written by the first sweep of a step, read by the others
-    double* ec;
-    const double* vel;
+    void* ec;          // double, or float in the mixed-precision mode
+    const void* vel;   // double, or float in the mixed-precision mode
     double kfac;
     double* fgeo;          // overflow of the y / z blocks' LDS flux tables, face layout of vel
     double* c_out;
@@ -64,6 +65,56 @@ __device__ double donor_fraction(const Dom& d, const double* __restrict__ c, int
     return slab(nm.m[0], nm.m[1], nm.m[2], alpha, AX, lam);
 }
 
+// Mixed-precision mode: face velocities and e_c are stored in single precision; the
+// donor's normal, plane constant and slab volume are evaluated in single precision,
+// except that the plane constant and the slab volume stay in double precision for
+// fractions within kMixedFp64Band of 0 or 1. The flux is kept inside the bounds of an
+// exact slab volume, [max(0, c_D - (1 - |lam|)), min(|lam|, c_D)]. Fractions,
+// energies, fluxes and all sums stay in double precision.
+constexpr double kMixedFp64Band = 1e-3;
+
+template <bool MP>
+struct Prec {
+    using T = double;
+};
+template <>
+struct Prec<true> {
+    using T = float;
+};
+
+// Stored values in their storage type: prefetched values stay in it until they are
+// used, so that the conversion does not wait for the load.
+template <bool MP>
+__device__ __forceinline__ typename Prec<MP>::T vel_at(const SweepArgs& a, long i) {
+    return ((const typename Prec<MP>::T*)a.vel)[i];
+}
+template <bool MP>
+__device__ __forceinline__ typename Prec<MP>::T ec_at(const SweepArgs& a, long i) {
+    return ((const typename Prec<MP>::T*)a.ec)[i];
+}
+
+template <int AX, bool MP>
+__device__ double donor_flux(const Dom& d, const double* __restrict__ c, int x, int y, int z, double cd,
+                             double lam) {
+    if (!MP) return donor_fraction<AX>(d, c, x, y, z, cd, lam);
+    double c27[27];
+    gather27(d, c, x, y, z, c27);
+    float c27f[27];
+#pragma unroll
+    for (int q = 0; q < 27; ++q) c27f[q] = (float)c27[q];
+    const NormalF nm = normal27_f(c27f, d.normal);
+    const double L = fabs(lam);
+    double F;
+    if (fmin(cd, 1.0 - cd) < kMixedFp64Band) {
+        const double alpha = alpha_of(nm.m[0], nm.m[1], nm.m[2], cd);
+        F = slab(nm.m[0], nm.m[1], nm.m[2], alpha, AX, lam);
+    } else {
+        const float alpha = alpha_of_f(nm.m[0], nm.m[1], nm.m[2], (float)cd, (float)(1.0 - cd));
+        F = (double)slab_f(nm.m[0], nm.m[1], nm.m[2], alpha, AX, (float)lam);
+    }
+    return fmin(fmax(F, fmax(0.0, cd - (1.0 - L))), fmin(L, cd));
+}
+
 // Appends item to a wavefront's work list in LDS where take is true; n is the
 // wavefront-uniform length of the list. Returns the item's position.
 __device__ __forceinline__ unsigned work_append(bool take, unsigned short item, unsigned short* work, unsigned& n) {
@@ -82,6 +133,7 @@ __device__ __forceinline__ int block_linear() {
 // Cell update of a sweep (section 3.3.1 with the split dilatation term, and the
 // conservative energy update of section 3.4.1), the clip into [0,1] keeping T, and the
 // step prologue when first: c_c = [c >= 1/2], e_c = C_p(c_c) T. Returns the new c.
+template <bool MP>
 __device__ __forceinline__ double update_cell(const Dom& d, const SweepArgs& a, long id, double cv, double ev,
                                               double Tv, double lamL, double lamR, double PhiL, double PhiR,
                                               double EL, double ER, uint8_t cc_in, double ec_in,
@@ -90,9 +142,11 @@ __device__ __forceinline__ double update_cell(const Dom& d, const SweepArgs& a, 
     if (a.first) {
         const bool liquid = cv >= 0.5;
         flag = liquid ? 1.0 : 0.0;
-        ecv = (liquid ? d.cp_l : d.cp_g) * Tv;
+        using T = typename Prec<MP>::T;
+        const T ecs = (T)((liquid ? d.cp_l : d.cp_g) * Tv);  // every sweep uses the stored value
+        ecv = (double)ecs;
         a.cc[id] = liquid ? 1 : 0;
-        a.ec[id] = ecv;
+        ((T*)a.ec)[id] = ecs;
     } else {
         flag = (double)cc_in;
         ecv = ec_in;
@@ -151,6 +205,7 @@ constexpr int TCH = 32;
 constexpr int TFCAP = 256;
 static_assert(TCH < 64 && (TCH + 1) * 64 <= 65536, "work items and positions fit 16 bits");
 
+template <bool MP>
 __global__ void __launch_bounds__(XW* XWAVES) k_sweep_x(Dom d, SweepArgs a) {
     __shared__ double s_c[XWAVES][XS];
     __shared__ double s_T[XWAVES][XS];
@@ -209,15 +264,17 @@ __global__ void __launch_bounds__(XW* XWAVES) k_sweep_x(Dom d, SweepArgs a) {
         const int r = it >> 6, l = it & (XW - 1);
         const int y = y0 + r;
         const int xf = x0 + l;
-        const double lam = a.vel[face_row_at(y) + xf] * a.kfac;
+        const double lam = vel_at<MP>(a, face_row_at(y) + xf) * a.kfac;
         if (lam == 0.0) continue;
         const int xd = lam > 0.0 ? xf - 1 : xf;
         const double cd = a.c[row_at(y) + wrap(xd, d.n[0], d.bc[0])];
         if (!mixed(d, cd)) continue;
-        s_F[wave][r][l] = donor_fraction<0>(d, a.c, xd, y, z, cd, lam);
+        s_F[wave][r][l] = donor_flux<0, MP>(d, a.c, xd, y, z, cd, lam);
     }
     __builtin_amdgcn_wave_barrier();
-    double pc0 = 0, pe0 = 0, pc1 = 0, pe1 = 0, pev = 0, pu = 0, pec = 0;
+    using T = typename Prec<MP>::T;
+    double pc0 = 0, pe0 = 0, pc1 = 0, pe1 = 0, pev = 0;
+    T pu = 0, pec = 0;
     uint8_t pcc = 0;
     auto prefetch = [&](int y) {
         const long rb = ((long)z * d.n[1] + y) * d.n[0];
@@ -232,16 +289,17 @@ __global__ void __launch_bounds__(XW* XWAVES) k_sweep_x(Dom d, SweepArgs a) {
             pev = a.e[rb + x];
             if (!a.first) {
                 pcc = a.cc[rb + x];
-                pec = a.ec[rb + x];
+                pec = ec_at<MP>(a, rb + x);
             }
         }
-        if (face) pu = a.vel[fr + x];
+        if (face) pu = vel_at<MP>(a, fr + x);
     };
     if (nrows > 0) prefetch(y0);
     for (int r = 0; r < nrows; ++r) {
         const int y = y0 + r;
         const long rowbase = row_at(y);
-        const double c0 = pc0, e0 = pe0, c1 = pc1, e1 = pe1, ev_own = pev, u = pu, ec_own = pec;
+        const double c0 = pc0, e0 = pe0, c1 = pc1, e1 = pe1, ev_own = pev;
+        const double u = (double)pu, ec_own = (double)pec;
         const uint8_t cc_own = pcc;
         if (r + 1 < nrows) prefetch(y + 1);
         s_c[wave][lane] = c0;
@@ -272,7 +330,7 @@ __global__ void __launch_bounds__(XW* XWAVES) k_sweep_x(Dom d, SweepArgs a) {
         const double lamR = __shfl_down(lam, 1, 64);
         bool mx = false;
         if (own) {
-            const double cn = update_cell(d, a, rowbase + x, s_c[wave][lane + XH], ev_own, s_T[wave][lane + XH],
+            const double cn = update_cell<MP>(d, a, rowbase + x, s_c[wave][lane + XH], ev_own, s_T[wave][lane + XH],
                                           lam, lamR, Phi, PhiR, E, ER, cc_own, ec_own, acc);
             mx = mixed(d, cn);
             if (d.bc[0] == 1) {
@@ -298,7 +356,7 @@ __global__ void __launch_bounds__(XW* XWAVES) k_sweep_x(Dom d, SweepArgs a) {
 // wavefront, so every load is coalesced) and marches over a chunk of it, keeping the
 // fractions, energies and temperatures of cells f-3 .. f+2 in registers; each face
 // flux is computed once and used by both neighbours.
-template <int AX>
+template <int AX, bool MP>
 __global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) {
     constexpr int TA = AX == 1 ? 2 : 1;  // the transverse axis other than x
     __shared__ unsigned short s_idx[4][TCH + 1][64];     // work position of each candidate face
@@ -356,13 +414,13 @@ __global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) 
         const long bw = AX == 1 ? (long)t * plane + xw : (long)t * d.n[0] + xw;
         const long fw = AX == 1 ? (long)t * (d.n[1] + 1) * d.n[0] + xw : (long)t * d.n[0] + xw;
         const int f = s0 + fl;
-        const double lam = a.vel[fw + (long)f * fstride] * a.kfac;
+        const double lam = vel_at<MP>(a, fw + (long)f * fstride) * a.kfac;
         if (lam == 0.0) continue;
         const int sd = lam > 0.0 ? f - 1 : f;
         const double cd = a.c[bw + (long)wrap(sd, ns, d.bc[AX]) * stride];
         if (!mixed(d, cd)) continue;
-        const double F = AX == 1 ? donor_fraction<1>(d, a.c, xw, sd, t, cd, lam)
-                                 : donor_fraction<2>(d, a.c, xw, t, sd, cd, lam);
+        const double F = AX == 1 ? donor_flux<1, MP>(d, a.c, xw, sd, t, cd, lam)
+                                 : donor_flux<2, MP>(d, a.c, xw, t, sd, cd, lam);
         if (i < TFCAP) s_F[tr][i] = F;
         else a.fgeo[fw + (long)f * fstride] = F;
     }
@@ -378,7 +436,7 @@ __global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) 
     // is a compile-time register.
     constexpr int R = 8;
     double cr[R], er[R], Tw[R];
-    double vr[4], ecr[4];
+    typename Prec<MP>::T vr[4], ecr[4];  // storage type until used
     uint8_t ccr[4];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
@@ -398,11 +456,11 @@ __global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) 
         ccr[j] = 0;
         const int f = s0 + j;
         if (ok && f <= s1) {
-            vr[j] = a.vel[fbase + (long)f * fstride];
+            vr[j] = vel_at<MP>(a, fbase + (long)f * fstride);
             // cell f-1 is updated at face f; the first face updates nothing
             if (!a.first && j > 0) {
                 ccr[j] = a.cc[base + (long)(f - 1) * stride];
-                ecr[j] = a.ec[base + (long)(f - 1) * stride];
+                ecr[j] = ec_at<MP>(a, base + (long)(f - 1) * stride);
             }
         }
     }
@@ -416,7 +474,7 @@ __global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) 
                       J5 = (K + 5) % R;
         constexpr int V = K % 4;
         Tw[J5] = ok ? er[J5] / cp_of(d, cr[J5]) : 0.0;
-        const double lam = ok ? vr[V] * a.kfac : 0.0;
+        const double lam = ok ? (double)vr[V] * a.kfac : 0.0;
         double Phi = 0.0, E = 0.0;
         if (lam != 0.0) {
             const double cd = lam > 0.0 ? cr[J2] : cr[J3];
@@ -434,7 +492,8 @@ __global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) 
             const int cell = f - 1;
             const long id = base + (long)cell * stride;
             const double cn =
-                update_cell(d, a, id, cr[J2], er[J2], Tw[J2], lamP, lam, PhiP, Phi, EP, E, ccr[V], ecr[V], acc);
+                update_cell<MP>(d, a, id, cr[J2], er[J2], Tw[J2], lamP, lam, PhiP, Phi, EP, E, ccr[V],
+                                (double)ecr[V], acc);
             mx = mixed(d, cn);
             if (d.bc[AX] == 1) {
                 if (cell == 0) {
@@ -465,10 +524,10 @@ __global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) 
                 er[J0] = a.e[id];
             }
             if (f + 4 <= s1) {
-                vr[V] = a.vel[fbase + (long)(f + 4) * fstride];
+                vr[V] = vel_at<MP>(a, fbase + (long)(f + 4) * fstride);
                 if (!a.first) {
                     ccr[V] = a.cc[base + (long)(f + 3) * stride];
-                    ecr[V] = a.ec[base + (long)(f + 3) * stride];
+                    ecr[V] = ec_at<MP>(a, base + (long)(f + 3) * stride);
                 }
             }
         }
@@ -636,17 +695,25 @@ hipError_t launch_classify(const Dom& d, const double* c, uint64_t* mask, hipStr
     return hipGetLastError();
 }
 
+template <bool MP>
+void launch_sweep_kernel(const Dom& d, int axis, const Launch& L, int chunk, const SweepArgs& a, hipStream_t s) {
+    if (axis == 0)
+        hipLaunchKernelGGL(k_sweep_x<MP>, L.grid, L.block, 0, s, d, a);
+    else if (axis == 1)
+        hipLaunchKernelGGL((k_sweep_t<1, MP>), L.grid, L.block, 0, s, d, a, chunk);
+    else
+        hipLaunchKernelGGL((k_sweep_t<2, MP>), L.grid, L.block, 0, s, d, a, chunk);
+}
+
 hipError_t launch_sweep(const Dom& d, int axis, const SweepIO& io, hipStream_t s) {
     int chunk = 0;
     const Launch L = sweep_launch(d, axis, &chunk);
     SweepArgs a{io.c,   io.e,    io.mask, io.mask_cpw, io.mask_out, io.cc,   io.ec,          io.vel,
                 io.kfac, io.fgeo, io.c_out, io.e_out,   io.part,     io.part_stride, io.first};
-    if (axis == 0)
-        hipLaunchKernelGGL(k_sweep_x, L.grid, L.block, 0, s, d, a);
-    else if (axis == 1)
-        hipLaunchKernelGGL(k_sweep_t<1>, L.grid, L.block, 0, s, d, a, chunk);
+    if (io.mixed)
+        launch_sweep_kernel<true>(d, axis, L, chunk, a, s);
     else
-        hipLaunchKernelGGL(k_sweep_t<2>, L.grid, L.block, 0, s, d, a, chunk);
+        launch_sweep_kernel<false>(d, axis, L, chunk, a, s);
     *io.nblocks = L.nblocks;
     return hipGetLastError();
 }

@@ -49,7 +49,7 @@ class Grid(C.Structure):
 class Params(C.Structure):
     _fields_ = [("cp_l", C.c_double), ("cp_g", C.c_double), ("rho_l", C.c_double),
                 ("T_gamma", C.c_double), ("eps_mixed", C.c_double), ("weno_eps", C.c_double),
-                ("cfl_max", C.c_double), ("normal", C.c_int), ("reserved", C.c_int)]
+                ("cfl_max", C.c_double), ("normal", C.c_int), ("precision", C.c_int)]
 
 
 STAT_NAMES = ("vol", "energy", "vol_clip", "energy_clip", "vol_phase", "energy_phase",
@@ -129,6 +129,9 @@ def _stream_ptr(stream=None) -> int:
     return int(s.cuda_stream)
 
 
+PRECISIONS = {"fp64": 0, "mixed": 1}
+
+
 @dataclass
 class DomainSpec:
     shape: tuple              # (nz, ny, nx); nz == 1 for 2D
@@ -143,6 +146,7 @@ class DomainSpec:
     weno_eps: float = 1e-6
     cfl_max: float = 0.5
     normal: int = NORMAL_MYC
+    precision: str = "fp64"   # "fp64" or "mixed"
 
     def grid(self) -> Grid:
         nz, ny, nx = self.shape
@@ -153,7 +157,7 @@ class DomainSpec:
 
     def params(self) -> Params:
         return Params(self.cp_l, self.cp_g, self.rho_l, self.T_gamma, self.eps_mixed,
-                      self.weno_eps, self.cfl_max, int(self.normal), 0)
+                      self.weno_eps, self.cfl_max, int(self.normal), PRECISIONS[self.precision])
 
 
 def workspace_bytes(spec: DomainSpec) -> int:

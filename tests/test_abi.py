@@ -48,6 +48,14 @@ def test_workspace_bytes_and_validation():
         pcvof.workspace_bytes(_spec(bc=(0, 2, 0)))
     n2 = pcvof.workspace_bytes(_spec(shape=(1, 33, 65), ndim=2))
     assert n2 > 33 * 65 * 8
+    # mixed precision stores e_c and the face velocities in single precision
+    nm = pcvof.workspace_bytes(_spec(precision="mixed"))
+    faces = 8 * 12 * 21 + 8 * 13 * 20 + 9 * 12 * 20
+    assert n - nm >= 4 * (cells + faces) - 4 * 256  # buffers are 256-byte aligned
+    spec = _spec()
+    p = spec.params()
+    p.precision = 2
+    assert pcvof.lib().pcvof_workspace_bytes(C.byref(spec.grid()), C.byref(p)) == 0
 
 
 def test_create_checks_workspace_without_touching_the_device():
