@@ -202,11 +202,11 @@ constexpr int XS = XW + 5;
 // wavefront keeps in LDS (fluxes beyond it go to a face array in global memory,
 // written and read back by the same wavefront).
 constexpr int TCH = 32;
-constexpr int TFCAP = 256;
+constexpr int TFCAP = 192;
 static_assert(TCH < 64 && (TCH + 1) * 64 <= 65536, "work items and positions fit 16 bits");
 
 template <bool MP>
-__global__ void __launch_bounds__(XW* XWAVES) k_sweep_x(Dom d, SweepArgs a) {
+__device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a) {
     __shared__ double s_c[XWAVES][XS];
     __shared__ double s_T[XWAVES][XS];
     __shared__ double s_F[XWAVES][XRPW][XW];                 // liquid flux of mixed donors
@@ -357,7 +357,7 @@ __global__ void __launch_bounds__(XW* XWAVES) k_sweep_x(Dom d, SweepArgs a) {
 // fractions, energies and temperatures of cells f-3 .. f+2 in registers; each face
 // flux is computed once and used by both neighbours.
 template <int AX, bool MP>
-__global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) {
+__device__ __forceinline__ void sweep_t_body(const Dom& d, const SweepArgs& a, int chunk) {
     constexpr int TA = AX == 1 ? 2 : 1;  // the transverse axis other than x
     __shared__ unsigned short s_idx[4][TCH + 1][64];     // work position of each candidate face
     __shared__ unsigned short s_work[4][(TCH + 1) * 64];  // candidate faces (face offset:lane)
@@ -553,6 +553,24 @@ __global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) 
     block_sum8<4>(acc, a.part + block_linear(), a.part_stride);
 }
 
+// Kernel entry points. The mixed-precision bodies fit fewer registers per lane, so
+// their launches ask for five (x) and four (y, z) wavefronts per SIMD; the double
+// precision bodies would spill at those limits and keep the compiler's allocation.
+__global__ void __launch_bounds__(XW* XWAVES) k_sweep_x(Dom d, SweepArgs a) { sweep_x_body<false>(d, a); }
+__global__ void __launch_bounds__(XW* XWAVES) __attribute__((amdgpu_waves_per_eu(5, 8)))
+k_sweep_x_mixed(Dom d, SweepArgs a) {
+    sweep_x_body<true>(d, a);
+}
+template <int AX>
+__global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) {
+    sweep_t_body<AX, false>(d, a, chunk);
+}
+template <int AX>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_sweep_t_mixed(Dom d, SweepArgs a, int chunk) {
+    sweep_t_body<AX, true>(d, a, chunk);
+}
+
 // Step 2, first pass (section 3.3.2), over every mixed cell of c~ with a non-zero mass
 // flux: the reconstruction and the moved plane constant, rec = (m, alpha~, alpha*)
 // with alpha* = alpha~ + |m|_2 Delta d and Delta d = -(m''/rho_l) dt / h.
@@ -698,11 +716,11 @@ hipError_t launch_classify(const Dom& d, const double* c, uint64_t* mask, hipStr
 template <bool MP>
 void launch_sweep_kernel(const Dom& d, int axis, const Launch& L, int chunk, const SweepArgs& a, hipStream_t s) {
     if (axis == 0)
-        hipLaunchKernelGGL(k_sweep_x<MP>, L.grid, L.block, 0, s, d, a);
+        hipLaunchKernelGGL(MP ? k_sweep_x_mixed : k_sweep_x, L.grid, L.block, 0, s, d, a);
     else if (axis == 1)
-        hipLaunchKernelGGL((k_sweep_t<1, MP>), L.grid, L.block, 0, s, d, a, chunk);
+        hipLaunchKernelGGL(MP ? k_sweep_t_mixed<1> : k_sweep_t<1>, L.grid, L.block, 0, s, d, a, chunk);
     else
-        hipLaunchKernelGGL((k_sweep_t<2, MP>), L.grid, L.block, 0, s, d, a, chunk);
+        hipLaunchKernelGGL(MP ? k_sweep_t_mixed<2> : k_sweep_t<2>, L.grid, L.block, 0, s, d, a, chunk);
 }
 
 hipError_t launch_sweep(const Dom& d, int axis, const SweepIO& io, hipStream_t s) {
