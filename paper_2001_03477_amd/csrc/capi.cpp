@@ -157,6 +157,7 @@ struct pcvof_handle {
     double step_cfl;
     // kernel timing
     int prof_mask;           // kernel classes timed (bit k = class k)
+    bool batch_view;         // owned by a batch (destroyed with it)
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending[PCVOF_PROF_CLASSES];
     std::vector<hipEvent_t> prof_pool;
     double prof_ms[PCVOF_PROF_CLASSES];
@@ -223,6 +224,28 @@ int prof_collect(pcvof_handle* h) {
     return PCVOF_OK;
 }
 
+// Step checksums from the column sums of the stage partials (cs, kSlots x 8 doubles).
+void fill_stats(const pcvof_handle* h, const double* cs, pcvof_stats* stats) {
+    constexpr int W = pcv::kPartialWidth;
+    const double hv = h->g.ndim == 3 ? h->g.h * h->g.h * h->g.h : h->g.h * h->g.h;
+    // sweeps: clip_v, clip_e, bnd_v, bnd_e, src_v, src_e, tot_v, tot_e; step 2: dc, de, .., tot
+    double q[6] = {0, 0, 0, 0, 0, 0};
+    for (int sl = 0; sl < 3; ++sl)
+        if (h->nb[sl])
+            for (int k = 0; k < 6; ++k) q[k] += cs[sl * W + k];
+    stats->vol = cs[h->last_slot * W + 6] * hv;
+    stats->energy = cs[h->last_slot * W + 7] * hv;
+    stats->vol_clip = q[0] * hv;
+    stats->energy_clip = q[1] * hv;
+    stats->vol_bnd_out = q[2] * hv;
+    stats->energy_bnd_out = q[3] * hv;
+    stats->vol_src = q[4] * hv;
+    stats->energy_src = q[5] * hv;
+    stats->vol_phase = h->nb[3] ? cs[3 * W + 0] * hv : 0.0;
+    stats->energy_phase = h->nb[3] ? cs[3 * W + 1] * hv : 0.0;
+    stats->max_cfl = h->step_cfl;
+}
+
 int check_handle(pcvof_handle* h) {
     if (!h || !h->ws) return fail(PCVOF_ERR_ARG, "null or destroyed handle");
     return PCVOF_OK;
@@ -284,6 +307,7 @@ int pcvof_create(const pcvof_grid* grid, const pcvof_params* params, void* d_wor
     h->stream = (hipStream_t)hip_stream;
     h->cur = 0;
     h->mask_cpw = pcv::kMaskCpw;
+    h->batch_view = false;
     h->has_vof = h->has_energy = h->has_vel = h->has_mdot = false;
     h->umax[0] = h->umax[1] = h->umax[2] = 0.0;
     h->step = 0;
@@ -298,6 +322,7 @@ int pcvof_create(const pcvof_grid* grid, const pcvof_params* params, void* d_wor
 }
 
 int pcvof_destroy(pcvof_handle* h) {
+    if (h && h->batch_view) return fail(PCVOF_ERR_STATE, "a batch domain is destroyed with its batch");
     if (!h) return fail(PCVOF_ERR_ARG, "null handle");
     if (h->ws && h->prof_mask) hipStreamSynchronize(h->stream);
     for (int k = 0; k < PCVOF_PROF_CLASSES; ++k)
@@ -489,32 +514,15 @@ int pcvof_end_step(pcvof_handle* h, pcvof_stats* stats) {
     h->in_step = false;
     h->step++;
     if (h->last_slot < 0) return fail(PCVOF_ERR_STATE, "empty step");
-    const double hv = h->g.ndim == 3 ? h->g.h * h->g.h * h->g.h : h->g.h * h->g.h;
     // column sums of the stage partials on the device, every step
     const int ps = prof_begin(h, PCVOF_PROF_CHECKSUM);
     HIP_TRY(pcv::launch_colsum(h->part(0), h->L.maxb, h->nb, h->colsum(), h->stream));
     prof_end(h, PCVOF_PROF_CHECKSUM, ps);
     if (stats) {
-        constexpr int W = pcv::kPartialWidth;
-        double cs[pcv::kSlots * W];
+        double cs[pcv::kSlots * pcv::kPartialWidth];
         HIP_TRY(hipMemcpyAsync(cs, h->colsum(), sizeof cs, hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
-        // sweeps: clip_v, clip_e, bnd_v, bnd_e, src_v, src_e, tot_v, tot_e; step 2: dc, de, .., tot
-        double q[6] = {0, 0, 0, 0, 0, 0};
-        for (int sl = 0; sl < 3; ++sl)
-            if (h->nb[sl])
-                for (int k = 0; k < 6; ++k) q[k] += cs[sl * W + k];
-        stats->vol = cs[h->last_slot * W + 6] * hv;
-        stats->energy = cs[h->last_slot * W + 7] * hv;
-        stats->vol_clip = q[0] * hv;
-        stats->energy_clip = q[1] * hv;
-        stats->vol_bnd_out = q[2] * hv;
-        stats->energy_bnd_out = q[3] * hv;
-        stats->vol_src = q[4] * hv;
-        stats->energy_src = q[5] * hv;
-        stats->vol_phase = h->nb[3] ? cs[3 * W + 0] * hv : 0.0;
-        stats->energy_phase = h->nb[3] ? cs[3 * W + 1] * hv : 0.0;
-        stats->max_cfl = h->step_cfl;
+        fill_stats(h, cs, stats);
     }
     return PCVOF_OK;
 }
@@ -619,6 +627,497 @@ int pcvof_set_step(pcvof_handle* h, long step) {
     if (h->in_step) return fail(PCVOF_ERR_STATE, "set_step inside a step");
     h->step = step;
     return PCVOF_OK;
+}
+
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------- batches
+
+namespace {
+
+constexpr int kArgSlots = 8;      // cached argument tables (one per recurring step state)
+constexpr int kBatchGrid = 1024;  // default blocks of a batched launch (resident on 256 CUs)
+
+struct BatchSlot {
+    bool used = false;
+    std::vector<long> key;        // step rotation, per domain: state buffer and mask layout
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+struct BatchLayout {
+    std::vector<size_t> dom_off, dom_bytes;
+    size_t doms, tiles[3], args, cs, total;
+    int max_tiles[3];
+};
+
+size_t batch_args_slot_bytes(int nd) { return align_up(3 * (size_t)nd * pcv::sweep_args_bytes()); }
+
+bool batch_layout(int nd, const pcvof_grid* g, const pcvof_params* p, BatchLayout* L) {
+    size_t off = 0;
+    L->dom_off.resize(nd);
+    L->dom_bytes.resize(nd);
+    for (int a = 0; a < 3; ++a) L->max_tiles[a] = 0;
+    for (int i = 0; i < nd; ++i) {
+        if (!grid_ok(&g[i]) || !params_ok(&p[i])) return false;
+        if (g[i].ndim != g[0].ndim || p[i].precision != p[0].precision) return false;
+        L->dom_bytes[i] = make_layout(g[i], p[i]).total;
+        L->dom_off[i] = off;
+        off = align_up(off + L->dom_bytes[i]);
+        const pcv::Dom d = make_dom(g[i], p[i]);
+        for (int a = 0; a < g[i].ndim; ++a)
+            L->max_tiles[a] += pcv::sweep_tiles(d, a, a == 0 ? 0 : pcv::min_chunk(), 0, nullptr);
+    }
+    L->doms = off;
+    off = align_up(off + (size_t)nd * sizeof(pcv::Dom));
+    for (int a = 0; a < 3; ++a) {
+        L->tiles[a] = off;
+        off = align_up(off + (size_t)L->max_tiles[a] * sizeof(pcv::BatchTile));
+    }
+    L->args = off;
+    off += kArgSlots * batch_args_slot_bytes(nd);
+    L->cs = off;
+    off = align_up(off + (size_t)kArgSlots * nd * sizeof(pcv::ColsumArgs));
+    L->total = off;
+    return true;
+}
+
+}  // namespace
+
+struct pcvof_batch {
+    int nd = 0;
+    int ndim = 3;
+    int mixed = 0;
+    BatchLayout L;
+    char* ws = nullptr;
+    hipStream_t stream = nullptr;
+    hipStream_t capture = nullptr;  // private stream the graphs are recorded on (never runs work)
+    std::vector<pcvof_handle*> dom;
+    int chunk[3] = {0, 0, 0};     // y / z column chunk (0: each domain's own default)
+    int grid[3] = {kBatchGrid, kBatchGrid, kBatchGrid};
+    int ntiles[3] = {0, 0, 0};
+    std::vector<int> dom_tiles[3];  // tiles per domain and axis (rows of its partial table)
+    BatchSlot slot[kArgSlots];
+    int next_victim = 0;
+    std::vector<double> dt;         // time steps the cached tables were built for
+    long step = 0;
+
+    pcv::Dom* doms() { return (pcv::Dom*)(ws + L.doms); }
+    pcv::BatchTile* tiles(int a) { return (pcv::BatchTile*)(ws + L.tiles[a]); }
+    char* args(int sl, int s) {
+        return ws + L.args + sl * batch_args_slot_bytes(nd) + (size_t)s * nd * pcv::sweep_args_bytes();
+    }
+    pcv::ColsumArgs* cs(int sl) { return (pcv::ColsumArgs*)(ws + L.cs) + (size_t)sl * nd; }
+};
+
+namespace {
+
+int batch_check(pcvof_batch* b) {
+    if (!b || !b->ws) return fail(PCVOF_ERR_ARG, "null or destroyed batch");
+    return PCVOF_OK;
+}
+
+void batch_drop_slot(BatchSlot& sl) {
+    if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
+    if (sl.graph) (void)hipGraphDestroy(sl.graph);
+    sl = BatchSlot();
+}
+
+// Drops every cached argument table and graph (waits for the stream first).
+int batch_invalidate(pcvof_batch* b) {
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    for (auto& sl : b->slot) batch_drop_slot(sl);
+    return PCVOF_OK;
+}
+
+// (Re)builds and uploads the tile tables of every axis with the current chunks.
+int batch_build_tiles(pcvof_batch* b) {
+    for (int a = 0; a < b->ndim; ++a) {
+        std::vector<pcv::BatchTile> t;
+        b->dom_tiles[a].assign(b->nd, 0);
+        for (int i = 0; i < b->nd; ++i) {
+            const int ch = a == 0 ? 0 : b->chunk[a];
+            const int n = pcv::sweep_tiles(b->dom[i]->d, a, ch, i, nullptr);
+            const size_t at = t.size();
+            t.resize(at + n);
+            pcv::sweep_tiles(b->dom[i]->d, a, ch, i, t.data() + at);
+            b->dom_tiles[a][i] = n;
+        }
+        if ((int)t.size() > b->L.max_tiles[a]) return fail(PCVOF_ERR_WORKSPACE, "tile table overflow");
+        b->ntiles[a] = (int)t.size();
+        HIP_TRY(hipMemcpy(b->tiles(a), t.data(), t.size() * sizeof(pcv::BatchTile), hipMemcpyHostToDevice));
+    }
+    return PCVOF_OK;
+}
+
+// The sweep arguments of domain i for sweep s of a step starting in state (cur, cpw).
+pcv::SweepIO batch_sweep_io(pcvof_batch* b, int i, int s, int axis, int cur, int cpw, double dt) {
+    pcvof_handle* h = b->dom[i];
+    pcv::SweepIO io;
+    io.c = h->c(cur);
+    io.e = h->e(cur);
+    io.mask = h->mask(cur);
+    io.mask_cpw = cpw;
+    io.mask_out = h->mask(1 - cur);
+    io.cc = h->cc();
+    io.ec = h->ec();
+    io.first = s == 0 ? 1 : 0;
+    io.mixed = h->mixed() ? 1 : 0;
+    io.vel = h->vel(axis);
+    io.kfac = dt / h->g.h;
+    io.fgeo = h->fgeo();
+    io.c_out = h->c(1 - cur);
+    io.e_out = h->e(1 - cur);
+    io.part = h->part(s);
+    io.part_stride = h->L.maxb;
+    io.nblocks = nullptr;
+    return io;
+}
+
+// The cached argument slot for the coming step (built and uploaded on first use).
+int batch_slot_for_step(pcvof_batch* b, const double* dt, int* out) {
+    std::vector<long> key;
+    key.push_back(b->step % b->ndim);
+    for (auto* h : b->dom) {
+        key.push_back(h->cur);
+        key.push_back(h->mask_cpw);
+        key.push_back(h->has_mdot ? 1 : 0);
+    }
+    for (int k = 0; k < kArgSlots; ++k)
+        if (b->slot[k].used && b->slot[k].key == key) {
+            *out = k;
+            return PCVOF_OK;
+        }
+    int k = -1;
+    for (int j = 0; j < kArgSlots && k < 0; ++j)
+        if (!b->slot[j].used) k = j;
+    if (k < 0) {  // evict: the slot may still be read by enqueued work
+        k = b->next_victim;
+        b->next_victim = (b->next_victim + 1) % kArgSlots;
+        HIP_TRY(hipStreamSynchronize(b->stream));
+        batch_drop_slot(b->slot[k]);
+    }
+    const size_t ab = pcv::sweep_args_bytes();
+    std::vector<char> args(3 * (size_t)b->nd * ab);
+    std::vector<pcv::ColsumArgs> cs(b->nd);
+    for (int i = 0; i < b->nd; ++i) {
+        pcvof_handle* h = b->dom[i];
+        int cur = h->cur, cpw = h->mask_cpw;
+        pcv::ColsumArgs c{h->part(0), h->L.maxb, {0, 0, 0, 0}, h->colsum()};
+        for (int s = 0; s < b->ndim; ++s) {
+            const int axis = (int)((b->step + s) % b->ndim);
+            const pcv::SweepIO io = batch_sweep_io(b, i, s, axis, cur, cpw, dt[i]);
+            pcv::sweep_args_pack(io, args.data() + ((size_t)s * b->nd + i) * ab);
+            c.nb[s] = b->dom_tiles[axis][i];
+            cur = 1 - cur;
+            cpw = axis == 0 ? pcv::kMaskCpwX : pcv::kMaskCpw;
+        }
+        if (h->has_mdot) c.nb[3] = pcv::cell_launch(h->d).nblocks;
+        cs[i] = c;
+    }
+    HIP_TRY(hipMemcpy(b->args(k, 0), args.data(), args.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b->cs(k), cs.data(), cs.size() * sizeof(pcv::ColsumArgs), hipMemcpyHostToDevice));
+    b->slot[k].used = true;
+    b->slot[k].key = key;
+    *out = k;
+    return PCVOF_OK;
+}
+
+// The launches of one batched step with argument slot k (sweeps, step 2 of the domains
+// with a mass flux, checksums) on stream s.
+int batch_enqueue(pcvof_batch* b, int k, const double* dt, hipStream_t s_) {
+    for (int s = 0; s < b->ndim; ++s) {
+        const int axis = (int)((b->step + s) % b->ndim);
+        const int grid = b->grid[axis] < b->ntiles[axis] ? b->grid[axis] : b->ntiles[axis];
+        HIP_TRY(pcv::launch_sweep_batch(axis, b->mixed, b->doms(), b->args(k, s), b->tiles(axis), b->ntiles[axis],
+                                        grid > 0 ? grid : 1, s_));
+    }
+    for (int i = 0; i < b->nd; ++i) {
+        pcvof_handle* h = b->dom[i];
+        if (!h->has_mdot) continue;
+        const int cur = b->ndim % 2 ? 1 - h->cur : h->cur;  // state after the sweeps
+        pcv::PhaseIO io;
+        io.c = h->c(cur);
+        io.e = h->e(cur);
+        io.mask_out = h->mask(1 - cur);
+        io.mdot = h->mdot();
+        io.dt = dt[i];
+        io.h = h->g.h;
+        io.rec = h->rec();
+        io.c_out = h->c(1 - cur);
+        io.e_out = h->e(1 - cur);
+        io.part = h->part(3);
+        io.part_stride = h->L.maxb;
+        int nb = 0;
+        io.nblocks = &nb;
+        HIP_TRY(pcv::launch_phase(h->d, io, s_));
+    }
+    HIP_TRY(pcv::launch_colsum_batch(b->nd, b->cs(k), s_));
+    return PCVOF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pcvof_batch_workspace_bytes(int nd, const pcvof_grid* grids, const pcvof_params* params) {
+    if (nd < 1 || !grids || !params) return 0;
+    BatchLayout L;
+    if (!batch_layout(nd, grids, params, &L)) return 0;
+    return L.total;
+}
+
+int pcvof_batch_create(int nd, const pcvof_grid* grids, const pcvof_params* params, void* d_workspace,
+                       size_t workspace_bytes, void* hip_stream, pcvof_batch** out) {
+    if (!out) return fail(PCVOF_ERR_ARG, "out is null");
+    *out = nullptr;
+    if (nd < 1 || !grids || !params) return fail(PCVOF_ERR_ARG, "need nd >= 1 grids and params");
+    BatchLayout L;
+    if (!batch_layout(nd, grids, params, &L))
+        return fail(PCVOF_ERR_ARG, "invalid grid or params, or domains differ in ndim or precision");
+    if (!d_workspace) return fail(PCVOF_ERR_WORKSPACE, "workspace is null");
+    if (((uintptr_t)d_workspace) % kAlign) return fail(PCVOF_ERR_WORKSPACE, "workspace not 256-byte aligned");
+    if (workspace_bytes < L.total)
+        return fail(PCVOF_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, L.total);
+    pcvof_batch* b = new (std::nothrow) pcvof_batch();
+    if (!b) return fail(PCVOF_ERR_ARG, "out of host memory");
+    b->nd = nd;
+    b->ndim = grids[0].ndim;
+    b->mixed = params[0].precision == PCVOF_PREC_MIXED ? 1 : 0;
+    b->L = L;
+    b->ws = (char*)d_workspace;
+    b->stream = (hipStream_t)hip_stream;
+    std::vector<pcv::Dom> doms(nd);
+    for (int i = 0; i < nd; ++i) {
+        pcvof_handle* h = nullptr;
+        if (int r = pcvof_create(&grids[i], &params[i], b->ws + L.dom_off[i], L.dom_bytes[i], hip_stream, &h)) {
+            for (auto* v : b->dom) {
+                v->batch_view = false;
+                pcvof_destroy(v);
+            }
+            delete b;
+            return r;
+        }
+        h->batch_view = true;
+        b->dom.push_back(h);
+        doms[i] = h->d;
+    }
+    int r = PCVOF_OK;
+    hipError_t e = hipMemcpy(b->doms(), doms.data(), nd * sizeof(pcv::Dom), hipMemcpyHostToDevice);
+    if (e != hipSuccess) r = fail(PCVOF_ERR_HIP, "hipMemcpy failed: %s", hipGetErrorString(e));
+    if (!r) r = batch_build_tiles(b);
+    if (r) {
+        pcvof_batch_destroy(b);
+        return r;
+    }
+    *out = b;
+    return PCVOF_OK;
+}
+
+int pcvof_batch_destroy(pcvof_batch* b) {
+    if (!b) return PCVOF_OK;
+    if (b->stream || b->ws) (void)hipStreamSynchronize(b->stream);
+    for (auto& sl : b->slot) batch_drop_slot(sl);
+    if (b->capture) (void)hipStreamDestroy(b->capture);
+    for (auto* h : b->dom) {
+        h->batch_view = false;
+        pcvof_destroy(h);
+    }
+    b->ws = nullptr;
+    delete b;
+    return PCVOF_OK;
+}
+
+int pcvof_batch_domain(pcvof_batch* b, int i, pcvof_handle** view) {
+    if (int r = batch_check(b)) return r;
+    if (!view) return fail(PCVOF_ERR_ARG, "view is null");
+    if (i < 0 || i >= b->nd) return fail(PCVOF_ERR_ARG, "domain %d out of range", i);
+    *view = b->dom[i];
+    return PCVOF_OK;
+}
+
+int pcvof_batch_advect_step(pcvof_batch* b, const double* dt, int use_graph, pcvof_stats* stats) {
+    if (int r = batch_check(b)) return r;
+    if (!dt) return fail(PCVOF_ERR_ARG, "dt is null");
+    bool any_mdot = false;
+    for (int i = 0; i < b->nd; ++i) {
+        pcvof_handle* h = b->dom[i];
+        if (!h->has_vof || !h->has_energy || !h->has_vel)
+            return fail(PCVOF_ERR_STATE, "domain %d: fraction, energy and velocity must be set", i);
+        if (h->in_step) return fail(PCVOF_ERR_STATE, "domain %d is inside a staged step", i);
+        if (h->step != b->step) return fail(PCVOF_ERR_STATE, "domain %d was stepped on its own", i);
+        if (!isfinite(dt[i]) || !(dt[i] >= 0.0)) return fail(PCVOF_ERR_ARG, "domain %d: bad dt", i);
+        for (int a = 0; a < h->g.ndim; ++a)
+            if (h->umax[a] * dt[i] / h->g.h > h->p.cfl_max)
+                return fail(PCVOF_ERR_CFL, "domain %d axis %d: CFL %.6g above the limit %.6g", i, a,
+                            h->umax[a] * dt[i] / h->g.h, h->p.cfl_max);
+        any_mdot = any_mdot || h->has_mdot;
+    }
+    if (b->dt.size() != (size_t)b->nd || memcmp(b->dt.data(), dt, b->nd * sizeof(double)) != 0) {
+        if (int r = batch_invalidate(b)) return r;
+        b->dt.assign(dt, dt + b->nd);
+    }
+    int k = 0;
+    if (int r = batch_slot_for_step(b, dt, &k)) return r;
+    BatchSlot& sl = b->slot[k];
+    if (use_graph && !any_mdot) {
+        if (!sl.exec) {
+            // recorded on a private stream (the caller's may be the null stream, which
+            // cannot be captured), replayed on the caller's
+            if (!b->capture) HIP_TRY(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
+            HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
+            const int r = batch_enqueue(b, k, dt, b->capture);
+            hipGraph_t g = nullptr;
+            const hipError_t e = hipStreamEndCapture(b->capture, &g);
+            if (r) {
+                if (g) (void)hipGraphDestroy(g);
+                return r;
+            }
+            if (e != hipSuccess) return fail(PCVOF_ERR_HIP, "stream capture failed: %s", hipGetErrorString(e));
+            sl.graph = g;
+            HIP_TRY(hipGraphInstantiate(&sl.exec, g, nullptr, nullptr, 0));
+        }
+        HIP_TRY(hipGraphLaunch(sl.exec, b->stream));
+    } else {
+        if (int r = batch_enqueue(b, k, dt, b->stream)) return r;
+    }
+    // the domains' states after the step
+    for (int i = 0; i < b->nd; ++i) {
+        pcvof_handle* h = b->dom[i];
+        h->step_cfl = 0.0;
+        for (int s = 0; s < b->ndim; ++s) {
+            const int axis = (int)((b->step + s) % b->ndim);
+            h->nb[s] = b->dom_tiles[axis][i];
+            h->cur = 1 - h->cur;
+            h->mask_cpw = axis == 0 ? pcv::kMaskCpwX : pcv::kMaskCpw;
+            const double cfl = h->umax[axis] * dt[i] / h->g.h;
+            if (cfl > h->step_cfl) h->step_cfl = cfl;
+        }
+        for (int s = b->ndim; s < 3; ++s) h->nb[s] = 0;
+        h->nb[3] = 0;
+        h->last_slot = b->ndim - 1;
+        if (h->has_mdot) {
+            h->nb[3] = pcv::cell_launch(h->d).nblocks;
+            h->cur = 1 - h->cur;
+            h->mask_cpw = pcv::kMaskCpw;
+            h->last_slot = 3;
+        }
+        h->step++;
+    }
+    b->step++;
+    if (stats) {
+        HIP_TRY(hipStreamSynchronize(b->stream));
+        for (int i = 0; i < b->nd; ++i) {
+            double cs[pcv::kSlots * pcv::kPartialWidth];
+            HIP_TRY(hipMemcpy(cs, b->dom[i]->colsum(), sizeof cs, hipMemcpyDeviceToHost));
+            fill_stats(b->dom[i], cs, &stats[i]);
+        }
+    }
+    return PCVOF_OK;
+}
+
+int pcvof_batch_get_step(pcvof_batch* b, long* step) {
+    if (int r = batch_check(b)) return r;
+    if (!step) return fail(PCVOF_ERR_ARG, "step is null");
+    *step = b->step;
+    return PCVOF_OK;
+}
+
+int pcvof_batch_set_tiles(pcvof_batch* b, const int* chunk, const int* grid) {
+    if (int r = batch_check(b)) return r;
+    for (int a = 1; a < b->ndim && chunk; ++a) {
+        const int c = chunk[a];
+        if (c != 0 && (c < pcv::min_chunk() || c > pcv::max_chunk() || (c & (c - 1))))
+            return fail(PCVOF_ERR_ARG, "axis %d: chunk %d is not 0 or a power of two in [%d, %d]", a, c,
+                        pcv::min_chunk(), pcv::max_chunk());
+    }
+    for (int a = 0; a < b->ndim && grid; ++a)
+        if (grid[a] < 1) return fail(PCVOF_ERR_ARG, "axis %d: grid %d < 1", a, grid[a]);
+    if (int r = batch_invalidate(b)) return r;
+    for (int a = 0; a < b->ndim; ++a) {
+        if (chunk && a > 0) b->chunk[a] = chunk[a];
+        if (grid) b->grid[a] = grid[a];
+    }
+    return batch_build_tiles(b);
+}
+
+int pcvof_batch_get_tiles(pcvof_batch* b, int* chunk, int* grid, int* ntiles) {
+    if (int r = batch_check(b)) return r;
+    for (int a = 0; a < 3; ++a) {
+        if (chunk) chunk[a] = b->chunk[a];
+        if (grid) grid[a] = b->grid[a];
+        if (ntiles) ntiles[a] = b->ntiles[a];
+    }
+    return PCVOF_OK;
+}
+
+int pcvof_batch_autotune(pcvof_batch* b, const double* dt, int reps, int* chosen_chunk, int* chosen_grid) {
+    if (int r = batch_check(b)) return r;
+    if (!dt || reps < 1) return fail(PCVOF_ERR_ARG, "need dt and reps >= 1");
+    for (int i = 0; i < b->nd; ++i)
+        if (!b->dom[i]->has_vof || !b->dom[i]->has_energy || !b->dom[i]->has_vel)
+            return fail(PCVOF_ERR_STATE, "domain %d: fraction, energy and velocity must be set", i);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int chunks[] = {0, 8, 16, 32};
+    const int grids[] = {0, 1024, 2048};  // 0: one block per tile
+    int best_chunk[3] = {0, 0, 0}, best_grid[3] = {kBatchGrid, kBatchGrid, kBatchGrid};
+    int rc = PCVOF_OK;
+    const size_t ab = pcv::sweep_args_bytes();
+    std::vector<char> args((size_t)b->nd * ab);
+    for (int axis = 0; axis < b->ndim && !rc; ++axis) {
+        float best = 1e30f;
+        for (int ci = 0; ci < (axis ? 4 : 1) && !rc; ++ci) {
+            int ch[3] = {b->chunk[0], b->chunk[1], b->chunk[2]};
+            ch[axis] = axis ? chunks[ci] : 0;
+            if ((rc = pcvof_batch_set_tiles(b, ch, nullptr))) break;
+            // a sweep of the current state into the other buffers (state not committed)
+            for (int i = 0; i < b->nd; ++i) {
+                pcvof_handle* h = b->dom[i];
+                pcv::SweepIO io = batch_sweep_io(b, i, 0, axis, h->cur, h->mask_cpw, dt[i]);
+                io.first = 1;
+                pcv::sweep_args_pack(io, args.data() + (size_t)i * ab);
+            }
+            char* dargs = b->args(0, 0);  // slot 0 is free after set_tiles
+            if (hipMemcpy(dargs, args.data(), args.size(), hipMemcpyHostToDevice) != hipSuccess) {
+                rc = fail(PCVOF_ERR_HIP, "autotune upload failed");
+                break;
+            }
+            for (int gi = 0; gi < 3 && !rc; ++gi) {
+                const int g = grids[gi] ? grids[gi] : b->ntiles[axis];
+                float ms = 0.0f;
+                for (int rep = 0; rep <= reps && !rc; ++rep) {  // the first run is a warm-up
+                    if (rep == 1 && hipEventRecord(e0, b->stream) != hipSuccess) rc = fail(PCVOF_ERR_HIP, "event");
+                    const hipError_t e = pcv::launch_sweep_batch(axis, b->mixed, b->doms(), dargs, b->tiles(axis),
+                                                                 b->ntiles[axis], g, b->stream);
+                    if (e != hipSuccess) rc = fail(PCVOF_ERR_HIP, "autotune launch: %s", hipGetErrorString(e));
+                }
+                if (rc) break;
+                if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                    rc = fail(PCVOF_ERR_HIP, "autotune timing failed");
+                    break;
+                }
+                if (ms < best) {
+                    best = ms;
+                    best_chunk[axis] = ch[axis];
+                    best_grid[axis] = g;
+                }
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!rc) rc = pcvof_batch_set_tiles(b, best_chunk, best_grid);
+    if (!rc) {
+        for (int a = 0; a < 3; ++a) {
+            if (chosen_chunk) chosen_chunk[a] = b->chunk[a];
+            if (chosen_grid) chosen_grid[a] = b->grid[a];
+        }
+    }
+    return rc;
 }
 
 const char* pcvof_last_error(void) { return g_err.c_str(); }

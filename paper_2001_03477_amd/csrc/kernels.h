@@ -63,6 +63,27 @@ hipError_t launch_classify(const Dom& d, const double* c, uint64_t* mask, hipStr
 // A direction sweep is one launch (geometry of the mixed donors inside each tile).
 hipError_t launch_sweep(const Dom& d, int axis, const SweepIO& io, hipStream_t s);
 
+// Batched sweeps of many domains. A tile is one block of a domain's single-domain
+// sweep launch: its coordinates in that launch grid, its row in the domain's partial
+// table (blk) and, for y / z sweeps, the column chunk.
+struct BatchTile {
+    int dom, bx, by, bz, blk, chunk;
+};
+// Tiles of a domain's sweep along axis (chunk <= 0: the single-domain rule; else the
+// given chunk, at most the longest supported); writes them to out (if not null) and
+// returns their number. The tiles' blk rows stay below max_partial_blocks.
+int sweep_tiles(const Dom& d, int axis, int chunk, int dom, BatchTile* out);
+// The device form of a sweep's arguments (the batched kernels read one per domain).
+size_t sweep_args_bytes();
+void sweep_args_pack(const SweepIO& io, void* out);
+// One launch of `grid` blocks over ntiles tiles of a sweep along axis.
+hipError_t launch_sweep_batch(int axis, int mixed, const Dom* doms, const void* args, const BatchTile* tiles,
+                              int ntiles, int grid, hipStream_t s);
+// Longest and shortest column chunks of the y / z sweeps (sweep_tiles accepts the
+// powers of two between them).
+int max_chunk();
+int min_chunk();
+
 struct PhaseIO {
     const double* c;
     const double* e;
@@ -81,6 +102,14 @@ hipError_t launch_phase(const Dom& d, const PhaseIO& io, hipStream_t s);
 
 // colsum[slot * 8 + q] = sum over the nb[slot] blocks of quantity q of slot.
 hipError_t launch_colsum(const double* part, long part_stride, const int* nb, double* colsum, hipStream_t s);
+// The same for many domains in one launch: domain i uses cs[i].
+struct ColsumArgs {
+    const double* part;
+    long stride;
+    int nb[4];
+    double* colsum;
+};
+hipError_t launch_colsum_batch(int nd, const ColsumArgs* cs, hipStream_t s);
 
 hipError_t launch_energy_from_T(const Dom& d, const double* c, const double* T, double* e, hipStream_t s);
 hipError_t launch_T_from_energy(const Dom& d, const double* c, const double* e, double* T, hipStream_t s);

@@ -36,6 +36,32 @@ k_colsum(const double* __restrict__ part, long stride, int nb0, int nb1, int nb2
     if (threadIdx.x == 0) colsum[slot * kPartialWidth + q] = sm[0];
 }
 
+// k_colsum for many domains: block (q, slot, i) sums quantity q of slot of domain i in
+// the same order as k_colsum.
+__global__ void __launch_bounds__(256) k_colsum_batch(const ColsumArgs* __restrict__ cs) {
+    __shared__ double sm[256];
+    const ColsumArgs c = cs[blockIdx.z];
+    const int q = blockIdx.x, slot = blockIdx.y;
+    const int nb = c.nb[slot];
+    const double* P = c.part + ((long)slot * kPartialWidth + q) * c.stride;
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+    int b = threadIdx.x;
+    for (; b + 768 < nb; b += 1024) {
+        v0 += P[b];
+        v1 += P[b + 256];
+        v2 += P[b + 512];
+        v3 += P[b + 768];
+    }
+    for (; b < nb; b += 256) v0 += P[b];
+    sm[threadIdx.x] = (v0 + v1) + (v2 + v3);
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) c.colsum[slot * kPartialWidth + q] = sm[0];
+}
+
 __global__ void k_energy_from_T(Dom d, const double* __restrict__ c, const double* __restrict__ T,
                                 double* __restrict__ e) {
     const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -130,6 +156,11 @@ dim3 linear_grid(long n, int bs) { return dim3((unsigned)((n + bs - 1) / bs)); }
 hipError_t launch_colsum(const double* part, long part_stride, const int* nb, double* colsum, hipStream_t s) {
     hipLaunchKernelGGL(k_colsum, dim3(kPartialWidth, kSlots), dim3(256), 0, s, part, part_stride, nb[0], nb[1],
                        nb[2], nb[3], colsum);
+    return hipGetLastError();
+}
+
+hipError_t launch_colsum_batch(int nd, const ColsumArgs* cs, hipStream_t s) {
+    hipLaunchKernelGGL(k_colsum_batch, dim3(kPartialWidth, kSlots, nd), dim3(256), 0, s, cs);
     return hipGetLastError();
 }
 

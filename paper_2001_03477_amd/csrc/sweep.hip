@@ -12,6 +12,7 @@
 // geometry of one wavefront overlaps with the streaming of the others on the same
 // SIMD. All floating point is double precision.
 #include <hip/hip_runtime.h>
+#include <string.h>
 
 #include <type_traits>
 
@@ -202,17 +203,25 @@ constexpr int XS = XW + 5;
 // wavefront keeps in LDS (fluxes beyond it go to a face array in global memory,
 // written and read back by the same wavefront).
 constexpr int TCH = 32;
+constexpr int kMinChunk = 8;
 constexpr int TFCAP = 192;
 static_assert(TCH < 64 && (TCH + 1) * 64 <= 65536, "work items and positions fit 16 bits");
 
+// A tile of a sweep: block coordinates in the domain's own launch grid and the row
+// of the partial tables it writes.
+struct TileAt {
+    int bx, by, bz;
+    int blk;
+};
+
 template <bool MP>
-__device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a) {
+__device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a, const TileAt& tl) {
     __shared__ double s_c[XWAVES][XS];
     __shared__ double s_T[XWAVES][XS];
     __shared__ double s_F[XWAVES][XRPW][XW];                 // liquid flux of mixed donors
     __shared__ unsigned short s_work[XWAVES][XRPW * XW];    // candidate faces (row:lane)
     const int lane = threadIdx.x, wave = threadIdx.y;
-    const int bx = blockIdx.x, by = blockIdx.y, z = blockIdx.z;
+    const int bx = tl.bx, by = tl.by, z = tl.bz;
     const int x0 = bx * XC;
     const int y0 = (by * XWAVES + wave) * XRPW;
     const int x = x0 + lane;
@@ -349,7 +358,7 @@ __device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a) {
         if (lane == 0) a.mask_out[((long)z * d.n[1] + y) * d.wpr + bx] = bits;
         __builtin_amdgcn_wave_barrier();
     }
-    block_sum8<XWAVES>(acc, a.part + block_linear(), a.part_stride);
+    block_sum8<XWAVES>(acc, a.part + tl.blk, a.part_stride);
 }
 
 // y and z sweeps: each thread owns one column along the sweep axis (x across the
@@ -357,13 +366,13 @@ __device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a) {
 // fractions, energies and temperatures of cells f-3 .. f+2 in registers; each face
 // flux is computed once and used by both neighbours.
 template <int AX, bool MP>
-__device__ __forceinline__ void sweep_t_body(const Dom& d, const SweepArgs& a, int chunk) {
+__device__ __forceinline__ void sweep_t_body(const Dom& d, const SweepArgs& a, int chunk, const TileAt& tl) {
     constexpr int TA = AX == 1 ? 2 : 1;  // the transverse axis other than x
     __shared__ unsigned short s_idx[4][TCH + 1][64];     // work position of each candidate face
     __shared__ unsigned short s_work[4][(TCH + 1) * 64];  // candidate faces (face offset:lane)
     __shared__ double s_F[4][TFCAP];                      // liquid flux of mixed donors, by position
     const int lane = threadIdx.x, tr = threadIdx.y;
-    const int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+    const int bx = tl.bx, by = tl.by, bz = tl.bz;
     const int x = bx * 64 + lane;
     const int t = by * 4 + tr;
     const int nt = (d.ndim == 2 && TA == 2) ? 1 : d.n[TA];
@@ -550,25 +559,73 @@ __device__ __forceinline__ void sweep_t_body(const Dom& d, const SweepArgs& a, i
         if (f + 7 > s1) break;
         step(integral_constant<int, 7>{}, f + 7);
     }
-    block_sum8<4>(acc, a.part + block_linear(), a.part_stride);
+    block_sum8<4>(acc, a.part + tl.blk, a.part_stride);
 }
 
 // Kernel entry points. The mixed-precision bodies fit fewer registers per lane, so
 // their launches ask for five (x) and four (y, z) wavefronts per SIMD; the double
 // precision bodies would spill at those limits and keep the compiler's allocation.
-__global__ void __launch_bounds__(XW* XWAVES) k_sweep_x(Dom d, SweepArgs a) { sweep_x_body<false>(d, a); }
+__device__ __forceinline__ TileAt own_tile() {
+    return {(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z, block_linear()};
+}
+__global__ void __launch_bounds__(XW* XWAVES) k_sweep_x(Dom d, SweepArgs a) { sweep_x_body<false>(d, a, own_tile()); }
 __global__ void __launch_bounds__(XW* XWAVES) __attribute__((amdgpu_waves_per_eu(5, 8)))
 k_sweep_x_mixed(Dom d, SweepArgs a) {
-    sweep_x_body<true>(d, a);
+    sweep_x_body<true>(d, a, own_tile());
 }
 template <int AX>
 __global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) {
-    sweep_t_body<AX, false>(d, a, chunk);
+    sweep_t_body<AX, false>(d, a, chunk, own_tile());
 }
 template <int AX>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_sweep_t_mixed(Dom d, SweepArgs a, int chunk) {
-    sweep_t_body<AX, true>(d, a, chunk);
+    sweep_t_body<AX, true>(d, a, chunk, own_tile());
+}
+
+// Batched sweeps: one launch advances the same sweep of many independent domains.
+// Every block walks a table of tiles (domain, tile coordinates in the domain's own
+// launch grid, partial-table row) with a grid stride, so a launch sized to the chip's
+// resident capacity stays resident until the table is done. Each domain's Dom and
+// SweepArgs come from device arrays; a tile computes exactly what the block of the
+// single-domain launch with the same coordinates computes.
+template <bool MP>
+__device__ __forceinline__ void sweep_x_tiles(const Dom* __restrict__ doms, const SweepArgs* __restrict__ args,
+                                              const BatchTile* __restrict__ tiles, int ntiles) {
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const BatchTile bt = tiles[t];
+        const Dom d = doms[bt.dom];
+        const SweepArgs a = args[bt.dom];
+        sweep_x_body<MP>(d, a, TileAt{bt.bx, bt.by, bt.bz, bt.blk});
+    }
+}
+template <int AX, bool MP>
+__device__ __forceinline__ void sweep_t_tiles(const Dom* __restrict__ doms, const SweepArgs* __restrict__ args,
+                                              const BatchTile* __restrict__ tiles, int ntiles) {
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const BatchTile bt = tiles[t];
+        const Dom d = doms[bt.dom];
+        const SweepArgs a = args[bt.dom];
+        sweep_t_body<AX, MP>(d, a, bt.chunk, TileAt{bt.bx, bt.by, bt.bz, bt.blk});
+    }
+}
+__global__ void __launch_bounds__(XW* XWAVES)
+k_sweep_x_batch(const Dom* doms, const SweepArgs* args, const BatchTile* tiles, int ntiles) {
+    sweep_x_tiles<false>(doms, args, tiles, ntiles);
+}
+__global__ void __launch_bounds__(XW* XWAVES) __attribute__((amdgpu_waves_per_eu(5, 8)))
+k_sweep_x_batch_mixed(const Dom* doms, const SweepArgs* args, const BatchTile* tiles, int ntiles) {
+    sweep_x_tiles<true>(doms, args, tiles, ntiles);
+}
+template <int AX>
+__global__ void __launch_bounds__(256)
+k_sweep_t_batch(const Dom* doms, const SweepArgs* args, const BatchTile* tiles, int ntiles) {
+    sweep_t_tiles<AX, false>(doms, args, tiles, ntiles);
+}
+template <int AX>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_sweep_t_batch_mixed(const Dom* doms, const SweepArgs* args, const BatchTile* tiles, int ntiles) {
+    sweep_t_tiles<AX, true>(doms, args, tiles, ntiles);
 }
 
 // Step 2, first pass (section 3.3.2), over every mixed cell of c~ with a non-zero mass
@@ -699,9 +756,10 @@ Launch sweep_launch(const Dom& d, int axis, int* chunk) {
 }
 
 int max_partial_blocks(const Dom& d) {
-    int ch, m = cell_launch(d).nblocks;
+    // y / z sweeps are counted with the shortest chunk a batch may choose (kMinChunk)
+    int m = cell_launch(d).nblocks;
     for (int a = 0; a < d.ndim; ++a) {
-        const int nb = sweep_launch(d, a, &ch).nblocks;
+        const int nb = sweep_tiles(d, a, a == 0 ? 0 : kMinChunk, 0, nullptr);
         if (nb > m) m = nb;
     }
     return m;
@@ -721,6 +779,45 @@ void launch_sweep_kernel(const Dom& d, int axis, const Launch& L, int chunk, con
         hipLaunchKernelGGL(MP ? k_sweep_t_mixed<1> : k_sweep_t<1>, L.grid, L.block, 0, s, d, a, chunk);
     else
         hipLaunchKernelGGL(MP ? k_sweep_t_mixed<2> : k_sweep_t<2>, L.grid, L.block, 0, s, d, a, chunk);
+}
+
+size_t sweep_args_bytes() { return sizeof(SweepArgs); }
+
+int max_chunk() { return TCH; }
+int min_chunk() { return kMinChunk; }
+
+void sweep_args_pack(const SweepIO& io, void* out) {
+    SweepArgs a{io.c,   io.e,    io.mask, io.mask_cpw, io.mask_out, io.cc,   io.ec,          io.vel,
+                io.kfac, io.fgeo, io.c_out, io.e_out,   io.part,     io.part_stride, io.first};
+    memcpy(out, &a, sizeof a);
+}
+
+hipError_t launch_sweep_batch(int axis, int mixed, const Dom* doms, const void* args, const BatchTile* tiles,
+                              int ntiles, int grid, hipStream_t s) {
+    const SweepArgs* a = (const SweepArgs*)args;
+    const dim3 g(grid), b(64, 4, 1);
+    if (axis == 0)
+        hipLaunchKernelGGL(mixed ? k_sweep_x_batch_mixed : k_sweep_x_batch, g, b, 0, s, doms, a, tiles, ntiles);
+    else if (axis == 1)
+        hipLaunchKernelGGL(mixed ? k_sweep_t_batch_mixed<1> : k_sweep_t_batch<1>, g, b, 0, s, doms, a, tiles, ntiles);
+    else
+        hipLaunchKernelGGL(mixed ? k_sweep_t_batch_mixed<2> : k_sweep_t_batch<2>, g, b, 0, s, doms, a, tiles, ntiles);
+    return hipGetLastError();
+}
+
+int sweep_tiles(const Dom& d, int axis, int chunk, int dom, BatchTile* out) {
+    int ch = 0;
+    Launch L = sweep_launch(d, axis, &ch);
+    if (axis != 0) {
+        ch = chunk > 0 ? chunk : ch;
+        L.grid.z = (d.n[axis] + ch - 1) / ch;
+    }
+    int k = 0;
+    for (unsigned z = 0; z < L.grid.z; ++z)
+        for (unsigned y = 0; y < L.grid.y; ++y)
+            for (unsigned x = 0; x < L.grid.x; ++x, ++k)
+                if (out) out[k] = BatchTile{dom, (int)x, (int)y, (int)z, k, ch};
+    return k;
 }
 
 hipError_t launch_sweep(const Dom& d, int axis, const SweepIO& io, hipStream_t s) {

@@ -29,7 +29,9 @@ EXPORTS = (
     "pcvof_get_energy", "pcvof_get_temperature", "pcvof_get_step", "pcvof_set_step",
     "pcvof_last_error", "pcvof_geom_volume", "pcvof_geom_alpha", "pcvof_geom_slab",
     "pcvof_geom_normal", "pcvof_geom_weno5", "pcvof_advect_steps", "pcvof_set_profiling",
-    "pcvof_get_profile",
+    "pcvof_get_profile", "pcvof_batch_workspace_bytes", "pcvof_batch_create", "pcvof_batch_destroy",
+    "pcvof_batch_domain", "pcvof_batch_advect_step", "pcvof_batch_get_step", "pcvof_batch_set_tiles",
+    "pcvof_batch_get_tiles", "pcvof_batch_autotune",
 )
 
 PROF_NAMES = ("sweep_x", "sweep_y", "sweep_z", "phase", "checksum")
@@ -110,9 +112,20 @@ def lib():
         L.pcvof_advect_steps.argtypes = [_vp, C.c_int, C.c_double, _vp, C.POINTER(Stats)]
         L.pcvof_set_profiling.argtypes = [_vp, C.c_int]
         L.pcvof_get_profile.argtypes = [_vp, C.POINTER(Profile)]
+        L.pcvof_batch_workspace_bytes.restype = C.c_size_t
+        L.pcvof_batch_workspace_bytes.argtypes = [C.c_int, C.POINTER(Grid), C.POINTER(Params)]
+        L.pcvof_batch_create.argtypes = [C.c_int, C.POINTER(Grid), C.POINTER(Params), _vp, C.c_size_t,
+                                         _vp, C.POINTER(_vp)]
+        L.pcvof_batch_destroy.argtypes = [_vp]
+        L.pcvof_batch_domain.argtypes = [_vp, C.c_int, C.POINTER(_vp)]
+        L.pcvof_batch_advect_step.argtypes = [_vp, _vp, C.c_int, _vp]
+        L.pcvof_batch_get_step.argtypes = [_vp, C.POINTER(C.c_long)]
+        L.pcvof_batch_set_tiles.argtypes = [_vp, _vp, _vp]
+        L.pcvof_batch_get_tiles.argtypes = [_vp, _vp, _vp, _vp]
+        L.pcvof_batch_autotune.argtypes = [_vp, _vp, C.c_int, _vp, _vp]
         for nm in EXPORTS:
             f = getattr(L, nm)
-            if nm not in ("pcvof_workspace_bytes", "pcvof_last_error"):
+            if nm not in ("pcvof_workspace_bytes", "pcvof_last_error", "pcvof_batch_workspace_bytes"):
                 f.restype = C.c_int
         _lib = L
     return _lib
@@ -300,10 +313,94 @@ class Domain:
     def step_index(self, n: int):
         check(lib().pcvof_set_step(self._h, int(n)))
 
+    @classmethod
+    def _view(cls, spec: DomainSpec, handle, device, stream):
+        """A domain owned by a Batch (no workspace or lifetime of its own)."""
+        import torch
+        d = cls.__new__(cls)
+        d.spec = spec
+        d.device = torch.device(device)
+        d.workspace = None
+        d.stream = stream
+        d._h = handle
+        d._view_of = True
+        return d
+
     def close(self):
-        if self._h:
+        if self._h and not getattr(self, "_view_of", False):
             check(lib().pcvof_destroy(self._h))
-            self._h = _vp()
+        self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent domains advected together: one fused launch per direction sweep
+    over the tiles of all domains, optionally replayed from captured HIP graphs."""
+
+    def __init__(self, specs, device="cuda", stream=None):
+        import torch
+        self.specs = list(specs)
+        nd = len(self.specs)
+        grids = (Grid * nd)(*[s.grid() for s in self.specs])
+        params = (Params * nd)(*[s.params() for s in self.specs])
+        nbytes = int(lib().pcvof_batch_workspace_bytes(nd, grids, params))
+        if nbytes == 0:
+            raise PcvofError(-1, "invalid grids or params, or domains differ in ndim or precision")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = stream
+        self._b = _vp()
+        check(lib().pcvof_batch_create(nd, grids, params, self.workspace.data_ptr(), nbytes,
+                                       _stream_ptr(stream), C.byref(self._b)))
+        self.domains = []
+        for i, s in enumerate(self.specs):
+            h = _vp()
+            check(lib().pcvof_batch_domain(self._b, i, C.byref(h)))
+            self.domains.append(Domain._view(s, h, device, stream))
+
+    def step(self, dt, use_graph: bool = False, stats: bool = False):
+        """One step of every domain with its own dt (sequence of len(domains))."""
+        arr = np.ascontiguousarray(np.asarray(dt, dtype=np.float64))
+        assert arr.shape == (len(self.domains),)
+        st = (Stats * len(self.domains))() if stats else None
+        check(lib().pcvof_batch_advect_step(self._b, arr.ctypes.data, 1 if use_graph else 0,
+                                            C.cast(st, _vp) if st is not None else None))
+        return [x.as_dict() for x in st] if st is not None else None
+
+    @property
+    def step_index(self) -> int:
+        v = C.c_long()
+        check(lib().pcvof_batch_get_step(self._b, C.byref(v)))
+        return v.value
+
+    def set_tiles(self, chunk=None, grid=None):
+        ch = (C.c_int * 3)(*chunk) if chunk is not None else None
+        gr = (C.c_int * 3)(*grid) if grid is not None else None
+        check(lib().pcvof_batch_set_tiles(self._b, C.cast(ch, _vp) if ch is not None else None,
+                                          C.cast(gr, _vp) if gr is not None else None))
+
+    def tiles(self):
+        ch, gr, nt = (C.c_int * 3)(), (C.c_int * 3)(), (C.c_int * 3)()
+        check(lib().pcvof_batch_get_tiles(self._b, C.cast(ch, _vp), C.cast(gr, _vp), C.cast(nt, _vp)))
+        return {"chunk": list(ch), "grid": list(gr), "ntiles": list(nt)}
+
+    def autotune(self, dt, reps: int = 3):
+        arr = np.ascontiguousarray(np.asarray(dt, dtype=np.float64))
+        ch, gr = (C.c_int * 3)(), (C.c_int * 3)()
+        check(lib().pcvof_batch_autotune(self._b, arr.ctypes.data, int(reps), C.cast(ch, _vp),
+                                         C.cast(gr, _vp)))
+        return {"chunk": list(ch), "grid": list(gr)}
+
+    def close(self):
+        for d in getattr(self, "domains", []):
+            d._h = _vp()
+        if getattr(self, "_b", None):
+            check(lib().pcvof_batch_destroy(self._b))
+            self._b = _vp()
 
     def __del__(self):
         try:

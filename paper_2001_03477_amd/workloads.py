@@ -279,16 +279,20 @@ def fourier_modes(rng, nmodes=8, kmax=4, nd=3):
     return ks, amps, phis
 
 
-def fourier_mac_velocity(ks, amps, phis, shape, h):
+def fourier_mac_velocity(ks, amps, phis, shape, h, lengths=None):
     """3D periodic MAC velocities of curl A for A = sum_j a_j sin(2 pi k_j.x + phi_j),
     like mac_velocity(fourier_potential(...)) but with the edge integrals evaluated
     separably: the integral of sin(2 pi k.x + phi) along an edge of length h in
     direction d is h sinc(k_d h) sin(2 pi k.x_mid + phi) with x_mid the edge midpoint,
     and sin(a + b + c) over the grid is built from 1D factors, so a 512^3 field takes
     seconds. Node coordinates wrap (the last node is at 0), so the two boundary faces
-    of every axis are bitwise equal."""
+    of every axis are bitwise equal. With lengths = (Lx, Ly, Lz) the box is periodic
+    with those lengths (cells of side h, n_a h = L_a) and the wave vectors are k_a / L_a."""
     nz, ny, nx = shape
     tp = 2.0 * math.pi
+    if lengths is None:
+        lengths = (1.0, 1.0, 1.0)
+    ks = [np.array([k[0] / lengths[0], k[1] / lengths[1], k[2] / lengths[2]]) for k in ks]
 
     def coords(n, mid):
         idx = np.arange(n if mid else n + 1)
@@ -587,3 +591,44 @@ def bubble_3d(n=256, R=0.1, u0=0.05, smooth=0.8, cfl=0.3, rho_l=2.5, cp_l=6.25, 
     mdot = np.full(shape, k_l * (T_inf - T_sat) / (delta_T * h_fg))
     return Workload(f"bubble3d_{n}", shape, h, 3, (1, 1, 1), cp_l, cp_g, rho_l, T_sat, c, e, u, v, w,
                     mdot, dt, 10)
+
+
+def batch_domains(nd=64, seed=5, smin=32, smax=160, cfl=0.3, cp=(1000.0, 1.0)):
+    """nd independent periodic 3D domains with sides uniform in [smin, smax] cells per
+    axis (cubic cells of side 1/nx), each holding one drop (liquid sphere) or bubble
+    (gas sphere), 50/50, of radius uniform in [0.15, 0.3] times the shortest side, at a
+    random position, in its own random periodic Fourier velocity (4 to 8 modes) scaled
+    to CFL 0.3 with its own dt; random per-phase temperatures; rho c_p 1000 : 1,
+    m'' = 0."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(nd):
+        nx, ny, nz = (int(v) for v in rng.integers(smin, smax + 1, size=3))
+        h = 1.0 / nx
+        shape = (nz, ny, nx)
+        L = (nx * h, ny * h, nz * h)
+        r = rng.uniform(0.15, 0.3) * min(nx, ny, nz) * h
+        centre = np.array([rng.uniform(0, L[0]), rng.uniform(0, L[1]), rng.uniform(0, L[2])])
+        drop = bool(rng.integers(0, 2))
+        # the sphere and its periodic images that reach into the box
+        cs, rs = [], []
+        for sx in (-1, 0, 1):
+            for sy in (-1, 0, 1):
+                for sz in (-1, 0, 1):
+                    q = centre + np.array([sx * L[0], sy * L[1], sz * L[2]])
+                    if np.all(q + r > 0) and np.all(q - r < np.array(L)):
+                        cs.append(q)
+                        rs.append(r)
+        c = sphere_fraction(shape, h, np.array(cs), np.array(rs), inside_liquid=drop, sub=8, nd=3,
+                            disjoint=True)
+        cp_l, cp_g = cp
+        T_l = rng.uniform(0, 1, size=shape)
+        T_g = rng.uniform(0, 1, size=shape)
+        e = energy_from_phase_temperatures(c, T_l, T_g, cp_l, cp_g)
+        ks, amps, phis = fourier_modes(rng, int(rng.integers(4, 9)), 4, 3)
+        u, v, w = fourier_mac_velocity(ks, amps, phis, shape, h, lengths=L)
+        umax = max_abs_face(u, v, w)
+        dt = cfl * h / umax
+        out.append(Workload(f"batch{i}_{nx}x{ny}x{nz}", shape, h, 3, (0, 0, 0), cp_l, cp_g, 1.0, 1.0,
+                            c, e, u, v, w, None, dt, 10))
+    return out
