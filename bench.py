@@ -48,6 +48,8 @@ def workload(name):
         return W.bubble_3d(256)
     if name == "droplets512":
         return W.droplets_3d(512)
+    if name == "batch64":
+        return W.batch_domains(64)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -129,6 +131,122 @@ def run(pcvof, torch, wl, precision, steps, warmup, scales):
             "sweep_bytes": sweep_b, "volume_drift": abs(vol1 - vol0) / vol0, "c_final": c_final}
 
 
+def run_batch(pcvof, torch, wls, precision, steps, warmup, use_graph, autotune):
+    """warmup + steps batched steps of all domains; returns the timed ms, the tile
+    choice, the volume drift (summed over domains) and the final fractions."""
+    specs = [pcvof.DomainSpec(shape=wl.shape, h=wl.h, ndim=3, bc=wl.bc, cp_l=wl.cp_l, cp_g=wl.cp_g,
+                              rho_l=wl.rho_l, T_gamma=wl.T_gamma, normal=wl.normal, precision=precision)
+             for wl in wls]
+    b = pcvof.Batch(specs)
+    for d, wl in zip(b.domains, wls):
+        d.set_vof(wl.c)
+        d.set_energy(wl.e)
+        d.set_velocity(wl.u, wl.v, wl.w)
+    dts = [wl.dt for wl in wls]
+    vol0 = sum(float(d.vof().sum()) * wl.h ** 3 for d, wl in zip(b.domains, wls))
+    tiles = b.autotune(dts, reps=3) if autotune else b.tiles()
+    for _ in range(warmup):
+        b.step(dts, use_graph=use_graph)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(steps):
+        b.step(dts, use_graph=use_graph)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    st = b.step(dts, use_graph=use_graph, stats=True)
+    vol1 = sum(x["vol"] for x in st)
+    finals = [d.vof().cpu().numpy() for d in b.domains]
+    b.close()
+    torch.cuda.empty_cache()
+    return {"total_ms": ms, "tiles": {"chunk": tiles["chunk"]},
+            "volume_drift": abs(vol1 - vol0) / vol0, "finals": finals}
+
+
+def run_per_domain(pcvof, torch, wls, steps, warmup):
+    """The same steps as one single-domain FP64 step call per domain (the domains in
+    turn, each with its own launches)."""
+    doms = []
+    for wl in wls:
+        spec = pcvof.DomainSpec(shape=wl.shape, h=wl.h, ndim=3, bc=wl.bc, cp_l=wl.cp_l, cp_g=wl.cp_g,
+                                rho_l=wl.rho_l, T_gamma=wl.T_gamma, normal=wl.normal)
+        d = pcvof.Domain(spec)
+        d.set_vof(wl.c)
+        d.set_energy(wl.e)
+        d.set_velocity(wl.u, wl.v, wl.w)
+        doms.append(d)
+    for _ in range(warmup):
+        for d, wl in zip(doms, wls):
+            d.step(wl.dt)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(steps):
+        for d, wl in zip(doms, wls):
+            d.step(wl.dt)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    for d, wl in zip(doms, wls):  # the step the batched runs take with checksums
+        d.step(wl.dt)
+    finals = [d.vof().cpu().numpy() for d in doms]
+    for d in doms:
+        d.close()
+    torch.cuda.empty_cache()
+    return {"total_ms": ms, "finals": finals}
+
+
+def bench_batch(args, pcvof, torch):
+    wls = workload("batch64")
+    ncells = sum(wl.ncells for wl in wls)
+    # algorithmic bytes of the three sweeps of a step, summed over the domains
+    step_bytes = sum(sweep_bytes(wl, a) for wl in wls for a in range(3))
+    step_bytes_mx = sum(sweep_bytes(wl, a, True) for wl in wls for a in range(3))
+    per = run_per_domain(pcvof, torch, wls, args.steps, args.warmup)
+    b64 = run_batch(pcvof, torch, wls, "fp64", args.steps, args.warmup, use_graph=True, autotune=True)
+    b64_plain = run_batch(pcvof, torch, wls, "fp64", args.steps, args.warmup, use_graph=False, autotune=False)
+    bmx = run_batch(pcvof, torch, wls, "mixed", args.steps, args.warmup, use_graph=True, autotune=True)
+    same = all(np.array_equal(a, c) for a, c in zip(per["finals"], b64["finals"]))
+    dmx = [np.abs(a - c) for a, c in zip(bmx["finals"], b64["finals"])]
+    rate = lambda r: ncells * args.steps / (r["total_ms"] * 1e-3)  # noqa: E731
+    value = rate(b64)
+    ms_step = b64["total_ms"] / args.steps
+    achieved = step_bytes / (ms_step * 1e-3) / 1e9
+    mx_ms = bmx["total_ms"] / args.steps
+    out = {
+        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"batch of {len(wls)} domains (sides 32-160, {ncells} cells)",
+                   "ndomains": len(wls), "cells": ncells, "bc": "periodic", "cfl": 0.3, "normal": "MYC",
+                   "mdot": "off", "precision": "fp64", "launch": "fused sweep launches, graph replay, autotuned chunks",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "batched sweeps (bytes of the three sweeps over the whole step time)",
+                     "bytes_per_cell": SWEEP_BYTES_PER_CELL + SWEEP_BYTES_PER_FACE},
+        "tiles": b64["tiles"],
+        "volume_drift": b64["volume_drift"],
+        "per_domain_fp64": {"value": rate(per), "ms_per_step": per["total_ms"] / args.steps,
+                            "fields_equal_to_batched": same},
+        "batched_fp64_no_graph": {"value": rate(b64_plain), "ms_per_step": b64_plain["total_ms"] / args.steps},
+        "mixed": {"value": rate(bmx), "ms_per_step": mx_ms, "speedup_vs_fp64": rate(bmx) / value,
+                  "speedup_vs_per_domain_fp64": rate(bmx) / rate(per), "tiles": bmx["tiles"],
+                  "roofline": {"achieved": step_bytes_mx / (mx_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                               "frac": step_bytes_mx / (mx_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                  "volume_drift": bmx["volume_drift"],
+                  "c_vs_fp64": {"max_abs": float(max(x.max() for x in dmx)),
+                                "l1_rel": float(sum(x.sum() for x in dmx) /
+                                                sum(np.abs(c).sum() for c in b64["finals"]))}},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wls[0])
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(wl, budget_s=15.0, max_side=128):
     """The oracle on the host: whole steps of the workload until the budget is used (at
     least one step). Domains larger than max_side per axis are sampled: the oracle
@@ -187,6 +305,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.workload == "batch64":
+        bench_batch(args, pcvof, torch)
+        return
     wl = workload(args.workload)
     scales = np.array([wl.u_scale(k) for k in range(args.warmup + args.steps)])
     r64 = run(pcvof, torch, wl, "fp64", args.steps, args.warmup, scales)

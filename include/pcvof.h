@@ -188,16 +188,16 @@ const char* pcvof_last_error(void);
    own between batched steps (PCVOF_ERR_STATE).
    pcvof_batch_advect_step advances every domain by one step (its own dt[i], velocity
    scale 1) with one fused launch per direction sweep over the tiles of all domains
-   (persistent grid-stride blocks; every tile computes what the single-domain sweep's
-   block computes, so results are bitwise those of pcvof_advect_step), step 2 for
+   (one block per tile; every tile computes what the single-domain sweep's block
+   computes, so results are bitwise those of pcvof_advect_step), step 2 for
    domains with a mass flux, and one checksum launch. Argument tables are cached per
    recurring step state. With use_graph != 0 (and no mass flux in any domain) the
    launches of a step are captured once per cached state into a HIP graph and replayed
    afterwards. stats (nullable) receives nd checksum records and synchronises.
-   pcvof_batch_set_tiles sets the column chunk of the y / z sweeps (0 = each domain's
-   single-domain rule, else a power of two in [8, 32]) and the blocks of each batched
-   launch; pcvof_batch_autotune times those choices on the current state (reps timed
-   launches per choice, the state is not advanced) and keeps the fastest per axis. */
+   pcvof_batch_set_tiles sets the column chunk of the y / z sweeps (chunk[1], chunk[2]:
+   0 = each domain's single-domain rule, else a power of two in [8, 32]);
+   pcvof_batch_autotune times the choices on the current state (reps timed launches per
+   choice; the state is not advanced) and keeps the fastest per axis. */
 typedef struct pcvof_batch pcvof_batch;
 size_t pcvof_batch_workspace_bytes(int nd, const pcvof_grid* grids, const pcvof_params* params);
 int pcvof_batch_create(int nd, const pcvof_grid* grids, const pcvof_params* params, void* d_workspace,
@@ -206,9 +206,9 @@ int pcvof_batch_destroy(pcvof_batch* b);
 int pcvof_batch_domain(pcvof_batch* b, int i, pcvof_handle** view);
 int pcvof_batch_advect_step(pcvof_batch* b, const double* dt, int use_graph, pcvof_stats* stats);
 int pcvof_batch_get_step(pcvof_batch* b, long* step);
-int pcvof_batch_set_tiles(pcvof_batch* b, const int* chunk, const int* grid);
-int pcvof_batch_get_tiles(pcvof_batch* b, int* chunk, int* grid, int* ntiles);
-int pcvof_batch_autotune(pcvof_batch* b, const double* dt, int reps, int* chosen_chunk, int* chosen_grid);
+int pcvof_batch_set_tiles(pcvof_batch* b, const int* chunk);
+int pcvof_batch_get_tiles(pcvof_batch* b, int* chunk, int* ntiles);
+int pcvof_batch_autotune(pcvof_batch* b, const double* dt, int reps, int* chosen_chunk);
 
 /* Batched cell geometry on device arrays of n entries (testing and reuse), enqueued
    on the given stream. m holds 3 doubles per entry; the volume functions accept any

@@ -636,8 +636,7 @@ int pcvof_set_step(pcvof_handle* h, long step) {
 
 namespace {
 
-constexpr int kArgSlots = 8;      // cached argument tables (one per recurring step state)
-constexpr int kBatchGrid = 1024;  // default blocks of a batched launch (resident on 256 CUs)
+constexpr int kArgSlots = 8;  // cached argument tables (one per recurring step state)
 
 struct BatchSlot {
     bool used = false;
@@ -695,7 +694,6 @@ struct pcvof_batch {
     hipStream_t capture = nullptr;  // private stream the graphs are recorded on (never runs work)
     std::vector<pcvof_handle*> dom;
     int chunk[3] = {0, 0, 0};     // y / z column chunk (0: each domain's own default)
-    int grid[3] = {kBatchGrid, kBatchGrid, kBatchGrid};
     int ntiles[3] = {0, 0, 0};
     std::vector<int> dom_tiles[3];  // tiles per domain and axis (rows of its partial table)
     BatchSlot slot[kArgSlots];
@@ -829,9 +827,8 @@ int batch_slot_for_step(pcvof_batch* b, const double* dt, int* out) {
 int batch_enqueue(pcvof_batch* b, int k, const double* dt, hipStream_t s_) {
     for (int s = 0; s < b->ndim; ++s) {
         const int axis = (int)((b->step + s) % b->ndim);
-        const int grid = b->grid[axis] < b->ntiles[axis] ? b->grid[axis] : b->ntiles[axis];
         HIP_TRY(pcv::launch_sweep_batch(axis, b->mixed, b->doms(), b->args(k, s), b->tiles(axis), b->ntiles[axis],
-                                        grid > 0 ? grid : 1, s_));
+                                        s_));
     }
     for (int i = 0; i < b->nd; ++i) {
         pcvof_handle* h = b->dom[i];
@@ -1024,7 +1021,7 @@ int pcvof_batch_get_step(pcvof_batch* b, long* step) {
     return PCVOF_OK;
 }
 
-int pcvof_batch_set_tiles(pcvof_batch* b, const int* chunk, const int* grid) {
+int pcvof_batch_set_tiles(pcvof_batch* b, const int* chunk) {
     if (int r = batch_check(b)) return r;
     for (int a = 1; a < b->ndim && chunk; ++a) {
         const int c = chunk[a];
@@ -1032,27 +1029,22 @@ int pcvof_batch_set_tiles(pcvof_batch* b, const int* chunk, const int* grid) {
             return fail(PCVOF_ERR_ARG, "axis %d: chunk %d is not 0 or a power of two in [%d, %d]", a, c,
                         pcv::min_chunk(), pcv::max_chunk());
     }
-    for (int a = 0; a < b->ndim && grid; ++a)
-        if (grid[a] < 1) return fail(PCVOF_ERR_ARG, "axis %d: grid %d < 1", a, grid[a]);
     if (int r = batch_invalidate(b)) return r;
-    for (int a = 0; a < b->ndim; ++a) {
-        if (chunk && a > 0) b->chunk[a] = chunk[a];
-        if (grid) b->grid[a] = grid[a];
-    }
+    for (int a = 1; a < b->ndim; ++a)
+        if (chunk) b->chunk[a] = chunk[a];
     return batch_build_tiles(b);
 }
 
-int pcvof_batch_get_tiles(pcvof_batch* b, int* chunk, int* grid, int* ntiles) {
+int pcvof_batch_get_tiles(pcvof_batch* b, int* chunk, int* ntiles) {
     if (int r = batch_check(b)) return r;
     for (int a = 0; a < 3; ++a) {
         if (chunk) chunk[a] = b->chunk[a];
-        if (grid) grid[a] = b->grid[a];
         if (ntiles) ntiles[a] = b->ntiles[a];
     }
     return PCVOF_OK;
 }
 
-int pcvof_batch_autotune(pcvof_batch* b, const double* dt, int reps, int* chosen_chunk, int* chosen_grid) {
+int pcvof_batch_autotune(pcvof_batch* b, const double* dt, int reps, int* chosen_chunk) {
     if (int r = batch_check(b)) return r;
     if (!dt || reps < 1) return fail(PCVOF_ERR_ARG, "need dt and reps >= 1");
     for (int i = 0; i < b->nd; ++i)
@@ -1062,8 +1054,7 @@ int pcvof_batch_autotune(pcvof_batch* b, const double* dt, int reps, int* chosen
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     const int chunks[] = {0, 8, 16, 32};
-    const int grids[] = {0, 1024, 2048};  // 0: one block per tile
-    int best_chunk[3] = {0, 0, 0}, best_grid[3] = {kBatchGrid, kBatchGrid, kBatchGrid};
+    int best_chunk[3] = {0, 0, 0};
     int rc = PCVOF_OK;
     const size_t ab = pcv::sweep_args_bytes();
     std::vector<char> args((size_t)b->nd * ab);
@@ -1072,7 +1063,7 @@ int pcvof_batch_autotune(pcvof_batch* b, const double* dt, int reps, int* chosen
         for (int ci = 0; ci < (axis ? 4 : 1) && !rc; ++ci) {
             int ch[3] = {b->chunk[0], b->chunk[1], b->chunk[2]};
             ch[axis] = axis ? chunks[ci] : 0;
-            if ((rc = pcvof_batch_set_tiles(b, ch, nullptr))) break;
+            if ((rc = pcvof_batch_set_tiles(b, ch))) break;
             // a sweep of the current state into the other buffers (state not committed)
             for (int i = 0; i < b->nd; ++i) {
                 pcvof_handle* h = b->dom[i];
@@ -1085,38 +1076,30 @@ int pcvof_batch_autotune(pcvof_batch* b, const double* dt, int reps, int* chosen
                 rc = fail(PCVOF_ERR_HIP, "autotune upload failed");
                 break;
             }
-            for (int gi = 0; gi < 3 && !rc; ++gi) {
-                const int g = grids[gi] ? grids[gi] : b->ntiles[axis];
-                float ms = 0.0f;
-                for (int rep = 0; rep <= reps && !rc; ++rep) {  // the first run is a warm-up
-                    if (rep == 1 && hipEventRecord(e0, b->stream) != hipSuccess) rc = fail(PCVOF_ERR_HIP, "event");
-                    const hipError_t e = pcv::launch_sweep_batch(axis, b->mixed, b->doms(), dargs, b->tiles(axis),
-                                                                 b->ntiles[axis], g, b->stream);
-                    if (e != hipSuccess) rc = fail(PCVOF_ERR_HIP, "autotune launch: %s", hipGetErrorString(e));
-                }
-                if (rc) break;
-                if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                    rc = fail(PCVOF_ERR_HIP, "autotune timing failed");
-                    break;
-                }
-                if (ms < best) {
-                    best = ms;
-                    best_chunk[axis] = ch[axis];
-                    best_grid[axis] = g;
-                }
+            float ms = 0.0f;
+            for (int rep = 0; rep <= reps && !rc; ++rep) {  // the first run is a warm-up
+                if (rep == 1 && hipEventRecord(e0, b->stream) != hipSuccess) rc = fail(PCVOF_ERR_HIP, "event");
+                const hipError_t e = pcv::launch_sweep_batch(axis, b->mixed, b->doms(), dargs, b->tiles(axis),
+                                                             b->ntiles[axis], b->stream);
+                if (e != hipSuccess) rc = fail(PCVOF_ERR_HIP, "autotune launch: %s", hipGetErrorString(e));
+            }
+            if (rc) break;
+            if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = fail(PCVOF_ERR_HIP, "autotune timing failed");
+                break;
+            }
+            if (ms < best) {
+                best = ms;
+                best_chunk[axis] = ch[axis];
             }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (!rc) rc = pcvof_batch_set_tiles(b, best_chunk, best_grid);
-    if (!rc) {
-        for (int a = 0; a < 3; ++a) {
-            if (chosen_chunk) chosen_chunk[a] = b->chunk[a];
-            if (chosen_grid) chosen_grid[a] = b->grid[a];
-        }
-    }
+    if (!rc) rc = pcvof_batch_set_tiles(b, best_chunk);
+    if (!rc && chosen_chunk)
+        for (int a = 0; a < 3; ++a) chosen_chunk[a] = b->chunk[a];
     return rc;
 }
 

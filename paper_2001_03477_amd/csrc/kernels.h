@@ -76,9 +76,9 @@ int sweep_tiles(const Dom& d, int axis, int chunk, int dom, BatchTile* out);
 // The device form of a sweep's arguments (the batched kernels read one per domain).
 size_t sweep_args_bytes();
 void sweep_args_pack(const SweepIO& io, void* out);
-// One launch of `grid` blocks over ntiles tiles of a sweep along axis.
+// One launch over the ntiles tiles of a sweep along axis (one block per tile).
 hipError_t launch_sweep_batch(int axis, int mixed, const Dom* doms, const void* args, const BatchTile* tiles,
-                              int ntiles, int grid, hipStream_t s);
+                              int ntiles, hipStream_t s);
 // Longest and shortest column chunks of the y / z sweeps (sweep_tiles accepts the
 // powers of two between them).
 int max_chunk();

@@ -583,31 +583,48 @@ k_sweep_t_mixed(Dom d, SweepArgs a, int chunk) {
     sweep_t_body<AX, true>(d, a, chunk, own_tile());
 }
 
-// Batched sweeps: one launch advances the same sweep of many independent domains.
-// Every block walks a table of tiles (domain, tile coordinates in the domain's own
-// launch grid, partial-table row) with a grid stride, so a launch sized to the chip's
-// resident capacity stays resident until the table is done. Each domain's Dom and
-// SweepArgs come from device arrays; a tile computes exactly what the block of the
-// single-domain launch with the same coordinates computes.
+// Batched sweeps: one launch advances the same sweep of many independent domains,
+// one block per entry of a table of tiles (domain, tile coordinates in the domain's
+// own launch grid, partial-table row). Each domain's Dom and SweepArgs come from
+// device arrays, read into scalar registers; a tile computes exactly what the block
+// of the single-domain launch with the same coordinates computes. (Blocks that loop
+// over several tiles would keep the tables' fields live across the loop: 40 to 65
+// more vector registers per lane and one wavefront per SIMD less.)
+// A structure every lane of the block reads at the same address, moved into scalar
+// registers one 32-bit word at a time (so that its fields do not occupy vector
+// registers in the sweep bodies).
+template <typename S>
+__device__ __forceinline__ S uniform_load(const S* p) {
+    static_assert(sizeof(S) % 4 == 0, "whole words");
+    constexpr int kWords = (int)(sizeof(S) / 4);
+    const unsigned* src = (const unsigned*)p;
+    unsigned w[kWords];
+#pragma unroll
+    for (int i = 0; i < kWords; ++i) w[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    S out;
+    memcpy(&out, w, sizeof(S));
+    return out;
+}
+
 template <bool MP>
 __device__ __forceinline__ void sweep_x_tiles(const Dom* __restrict__ doms, const SweepArgs* __restrict__ args,
                                               const BatchTile* __restrict__ tiles, int ntiles) {
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const BatchTile bt = tiles[t];
-        const Dom d = doms[bt.dom];
-        const SweepArgs a = args[bt.dom];
-        sweep_x_body<MP>(d, a, TileAt{bt.bx, bt.by, bt.bz, bt.blk});
-    }
+    const int t = blockIdx.x;
+    if (t >= ntiles) return;
+    const BatchTile bt = uniform_load(tiles + t);
+    const Dom d = uniform_load(doms + bt.dom);
+    const SweepArgs a = uniform_load(args + bt.dom);
+    sweep_x_body<MP>(d, a, TileAt{bt.bx, bt.by, bt.bz, bt.blk});
 }
 template <int AX, bool MP>
 __device__ __forceinline__ void sweep_t_tiles(const Dom* __restrict__ doms, const SweepArgs* __restrict__ args,
                                               const BatchTile* __restrict__ tiles, int ntiles) {
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const BatchTile bt = tiles[t];
-        const Dom d = doms[bt.dom];
-        const SweepArgs a = args[bt.dom];
-        sweep_t_body<AX, MP>(d, a, bt.chunk, TileAt{bt.bx, bt.by, bt.bz, bt.blk});
-    }
+    const int t = blockIdx.x;
+    if (t >= ntiles) return;
+    const BatchTile bt = uniform_load(tiles + t);
+    const Dom d = uniform_load(doms + bt.dom);
+    const SweepArgs a = uniform_load(args + bt.dom);
+    sweep_t_body<AX, MP>(d, a, bt.chunk, TileAt{bt.bx, bt.by, bt.bz, bt.blk});
 }
 __global__ void __launch_bounds__(XW* XWAVES)
 k_sweep_x_batch(const Dom* doms, const SweepArgs* args, const BatchTile* tiles, int ntiles) {
@@ -793,9 +810,9 @@ void sweep_args_pack(const SweepIO& io, void* out) {
 }
 
 hipError_t launch_sweep_batch(int axis, int mixed, const Dom* doms, const void* args, const BatchTile* tiles,
-                              int ntiles, int grid, hipStream_t s) {
+                              int ntiles, hipStream_t s) {
     const SweepArgs* a = (const SweepArgs*)args;
-    const dim3 g(grid), b(64, 4, 1);
+    const dim3 g(ntiles > 0 ? ntiles : 1), b(64, 4, 1);
     if (axis == 0)
         hipLaunchKernelGGL(mixed ? k_sweep_x_batch_mixed : k_sweep_x_batch, g, b, 0, s, doms, a, tiles, ntiles);
     else if (axis == 1)

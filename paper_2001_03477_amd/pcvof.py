@@ -120,9 +120,9 @@ def lib():
         L.pcvof_batch_domain.argtypes = [_vp, C.c_int, C.POINTER(_vp)]
         L.pcvof_batch_advect_step.argtypes = [_vp, _vp, C.c_int, _vp]
         L.pcvof_batch_get_step.argtypes = [_vp, C.POINTER(C.c_long)]
-        L.pcvof_batch_set_tiles.argtypes = [_vp, _vp, _vp]
-        L.pcvof_batch_get_tiles.argtypes = [_vp, _vp, _vp, _vp]
-        L.pcvof_batch_autotune.argtypes = [_vp, _vp, C.c_int, _vp, _vp]
+        L.pcvof_batch_set_tiles.argtypes = [_vp, _vp]
+        L.pcvof_batch_get_tiles.argtypes = [_vp, _vp, _vp]
+        L.pcvof_batch_autotune.argtypes = [_vp, _vp, C.c_int, _vp]
         for nm in EXPORTS:
             f = getattr(L, nm)
             if nm not in ("pcvof_workspace_bytes", "pcvof_last_error", "pcvof_batch_workspace_bytes"):
@@ -377,23 +377,21 @@ class Batch:
         check(lib().pcvof_batch_get_step(self._b, C.byref(v)))
         return v.value
 
-    def set_tiles(self, chunk=None, grid=None):
-        ch = (C.c_int * 3)(*chunk) if chunk is not None else None
-        gr = (C.c_int * 3)(*grid) if grid is not None else None
-        check(lib().pcvof_batch_set_tiles(self._b, C.cast(ch, _vp) if ch is not None else None,
-                                          C.cast(gr, _vp) if gr is not None else None))
+    def set_tiles(self, chunk):
+        """Column chunk of the y / z sweeps: chunk[1], chunk[2] in (0, 8, 16, 32)."""
+        ch = (C.c_int * 3)(*chunk)
+        check(lib().pcvof_batch_set_tiles(self._b, C.cast(ch, _vp)))
 
     def tiles(self):
-        ch, gr, nt = (C.c_int * 3)(), (C.c_int * 3)(), (C.c_int * 3)()
-        check(lib().pcvof_batch_get_tiles(self._b, C.cast(ch, _vp), C.cast(gr, _vp), C.cast(nt, _vp)))
-        return {"chunk": list(ch), "grid": list(gr), "ntiles": list(nt)}
+        ch, nt = (C.c_int * 3)(), (C.c_int * 3)()
+        check(lib().pcvof_batch_get_tiles(self._b, C.cast(ch, _vp), C.cast(nt, _vp)))
+        return {"chunk": list(ch), "ntiles": list(nt)}
 
     def autotune(self, dt, reps: int = 3):
         arr = np.ascontiguousarray(np.asarray(dt, dtype=np.float64))
-        ch, gr = (C.c_int * 3)(), (C.c_int * 3)()
-        check(lib().pcvof_batch_autotune(self._b, arr.ctypes.data, int(reps), C.cast(ch, _vp),
-                                         C.cast(gr, _vp)))
-        return {"chunk": list(ch), "grid": list(gr)}
+        ch = (C.c_int * 3)()
+        check(lib().pcvof_batch_autotune(self._b, arr.ctypes.data, int(reps), C.cast(ch, _vp)))
+        return {"chunk": list(ch)}
 
     def close(self):
         for d in getattr(self, "domains", []):
