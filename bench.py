@@ -7,8 +7,9 @@ m'' = 0, FP64. A step is the whole hot path: prologue, three direction sweeps
 
 Prints one JSON line: whole-job cell-updates/s of the FP64 path over the timed steps
 (inputs already resident in HBM), the roofline of the dominant kernel (the sweep;
-algorithmic bytes per launch over its average duration measured with HIP events on
-the library's stream), the same run in the mixed-precision mode (rate, speedup,
+algorithmic bytes per launch over its average duration, measured with HIP events on
+the library's stream over as many steps again, right after the timed ones), the same
+run in the mixed-precision mode (rate, speedup,
 roofline, volume drift and difference from the FP64 fractions), and the oracle timed
 on the host on a bounded sample.
 """
@@ -105,16 +106,19 @@ def run(pcvof, torch, wl, precision, steps, warmup, scales):
     vol0 = float(dom.vof().sum()) * hv
     dom.steps(warmup, wl.dt, scales[:warmup])
     torch.cuda.synchronize()
-    # sweep kernel durations: HIP events recorded by the library around each sweep
-    # launch, on the stream the kernels run on, over the timed steps
-    dom.set_profiling(["sweep_x", "sweep_y", "sweep_z"][:wl.ndim])
+    # the timed steps: events on the stream around them, nothing inside
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     t_start.record(stream)
-    dom.steps(steps, wl.dt, scales[warmup:])
+    dom.steps(steps, wl.dt, scales[warmup:warmup + steps])
     t_end.record(stream)
     torch.cuda.synchronize()
     total_ms = t_start.elapsed_time(t_end)
+    # sweep kernel durations: the same number of steps again, with HIP events recorded
+    # by the library around each sweep launch on the stream the kernels run on (the
+    # events add time between launches, so they are kept out of the timed steps)
+    dom.set_profiling(["sweep_x", "sweep_y", "sweep_z"][:wl.ndim])
+    dom.steps(steps, wl.dt, scales[warmup + steps:])
     prof = dom.profile()
     dom.set_profiling(False)
     sweep_ms = np.array([prof[f"sweep_{a}"]["ms"] for a in "xyz"[:wl.ndim]])
@@ -122,7 +126,7 @@ def run(pcvof, torch, wl, precision, steps, warmup, scales):
     mixed = precision == "mixed"
     sweep_b = sum(sweep_bytes(wl, a, mixed) * sweep_n[a] for a in range(wl.ndim))
     # one untimed step with checksums for the bookkeeping terms of the drift
-    st = dom.step(wl.dt, wl.u_scale(warmup + steps), stats=True)
+    st = dom.step(wl.dt, wl.u_scale(warmup + 2 * steps), stats=True)
     vol1 = st["vol"]
     c_final = dom.vof().cpu().numpy()
     del dom
@@ -309,7 +313,7 @@ def main():
         bench_batch(args, pcvof, torch)
         return
     wl = workload(args.workload)
-    scales = np.array([wl.u_scale(k) for k in range(args.warmup + args.steps)])
+    scales = np.array([wl.u_scale(k) for k in range(args.warmup + 2 * args.steps)])
     r64 = run(pcvof, torch, wl, "fp64", args.steps, args.warmup, scales)
     c64 = r64.pop("c_final")
     torch.cuda.synchronize()

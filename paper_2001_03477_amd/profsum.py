@@ -26,7 +26,7 @@ import sqlite3
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SWEEP_SOURCES = ("sweep.hip", "common.h", "geom.h", "kernels.h")
+SWEEP_SOURCES = ("sweep.hip", "common.h", "geom.h", "geom32.h", "kernels.h")
 SWEEP_KERNELS = ("k_sweep_x", "k_sweep_t<1>", "k_sweep_t<2>")  # axis order
 
 
@@ -84,11 +84,12 @@ def trace_summary(db, command):
 
 
 def calib_value(rows, counter):
-    """The counter of the calibration copy: the largest reading among copy kernels."""
-    vals = [c[counter] for n, c in rows if "copy" in n.lower() and counter in c]
-    if not vals:
-        raise SystemExit(f"no copy kernel with {counter} in the run")
-    return max(vals)
+    """The counter of the calibration copy: the first copy kernel of the run (bench.py
+    copies the calibration buffer before anything else is copied)."""
+    for n, c in rows:
+        if "copy" in n.lower() and counter in c:
+            return c[counter]
+    raise SystemExit(f"no copy kernel with {counter} in the run")
 
 
 def traffic_summary(fetch_db, write_db, calib_mib, workload, cmd_fetch, cmd_write):
