@@ -64,7 +64,9 @@ enum { PCVOF_NORMAL_YOUNGS = 0, PCVOF_NORMAL_MYC = 1, PCVOF_NORMAL_CC = 2 };
    volume. Volume fractions, energies, flux differences, clipping, step 2 and all
    checksums stay in double precision, so volume and energy remain conserved to
    round-off; the fractions differ from the FP64 result at the level of single
-   precision rounding of the geometry. */
+   precision rounding of the geometry. The mixed-cell threshold of this mode is
+   max(eps_mixed, 1e-6): single-precision rounding of the fluxes leaves fractions of
+   order 1e-8 in cells the FP64 path leaves pure, and those are not interface cells. */
 enum { PCVOF_PREC_FP64 = 0, PCVOF_PREC_MIXED = 1 };
 
 typedef struct {

@@ -39,6 +39,7 @@ int fail(int code, const char* fmt, ...) {
     } while (0)
 
 constexpr size_t kAlign = 256;
+constexpr double kMixedEps = 1e-6;  // smallest mixed-cell threshold of the mixed-precision mode
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -91,7 +92,10 @@ pcv::Dom make_dom(const pcvof_grid& g, const pcvof_params& p) {
     d.cp_g = p.cp_g;
     d.rho_l = p.rho_l;
     d.T_gamma = p.T_gamma;
-    d.eps = p.eps_mixed;
+    // mixed precision: single-precision rounding of the fluxes leaves fractions of order
+    // 1e-8 in cells that the double-precision path leaves pure; they must not count as
+    // interface cells (step 2 would move planes through them)
+    d.eps = p.precision == PCVOF_PREC_MIXED ? fmax(p.eps_mixed, kMixedEps) : p.eps_mixed;
     d.weno_eps = p.weno_eps;
     d.normal = p.normal;
     d.wpr = (g.nx + pcv::kMaskCpwX - 1) / pcv::kMaskCpwX;
