@@ -201,14 +201,24 @@ int prof_begin(pcvof_handle* h, int cls) {
     if (!(h->prof_mask >> cls & 1)) return -1;
     hipEvent_t a = prof_event(h), b = prof_event(h);
     if (!a || !b) return -1;
-    hipEventRecord(a, h->stream);
+    (void)hipEventRecord(a, h->stream);
     h->prof_pending[cls].push_back({a, b});
     return (int)h->prof_pending[cls].size() - 1;
 }
 
 void prof_end(pcvof_handle* h, int cls, int slot) {
     if (slot < 0) return;
-    hipEventRecord(h->prof_pending[cls][slot].second, h->stream);
+    (void)hipEventRecord(h->prof_pending[cls][slot].second, h->stream);
+}
+
+// An event pair for a launch of class cls that records them itself (with the kernel's
+// dispatch); nulls when the class is not timed.
+std::pair<hipEvent_t, hipEvent_t> prof_dispatch_pair(pcvof_handle* h, int cls) {
+    if (!(h->prof_mask >> cls & 1)) return {nullptr, nullptr};
+    hipEvent_t a = prof_event(h), b = prof_event(h);
+    if (!a || !b) return {nullptr, nullptr};
+    h->prof_pending[cls].push_back({a, b});
+    return {a, b};
 }
 
 // Waits for the stream, folds the pending event pairs into the totals and recycles them.
@@ -328,13 +338,13 @@ int pcvof_create(const pcvof_grid* grid, const pcvof_params* params, void* d_wor
 int pcvof_destroy(pcvof_handle* h) {
     if (h && h->batch_view) return fail(PCVOF_ERR_STATE, "a batch domain is destroyed with its batch");
     if (!h) return fail(PCVOF_ERR_ARG, "null handle");
-    if (h->ws && h->prof_mask) hipStreamSynchronize(h->stream);
+    if (h->ws && h->prof_mask) (void)hipStreamSynchronize(h->stream);
     for (int k = 0; k < PCVOF_PROF_CLASSES; ++k)
         for (auto& pr : h->prof_pending[k]) {
-            hipEventDestroy(pr.first);
-            hipEventDestroy(pr.second);
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
         }
-    for (hipEvent_t e : h->prof_pool) hipEventDestroy(e);
+    for (hipEvent_t e : h->prof_pool) (void)hipEventDestroy(e);
     h->ws = nullptr;
     delete h;
     return PCVOF_OK;
@@ -471,9 +481,10 @@ int pcvof_sweep(pcvof_handle* h, int axis, double dt, double u_scale) {
     io.part = h->part(slot);
     io.part_stride = h->L.maxb;
     io.nblocks = &h->nb[slot];
-    const int ps = prof_begin(h, PCVOF_PROF_SWEEP_X + axis);
+    const auto ev = prof_dispatch_pair(h, PCVOF_PROF_SWEEP_X + axis);
+    io.ev_start = ev.first;
+    io.ev_stop = ev.second;
     HIP_TRY(pcv::launch_sweep(h->d, axis, io, h->stream));
-    prof_end(h, PCVOF_PROF_SWEEP_X + axis, ps);
     h->first_pending = false;
     h->cur = nxt;
     h->mask_cpw = axis == 0 ? pcv::kMaskCpwX : pcv::kMaskCpw;

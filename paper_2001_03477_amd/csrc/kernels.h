@@ -56,6 +56,8 @@ struct SweepIO {
     double* part;              // partials: quantity q of block b at part[q * part_stride + b]
     long part_stride;
     int* nblocks;              // out: blocks of the sweep kernel
+    hipEvent_t ev_start = nullptr;  // if set: events recorded with the kernel's dispatch
+    hipEvent_t ev_stop = nullptr;
 };
 // Mask of the mixed cells of c (cpw kMaskCpw), after the fractions were set.
 hipError_t launch_classify(const Dom& d, const double* c, uint64_t* mask, hipStream_t s);

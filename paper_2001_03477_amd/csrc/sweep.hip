@@ -11,6 +11,7 @@
 // the cell update, the clip, the checksum partials and the mask of the output. The
 // geometry of one wavefront overlaps with the streaming of the others on the same
 // SIMD. All floating point is double precision.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -788,8 +789,22 @@ hipError_t launch_classify(const Dom& d, const double* c, uint64_t* mask, hipStr
     return hipGetLastError();
 }
 
+// With events, the launch goes through hipExtLaunchKernelGGL, which records them with
+// the kernel's own dispatch (so that they time the kernel alone).
 template <bool MP>
-void launch_sweep_kernel(const Dom& d, int axis, const Launch& L, int chunk, const SweepArgs& a, hipStream_t s) {
+void launch_sweep_kernel(const Dom& d, int axis, const Launch& L, int chunk, const SweepArgs& a, hipStream_t s,
+                         hipEvent_t e0, hipEvent_t e1) {
+    if (e0 && e1) {
+        if (axis == 0)
+            hipExtLaunchKernelGGL(MP ? k_sweep_x_mixed : k_sweep_x, L.grid, L.block, 0, s, e0, e1, 0, d, a);
+        else if (axis == 1)
+            hipExtLaunchKernelGGL(MP ? k_sweep_t_mixed<1> : k_sweep_t<1>, L.grid, L.block, 0, s, e0, e1, 0, d, a,
+                                  chunk);
+        else
+            hipExtLaunchKernelGGL(MP ? k_sweep_t_mixed<2> : k_sweep_t<2>, L.grid, L.block, 0, s, e0, e1, 0, d, a,
+                                  chunk);
+        return;
+    }
     if (axis == 0)
         hipLaunchKernelGGL(MP ? k_sweep_x_mixed : k_sweep_x, L.grid, L.block, 0, s, d, a);
     else if (axis == 1)
@@ -843,9 +858,9 @@ hipError_t launch_sweep(const Dom& d, int axis, const SweepIO& io, hipStream_t s
     SweepArgs a{io.c,   io.e,    io.mask, io.mask_cpw, io.mask_out, io.cc,   io.ec,          io.vel,
                 io.kfac, io.fgeo, io.c_out, io.e_out,   io.part,     io.part_stride, io.first};
     if (io.mixed)
-        launch_sweep_kernel<true>(d, axis, L, chunk, a, s);
+        launch_sweep_kernel<true>(d, axis, L, chunk, a, s, io.ev_start, io.ev_stop);
     else
-        launch_sweep_kernel<false>(d, axis, L, chunk, a, s);
+        launch_sweep_kernel<false>(d, axis, L, chunk, a, s, io.ev_start, io.ev_stop);
     *io.nblocks = L.nblocks;
     return hipGetLastError();
 }
