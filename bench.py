@@ -35,6 +35,7 @@ SWEEP_BYTES_PER_FACE = 8
 # mixed precision: e_c (4) and the face velocity (4) in single precision
 SWEEP_BYTES_PER_CELL_MIXED = 8 + 8 + 4 + 1 + 8 + 8
 SWEEP_BYTES_PER_FACE_MIXED = 4
+CHECKED_STEPS = 20  # untimed steps with checksums for the bookkeeping residue
 
 
 def workload(name):
@@ -87,6 +88,26 @@ def recorded_traffic(wl, sweep_n):
     return float(tot / sweep_n.sum())
 
 
+def copy_bandwidth(torch, mib=1024, reps=10):
+    """GB/s of a device-to-device copy of mib MiB (bytes read + written per second), a
+    measured reference beside the specified peak."""
+    n = mib * (1 << 20) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    t1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * n * 8 * reps / (t0.elapsed_time(t1) * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def run(pcvof, torch, wl, precision, steps, warmup, scales):
     """warmup + steps steps of the workload in the given precision: the timed steps
     bracketed by events on the stream, the sweep kernels timed by the library's events,
@@ -125,14 +146,26 @@ def run(pcvof, torch, wl, precision, steps, warmup, scales):
     sweep_n = np.array([prof[f"sweep_{a}"]["launches"] for a in "xyz"[:wl.ndim]])
     mixed = precision == "mixed"
     sweep_b = sum(sweep_bytes(wl, a, mixed) * sweep_n[a] for a in range(wl.ndim))
-    # one untimed step with checksums for the bookkeeping terms of the drift
-    st = dom.step(wl.dt, wl.u_scale(warmup + 2 * steps), stats=True)
+    # checked steps (untimed, with checksums): the change of total volume and energy net
+    # of the reported boundary, source, clip and phase-change terms
+    k0 = warmup + 2 * steps
+    st = dom.step(wl.dt, wl.u_scale(k0), stats=True)
+    v_prev, e_prev, e0 = st["vol"], st["energy"], abs(st["energy"])
+    v_res = e_res = 0.0
+    for k in range(CHECKED_STEPS):
+        st = dom.step(wl.dt, wl.u_scale(k0 + 1 + k), stats=True)
+        v_res += st["vol"] - v_prev - (-st["vol_bnd_out"] + st["vol_src"] + st["vol_clip"] + st["vol_phase"])
+        e_res += st["energy"] - e_prev - (-st["energy_bnd_out"] + st["energy_src"] + st["energy_clip"]
+                                          + st["energy_phase"])
+        v_prev, e_prev = st["vol"], st["energy"]
     vol1 = st["vol"]
     c_final = dom.vof().cpu().numpy()
     del dom
     torch.cuda.empty_cache()
     return {"total_ms": total_ms, "sweep_ms": sweep_ms, "sweep_n": sweep_n, "prof": prof,
-            "sweep_bytes": sweep_b, "volume_drift": abs(vol1 - vol0) / vol0, "c_final": c_final}
+            "sweep_bytes": sweep_b, "volume_drift": abs(vol1 - vol0) / vol0,
+            "unexplained": {"steps": CHECKED_STEPS, "volume": abs(v_res) / vol0, "energy": abs(e_res) / e0},
+            "c_final": c_final}
 
 
 def run_batch(pcvof, torch, wls, precision, steps, warmup, use_graph, autotune):
@@ -309,6 +342,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    copy_gbs = None if args.calibration_copy_mib > 0 else copy_bandwidth(torch)
     if args.workload == "batch64":
         bench_batch(args, pcvof, torch)
         return
@@ -341,12 +375,14 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(wl, sweep_n),
+                     "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs if copy_gbs else None,
                      "kernel": "k_sweep_x / k_sweep_t<1> / k_sweep_t<2>",
                      "avg_launch_ms": avg_sweep_ms,
                      "per_axis_ms": [float(t / n) for t, n in zip(sweep_ms, sweep_n)],
                      "bytes_per_cell": SWEEP_BYTES_PER_CELL + SWEEP_BYTES_PER_FACE},
         "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items() if v["launches"]},
         "volume_drift": r64["volume_drift"],
+        "drift_net_of_reported_terms": r64["unexplained"],
     }
     if rmx is not None:
         cmx = rmx.pop("c_final")
@@ -361,6 +397,7 @@ def main():
                          "frac": mx_achieved / HBM_PEAK_GBS,
                          "bytes_per_cell": SWEEP_BYTES_PER_CELL_MIXED + SWEEP_BYTES_PER_FACE_MIXED},
             "volume_drift": rmx["volume_drift"],
+            "drift_net_of_reported_terms": rmx["unexplained"],
             "c_vs_fp64": {"max_abs": float(dc.max()), "l1_rel": float(dc.sum() / np.abs(c64).sum())},
         }
     if not args.no_cpu_baseline:
