@@ -185,12 +185,15 @@ __device__ __forceinline__ void face_energy(const Dom& d, double lam, double F, 
     E = sg * ((d.cp_l * F + d.cp_g * (L - F)) * Tf);
 }
 
-// x sweep: each wavefront walks XRPW row segments of XC = 63 cells. A segment is
+// x sweep: each wavefront walks XRPW rows of one segment of XC = 63 cells (block
+// (bx, by, z): segment bx of rows (4 by + wave) XRPW .. + XRPW - 1 of plane z). A segment is
 // staged in the wavefront's own LDS row with a 3-cell halo on both sides (no block
 // barrier: a wavefront's LDS accesses complete in order); lane l computes the flux of
 // face x0 + l (64 faces for 63 cells) and cell l takes its right face from lane l + 1.
 // The next row's loads are issued before the current row is computed, and the
-// checksums are reduced once per wavefront.
+// checksums are reduced once per wavefront. Indices that depend on the lane's position
+// are recomputed per row rather than kept, which lets the kernel fit five wavefronts
+// per SIMD without spilling.
 constexpr int XW = 64;
 constexpr int XC = XW - 1;
 constexpr int XWAVES = 4;
@@ -221,20 +224,14 @@ __device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a, c
     __shared__ double s_T[XWAVES][XS];
     __shared__ double s_F[XWAVES][XRPW][XW];                 // liquid flux of mixed donors
     __shared__ unsigned short s_work[XWAVES][XRPW * XW];    // candidate faces (row:lane)
-    const int lane = threadIdx.x, wave = threadIdx.y;
-    const int bx = tl.bx, by = tl.by, z = tl.bz;
-    const int x0 = bx * XC;
-    const int y0 = (by * XWAVES + wave) * XRPW;
-    const int x = x0 + lane;
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int lane = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    const int nx = d.n[0];
+    const int sx = tl.bx;  // the wavefront's segment
+    const int y0 = (tl.by * XWAVES + wave) * XRPW;
     const int nrows = max(0, min(XRPW, d.n[1] - y0));  // uniform over the wavefront
-    const int xi0 = wrap(x0 - XH + lane, d.n[0], d.bc[0]);
-    const int xi1 = wrap(x0 - XH + lane + XW, d.n[0], d.bc[0]);
-    const bool two = lane + XW < XS;  // lanes 0..4 stage a second position (LDS 64 .. 68)
-    const bool own = lane < XC && x < d.n[0];
-    const bool face = x <= d.n[0];
-    auto row_at = [&](int y) { return ((long)z * d.n[1] + y) * d.n[0]; };
-    auto face_row_at = [&](int y) { return ((long)z * d.n[1] + y) * (d.n[0] + 1); };
+    const int R0 = tl.bz * d.n[1] + y0;                 // row index (z ny + y) of row 0
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 
     // Geometry, first pass: the faces x0 .. x0+63 of the wavefront's rows with a mixed
     // cell on either side (lane = face offset, item = row:lane), read from the mask of
@@ -243,8 +240,9 @@ __device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a, c
     unsigned nwork = 0;
     {
         const int cpw = a.mask_cpw;
-        const int xl = wrap(x - 1, d.n[0], d.bc[0]);
-        const int xr = wrap(x0 + XW - 1, d.n[0], d.bc[0]);  // lane 63's right cell
+        const int x0 = sx * XC;
+        const int xl = wrap(x0 + lane - 1, nx, d.bc[0]);
+        const int xr = wrap(x0 + XW - 1, nx, d.bc[0]);  // lane 63's right cell
         const int kl = xl / cpw, bl = xl - kl * cpw;
         const int kr = xr / cpw, br = xr - kr * cpw;
         uint64_t g_wl[XRPW], g_wr[XRPW];
@@ -253,7 +251,7 @@ __device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a, c
             g_wl[r] = 0ull;
             g_wr[r] = 0ull;
             if (r < nrows) {
-                const long rw = ((long)z * d.n[1] + y0 + r) * d.wpr;
+                const long rw = (long)(R0 + r) * d.wpr;
                 g_wl[r] = a.mask[rw + kl];
                 if (lane == XW - 1) g_wr[r] = a.mask[rw + kr];
             }
@@ -263,7 +261,7 @@ __device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a, c
             const int ml = (int)((g_wl[r] >> bl) & 1ull);
             const int right = __shfl_down(ml, 1, 64);  // cell x of lane l is cell x-1 of lane l+1
             const int mr = lane == XW - 1 ? (int)((g_wr[r] >> br) & 1ull) : right;
-            const bool need = r < nrows && face && (ml | mr);
+            const bool need = r < nrows && x0 + lane <= nx && (ml | mr);
             work_append(need, (unsigned short)((r << 6) | lane), s_work[wave], nwork);
         }
     }
@@ -272,46 +270,53 @@ __device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a, c
     for (unsigned i = lane; i < nwork; i += XW) {
         const unsigned it = s_work[wave][i];
         const int r = it >> 6, l = it & (XW - 1);
-        const int y = y0 + r;
-        const int xf = x0 + l;
-        const double lam = vel_at<MP>(a, face_row_at(y) + xf) * a.kfac;
+        const int R = R0 + r;
+        const int xf = sx * XC + l;
+        const double lam = vel_at<MP>(a, (long)R * (nx + 1) + xf) * a.kfac;
         if (lam == 0.0) continue;
         const int xd = lam > 0.0 ? xf - 1 : xf;
-        const double cd = a.c[row_at(y) + wrap(xd, d.n[0], d.bc[0])];
+        const double cd = a.c[(long)R * nx + wrap(xd, nx, d.bc[0])];
         if (!mixed(d, cd)) continue;
-        s_F[wave][r][l] = donor_flux<0, MP>(d, a.c, xd, y, z, cd, lam);
+        s_F[wave][r][l] = donor_flux<0, MP>(d, a.c, xd, y0 + r, tl.bz, cd, lam);
     }
     __builtin_amdgcn_wave_barrier();
     using T = typename Prec<MP>::T;
     double pc0 = 0, pe0 = 0, pc1 = 0, pe1 = 0, pev = 0;
     T pu = 0, pec = 0;
     uint8_t pcc = 0;
-    auto prefetch = [&](int y) {
-        const long rb = ((long)z * d.n[1] + y) * d.n[0];
-        const long fr = ((long)z * d.n[1] + y) * (d.n[0] + 1);
+    const bool two = lane + XW < XS;  // lanes 0..4 stage a second position (LDS 64 .. 68)
+    auto prefetch = [&](int R) {
+        const int x0 = sx * XC, x = x0 + lane;
+        const long rb = (long)R * nx;
+        const long fr = (long)R * (nx + 1);
+        const int xi0 = wrap(x0 - XH + lane, nx, d.bc[0]);
         pc0 = a.c[rb + xi0];
         pe0 = a.e[rb + xi0];
         if (two) {
+            const int xi1 = wrap(x0 - XH + lane + XW, nx, d.bc[0]);
             pc1 = a.c[rb + xi1];
             pe1 = a.e[rb + xi1];
         }
-        if (own) {
+        if (lane < XC && x < nx) {
             pev = a.e[rb + x];
             if (!a.first) {
                 pcc = a.cc[rb + x];
                 pec = ec_at<MP>(a, rb + x);
             }
         }
-        if (face) pu = vel_at<MP>(a, fr + x);
+        if (x <= nx) pu = vel_at<MP>(a, fr + x);
     };
-    if (nrows > 0) prefetch(y0);
+    if (nrows > 0) prefetch(R0);
     for (int r = 0; r < nrows; ++r) {
-        const int y = y0 + r;
-        const long rowbase = row_at(y);
+        const int R = R0 + r;
+        const int x = sx * XC + lane;
+        const bool own = lane < XC && x < nx;
+        const bool face = x <= nx;
+        const long rowbase = (long)R * nx;
         const double c0 = pc0, e0 = pe0, c1 = pc1, e1 = pe1, ev_own = pev;
         const double u = (double)pu, ec_own = (double)pec;
         const uint8_t cc_own = pcc;
-        if (r + 1 < nrows) prefetch(y + 1);
+        if (r + 1 < nrows) prefetch(R + 1);
         s_c[wave][lane] = c0;
         s_T[wave][lane] = e0 / cp_of(d, c0);
         if (two) {
@@ -348,7 +353,7 @@ __device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a, c
                     acc[2] -= Phi;
                     acc[3] -= E;
                 }
-                if (x == d.n[0] - 1) {
+                if (x == nx - 1) {
                     acc[2] += PhiR;
                     acc[3] += ER;
                 }
@@ -356,7 +361,7 @@ __device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a, c
         }
         // mask of the output: the segment's 63 cells are one word (cpw = 63)
         const unsigned long long bits = __ballot(mx);
-        if (lane == 0) a.mask_out[((long)z * d.n[1] + y) * d.wpr + bx] = bits;
+        if (lane == 0) a.mask_out[(long)R * d.wpr + sx] = bits;
         __builtin_amdgcn_wave_barrier();
     }
     block_sum8<XWAVES>(acc, a.part + tl.blk, a.part_stride);
@@ -563,13 +568,16 @@ __device__ __forceinline__ void sweep_t_body(const Dom& d, const SweepArgs& a, i
     block_sum8<4>(acc, a.part + tl.blk, a.part_stride);
 }
 
-// Kernel entry points. The mixed-precision bodies fit fewer registers per lane, so
-// their launches ask for five (x) and four (y, z) wavefronts per SIMD; the double
-// precision bodies would spill at those limits and keep the compiler's allocation.
+// Kernel entry points. The x sweeps ask for five wavefronts per SIMD (both precisions
+// fit without spilling); the mixed-precision y / z sweeps ask for four, while the
+// double-precision ones would spill at that limit and keep the compiler's allocation.
 __device__ __forceinline__ TileAt own_tile() {
     return {(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z, block_linear()};
 }
-__global__ void __launch_bounds__(XW* XWAVES) k_sweep_x(Dom d, SweepArgs a) { sweep_x_body<false>(d, a, own_tile()); }
+__global__ void __launch_bounds__(XW* XWAVES) __attribute__((amdgpu_waves_per_eu(5, 8)))
+k_sweep_x(Dom d, SweepArgs a) {
+    sweep_x_body<false>(d, a, own_tile());
+}
 __global__ void __launch_bounds__(XW* XWAVES) __attribute__((amdgpu_waves_per_eu(5, 8)))
 k_sweep_x_mixed(Dom d, SweepArgs a) {
     sweep_x_body<true>(d, a, own_tile());
@@ -627,7 +635,7 @@ __device__ __forceinline__ void sweep_t_tiles(const Dom* __restrict__ doms, cons
     const SweepArgs a = uniform_load(args + bt.dom);
     sweep_t_body<AX, MP>(d, a, bt.chunk, TileAt{bt.bx, bt.by, bt.bz, bt.blk});
 }
-__global__ void __launch_bounds__(XW* XWAVES)
+__global__ void __launch_bounds__(XW* XWAVES) __attribute__((amdgpu_waves_per_eu(5, 8)))
 k_sweep_x_batch(const Dom* doms, const SweepArgs* args, const BatchTile* tiles, int ntiles) {
     sweep_x_tiles<false>(doms, args, tiles, ntiles);
 }
@@ -749,16 +757,16 @@ Launch cell_launch(const Dom& d) {
     return L;
 }
 
-// Launch shape of a sweep. x: XRPW row segments of 63 cells per wavefront, four
-// wavefronts per block. y, z: 64 x 4 columns per block marching over a chunk of the
-// sweep axis; the chunk is the longest of TCH, TCH / 2, ... 8 cells that still gives
-// >= 2048 blocks.
+// Launch shape of a sweep. x: XRPW rows of a 63-cell segment per wavefront, four
+// wavefronts per block. y, z: 64 x 4 columns
+// per block marching over a chunk of the sweep axis; the chunk is the longest of TCH,
+// TCH / 2, ... 8 cells that still gives >= 2048 blocks.
 Launch sweep_launch(const Dom& d, int axis, int* chunk) {
     Launch L;
     L.block = dim3(64, 4, 1);
     const int nz = d.ndim == 2 ? 1 : d.n[2];
     if (axis == 0) {
-        L.grid = dim3((d.n[0] + XC - 1) / XC, (d.n[1] + XWAVES * XRPW - 1) / (XWAVES * XRPW), nz);
+        L.grid = dim3(d.wpr, (d.n[1] + XWAVES * XRPW - 1) / (XWAVES * XRPW), nz);
         *chunk = 0;
     } else {
         const int nt = axis == 1 ? nz : d.n[1];
