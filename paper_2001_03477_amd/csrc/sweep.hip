@@ -447,12 +447,16 @@ __device__ __forceinline__ void sweep_t_body(const Dom& d, const SweepArgs& a, i
     // update window, cells f+3, f+4 are loads in flight; at each face the load of cell
     // f+5 is issued into the slot of cell f-3 (three faces ahead, so that many loads
     // stay in flight per wavefront). Face velocities and the frozen fields of the cell
-    // to update use rings of four. The loop is unrolled eight times so that every slot
-    // is a compile-time register.
+    // to update use rings of VR slots, loaded VR faces ahead: four in the mixed mode,
+    // two in double precision, where that keeps the kernel within 128 registers per lane
+    // (four wavefronts per SIMD instead of three). The loop is unrolled eight times so
+    // that every slot is a compile-time register.
     constexpr int R = 8;
+    constexpr int VR = MP ? 4 : 2;
+    static_assert(R % VR == 0, "the unrolled loop keeps the ring slots fixed");
     double cr[R], er[R], Tw[R];
-    typename Prec<MP>::T vr[4], ecr[4];  // storage type until used
-    uint8_t ccr[4];
+    typename Prec<MP>::T vr[VR], ecr[VR];  // storage type until used
+    uint8_t ccr[VR];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         cr[j] = 0.0;
@@ -465,7 +469,7 @@ __device__ __forceinline__ void sweep_t_body(const Dom& d, const SweepArgs& a, i
         }
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < VR; ++j) {
         vr[j] = 0.0;
         ecr[j] = 0.0;
         ccr[j] = 0;
@@ -487,7 +491,7 @@ __device__ __forceinline__ void sweep_t_body(const Dom& d, const SweepArgs& a, i
         constexpr int K = decltype(kc)::value;
         constexpr int J0 = K % R, J1 = (K + 1) % R, J2 = (K + 2) % R, J3 = (K + 3) % R, J4 = (K + 4) % R,
                       J5 = (K + 5) % R;
-        constexpr int V = K % 4;
+        constexpr int V = K % VR;
         Tw[J5] = ok ? er[J5] / cp_of(d, cr[J5]) : 0.0;
         const double lam = ok ? (double)vr[V] * a.kfac : 0.0;
         double Phi = 0.0, E = 0.0;
@@ -531,18 +535,18 @@ __device__ __forceinline__ void sweep_t_body(const Dom& d, const SweepArgs& a, i
         PhiP = Phi;
         EP = E;
         lamP = lam;
-        // loads three faces ahead into the slots just released
+        // loads ahead into the slots just released
         if (ok) {
             if (f + 5 - 2 <= s1) {  // cell f+5 enters the window at face f+3
                 const long id = cell_id(f + 5);
                 cr[J0] = a.c[id];
                 er[J0] = a.e[id];
             }
-            if (f + 4 <= s1) {
-                vr[V] = vel_at<MP>(a, fbase + (long)(f + 4) * fstride);
+            if (f + VR <= s1) {
+                vr[V] = vel_at<MP>(a, fbase + (long)(f + VR) * fstride);
                 if (!a.first) {
-                    ccr[V] = a.cc[base + (long)(f + 3) * stride];
-                    ecr[V] = ec_at<MP>(a, base + (long)(f + 3) * stride);
+                    ccr[V] = a.cc[base + (long)(f + VR - 1) * stride];
+                    ecr[V] = ec_at<MP>(a, base + (long)(f + VR - 1) * stride);
                 }
             }
         }
