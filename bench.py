@@ -284,6 +284,60 @@ def bench_batch(args, pcvof, torch):
     print(json.dumps(out), flush=True)
 
 
+def energy_flux_ablation(pcvof, torch, steps=10, timed_steps=50):
+    """Conservative (eq. disc_et_adv) against non-conservative (eq. disc_et_adv_noncons)
+    energy fluxes of section 3.4.1 at the water heat-capacity ratio of about 3240: 30
+    seeded droplets in a 128^3 periodic box under a random divergence-free velocity,
+    with a uniform temperature T0 = 1, which the exact solution keeps. Per mode: the
+    largest temperature error after `steps` steps (everywhere and in interface cells),
+    the change of total energy net of the reported boundary, dilatation and clip terms,
+    and the throughput of `timed_steps` more steps. The error is taken after a few steps
+    because WENO5 face values in a single explicit stage amplify high-wavenumber
+    round-off (about 6% per sweep at CFL 0.3 for the linear weights): without the
+    paper's diffusion step, the round-off of any run grows to visible levels after a few
+    tens of steps."""
+    from paper_2001_03477_amd import workloads as W
+    wl = W.droplets_3d(128, ndrops=30, seed=9, rmin=4.0, rmax=12.0)
+    T0 = 1.0
+    wl.e = (wl.cp_l * wl.c + wl.cp_g * (1.0 - wl.c)) * T0
+    hv = wl.h ** 3
+    e_tot0 = math.fsum(wl.e.ravel().tolist()) * hv
+    out = {"workload": "droplets3d_128: 30 drops, C_pl/C_pg = 4.039e6/1.248e3, uniform T",
+           "steps": steps, "timed_steps": timed_steps}
+    for mode in ("conservative", "nonconservative"):
+        spec = pcvof.DomainSpec(shape=wl.shape, h=wl.h, ndim=3, bc=wl.bc, cp_l=wl.cp_l, cp_g=wl.cp_g,
+                                energy_flux=mode)
+        d = pcvof.Domain(spec)
+        d.set_vof(wl.c)
+        d.set_energy(wl.e)
+        d.set_velocity(wl.u, wl.v, wl.w)
+        prev, res = e_tot0, 0.0
+        for _ in range(steps):
+            st = d.step(wl.dt, 1.0, stats=True)
+            res += st["energy"] - prev - (-st["energy_bnd_out"] + st["energy_src"] + st["energy_clip"]
+                                          + st["energy_phase"])
+            prev = st["energy"]
+        T = d.temperature().cpu().numpy()
+        c = d.vof().cpu().numpy()
+        iface = (c > 0.01) & (c < 0.99)
+        err = np.abs(T - T0) / T0
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(timed_steps):
+            d.step(wl.dt, 1.0)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        out[mode] = {"T_max_rel_err": float(err.max()), "T_max_rel_err_interface": float(err[iface].max()),
+                     "T_mean_rel_err_interface": float(err[iface].mean()),
+                     "energy_change_net_of_reported_terms_rel": abs(res) / abs(e_tot0),
+                     "value": wl.ncells * timed_steps / (ms * 1e-3), "unit": "cell-updates/s"}
+        del d
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(wl, budget_s=15.0, max_side=128):
     """The oracle on the host: whole steps of the workload until the budget is used (at
     least one step). Domains larger than max_side per axis are sampled: the oracle
@@ -322,6 +376,8 @@ def main():
     ap.add_argument("--workload", default="leveque128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64-only", action="store_true", help="skip the mixed-precision run")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the conservative / non-conservative energy flux comparison")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="first copy this many MiB device to device, a kernel of known traffic "
                          "for scaling the HBM byte counters of a profiler run")
@@ -400,6 +456,8 @@ def main():
             "drift_net_of_reported_terms": rmx["unexplained"],
             "c_vs_fp64": {"max_abs": float(dc.max()), "l1_rel": float(dc.sum() / np.abs(c64).sum())},
         }
+    if not args.no_ablation and args.workload == "leveque128":
+        out["energy_flux_ablation"] = energy_flux_ablation(pcvof, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

@@ -68,6 +68,16 @@ enum { PCVOF_NORMAL_YOUNGS = 0, PCVOF_NORMAL_MYC = 1, PCVOF_NORMAL_CC = 2 };
    max(eps_mixed, 1e-6): single-precision rounding of the fluxes leaves fractions of
    order 1e-8 in cells the FP64 path leaves pure, and those are not interface cells. */
 enum { PCVOF_PREC_FP64 = 0, PCVOF_PREC_MIXED = 1 };
+/* Energy flux of the sweeps (section 3.4.1). CONSERVATIVE (eq. disc_et_adv): the face
+   carries the fluxed heat capacity of the geometric liquid and gas volumes times the
+   WENO5 face temperature, E_f = sgn(lambda) [C_pl F + C_pg (|lambda| - F)] T_f, so that
+   the energy is conserved and a uniform temperature stays uniform.
+   NONCONSERVATIVE (eq. disc_et_adv_noncons, the approximation the paper argues
+   against): the face carries lambda T_f and each cell multiplies the difference of its
+   two faces by its own heat capacity C_p(c) of the current sweep; energy is then not
+   conserved (stats.energy no longer obeys the bookkeeping identity) and temperatures
+   near the interface drift. Provided as an ablation of the conservative scheme. */
+enum { PCVOF_EFLUX_CONSERVATIVE = 0, PCVOF_EFLUX_NONCONSERVATIVE = 1 };
 
 typedef struct {
     int ndim;        /* 2 or 3 */
@@ -86,6 +96,7 @@ typedef struct {
     double cfl_max;     /* largest admissible face CFL number (0.5) */
     int normal;         /* PCVOF_NORMAL_*: interface normal estimator (MYC per section 3.2) */
     int precision;      /* PCVOF_PREC_* */
+    int energy_flux;    /* PCVOF_EFLUX_* (CONSERVATIVE is the paper's scheme) */
 } pcvof_params;
 
 /* Checksums of one step (cell volume hv = h^ndim). The change of total volume obeys

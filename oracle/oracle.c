@@ -380,7 +380,9 @@ void or_prologue(const or_grid* g, const or_params* p, const double* c, const do
 /* Face flux of one sweep: the liquid volume F through the face (section 3.3) and the
    energy flux E = sgn(lam) [C_pl F + C_pg (|lam| - F)] T_f, i.e. the fluxed heat
    capacity weighted by the fluxed liquid and gas volumes times the WENO5 face
-   temperature (section 3.4.1). Position (x,y,z) is the cell right of the face. */
+   temperature (section 3.4.1, eq. disc_et_adv). With the non-conservative energy flux
+   (eq. disc_et_adv_noncons) the face carries only lam T_f; each cell multiplies it by
+   its own heat capacity in or_sweep. Position (x,y,z) is the cell right of the face. */
 static void face_flux(const or_grid* g, const or_params* p, int a, const double* c,
                       const double* e, double lam, int x, int y, int z, double* Phi,
                       double* E) {
@@ -412,7 +414,10 @@ static void face_flux(const or_grid* g, const or_params* p, int a, const double*
     double Tf = or_weno5(T, p->weno_eps);
     double sg = lam > 0.0 ? 1.0 : -1.0;
     *Phi = sg * F;
-    *E = sg * ((p->cp_l * F + p->cp_g * (L - F)) * Tf);
+    if (p->energy_flux == 1)
+        *E = lam * Tf;
+    else
+        *E = sg * ((p->cp_l * F + p->cp_g * (L - F)) * Tf);
 }
 
 int or_sweep(const or_grid* g, const or_params* p, int a, const double* c, const double* e,
@@ -434,6 +439,13 @@ int or_sweep(const or_grid* g, const or_params* p, int a, const double* c, const
                 face_flux(g, p, a, c, e, lamL, pos[0], pos[1], pos[2], &PhiL, &EL);
                 face_flux(g, p, a, c, e, lamR, posR[0], posR[1], posR[2], &PhiR, &ER);
                 long id = cell_id(g, x, y, z);
+                if (p->energy_flux == 1) {
+                    /* eq. disc_et_adv_noncons: the cell's own heat capacity (of the
+                       current sweep's state) times the temperature fluxes */
+                    double k = cp_of(p, c[id]);
+                    EL *= k;
+                    ER *= k;
+                }
                 double dl = lamR - lamL;
                 double cn = c[id] - (PhiR - PhiL) + cc[id] * dl;
                 double en = e[id] - (ER - EL) + ec[id] * dl;

@@ -35,6 +35,8 @@ typedef struct {
     double eps_mixed;    /* mixed-cell threshold eps < c < 1-eps (section 3.1: 1e-12) */
     double weno_eps;     /* WENO5 epsilon of the nonlinear weights */
     int normal;          /* 0 Youngs, 1 mixed Youngs-centred (MYC), 2 centred columns only */
+    int energy_flux;     /* 0 conservative fluxes (section 3.4.1, eq. disc_et_adv); 1 the
+                            non-conservative approximation of eq. disc_et_adv_noncons */
 } or_params;
 
 typedef struct {

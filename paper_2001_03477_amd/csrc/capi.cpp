@@ -77,6 +77,7 @@ bool params_ok(const pcvof_params* p) {
     if (!(p->cfl_max > 0.0 && p->cfl_max <= 1.0)) return false;
     if (p->normal < 0 || p->normal > 2) return false;
     if (p->precision != PCVOF_PREC_FP64 && p->precision != PCVOF_PREC_MIXED) return false;
+    if (p->energy_flux != PCVOF_EFLUX_CONSERVATIVE && p->energy_flux != PCVOF_EFLUX_NONCONSERVATIVE) return false;
     return true;
 }
 
@@ -99,6 +100,7 @@ pcv::Dom make_dom(const pcvof_grid& g, const pcvof_params& p) {
     d.weno_eps = p.weno_eps;
     d.normal = p.normal;
     d.wpr = (g.nx + pcv::kMaskCpwX - 1) / pcv::kMaskCpwX;
+    d.ncons = p.energy_flux == PCVOF_EFLUX_NONCONSERVATIVE ? 1 : 0;
     return d;
 }
 

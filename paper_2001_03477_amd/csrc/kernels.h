@@ -15,6 +15,7 @@ struct Dom {
     double cp_l, cp_g, rho_l, T_gamma, eps, weno_eps;
     int normal;
     int wpr;       // words per row of the mixed-cell masks: ceil(n[0] / 63)
+    int ncons;     // 1: non-conservative energy flux (cells scale lambda T_f by their C_p)
 };
 
 // Mixed-cell mask of a state: one bit per cell, rows of wpr 64-bit words, word k of a

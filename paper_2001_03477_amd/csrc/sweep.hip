@@ -176,13 +176,29 @@ __device__ __forceinline__ double update_cell(const Dom& d, const SweepArgs& a, 
 
 // Volume and energy fluxes through a face with CFL number lam, given the liquid volume
 // F of the upwind region and the WENO5 face temperature Tf: Phi = sgn(lam) F and
-// E = sgn(lam) [C_pl F + C_pg (|lam| - F)] Tf (section 3.4.1).
+// E = sgn(lam) [C_pl F + C_pg (|lam| - F)] Tf (section 3.4.1, eq. disc_et_adv). With the
+// non-conservative energy flux (eq. disc_et_adv_noncons) E = lam Tf, which each cell
+// scales by its own heat capacity (cell_energy_flux).
 __device__ __forceinline__ void face_energy(const Dom& d, double lam, double F, double Tf, double& Phi,
                                             double& E) {
     const double L = fabs(lam);
     const double sg = lam > 0.0 ? 1.0 : -1.0;
     Phi = sg * F;
-    E = sg * ((d.cp_l * F + d.cp_g * (L - F)) * Tf);
+    if (d.ncons)
+        E = lam * Tf;
+    else
+        E = sg * ((d.cp_l * F + d.cp_g * (L - F)) * Tf);
+}
+
+// The energy fluxes through the left and right faces of a cell with fraction cv as the
+// cell sees them: as computed (conservative), or scaled by the cell's own heat capacity
+// (non-conservative).
+__device__ __forceinline__ void cell_energy_flux(const Dom& d, double cv, double& EL, double& ER) {
+    if (d.ncons) {
+        const double k = cp_of(d, cv);
+        EL *= k;
+        ER *= k;
+    }
 }
 
 // x sweep: each wavefront walks XRPW rows of one segment of XC = 63 cells (block
@@ -345,17 +361,20 @@ __device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a, c
         const double lamR = __shfl_down(lam, 1, 64);
         bool mx = false;
         if (own) {
-            const double cn = update_cell<MP>(d, a, rowbase + x, s_c[wave][lane + XH], ev_own, s_T[wave][lane + XH],
-                                          lam, lamR, Phi, PhiR, E, ER, cc_own, ec_own, acc);
+            const double cv = s_c[wave][lane + XH];
+            double EL = E, ERc = ER;
+            cell_energy_flux(d, cv, EL, ERc);
+            const double cn = update_cell<MP>(d, a, rowbase + x, cv, ev_own, s_T[wave][lane + XH], lam, lamR, Phi,
+                                              PhiR, EL, ERc, cc_own, ec_own, acc);
             mx = mixed(d, cn);
             if (d.bc[0] == 1) {
                 if (x == 0) {
                     acc[2] -= Phi;
-                    acc[3] -= E;
+                    acc[3] -= EL;
                 }
                 if (x == nx - 1) {
                     acc[2] += PhiR;
-                    acc[3] += ER;
+                    acc[3] += ERc;
                 }
             }
         }
@@ -510,18 +529,19 @@ __device__ __forceinline__ void sweep_t_body(const Dom& d, const SweepArgs& a, i
         if (ok && f > s0) {
             const int cell = f - 1;
             const long id = base + (long)cell * stride;
-            const double cn =
-                update_cell<MP>(d, a, id, cr[J2], er[J2], Tw[J2], lamP, lam, PhiP, Phi, EP, E, ccr[V],
-                                (double)ecr[V], acc);
+            double EL = EP, ER = E;
+            cell_energy_flux(d, cr[J2], EL, ER);
+            const double cn = update_cell<MP>(d, a, id, cr[J2], er[J2], Tw[J2], lamP, lam, PhiP, Phi, EL, ER,
+                                              ccr[V], (double)ecr[V], acc);
             mx = mixed(d, cn);
             if (d.bc[AX] == 1) {
                 if (cell == 0) {
                     acc[2] -= PhiP;
-                    acc[3] -= EP;
+                    acc[3] -= EL;
                 }
                 if (cell == ns - 1) {
                     acc[2] += Phi;
-                    acc[3] += E;
+                    acc[3] += ER;
                 }
             }
         }
@@ -762,9 +782,10 @@ Launch cell_launch(const Dom& d) {
 }
 
 // Launch shape of a sweep. x: XRPW rows of a 63-cell segment per wavefront, four
-// wavefronts per block. y, z: 64 x 4 columns
-// per block marching over a chunk of the sweep axis; the chunk is the longest of TCH,
-// TCH / 2, ... 8 cells that still gives >= 2048 blocks.
+// wavefronts per block. y, z: 64 x 4 columns per block marching over a chunk of the
+// sweep axis; the chunk is the longest of TCH, TCH / 2, ... 8 cells that still gives
+// >= 4096 blocks (four rounds of blocks at four wavefronts per SIMD on 256 CUs; fewer,
+// longer columns leave the last round partly idle).
 Launch sweep_launch(const Dom& d, int axis, int* chunk) {
     Launch L;
     L.block = dim3(64, 4, 1);
@@ -777,7 +798,7 @@ Launch sweep_launch(const Dom& d, int axis, int* chunk) {
         const long bxy = (long)((d.n[0] + 63) / 64) * ((nt + 3) / 4);
         const int ns = d.n[axis];
         int ch = TCH;
-        while (ch > 8 && bxy * ((ns + ch - 1) / ch) < 2048) ch >>= 1;
+        while (ch > 8 && bxy * ((ns + ch - 1) / ch) < 4096) ch >>= 1;
         *chunk = ch;
         L.grid = dim3((d.n[0] + 63) / 64, (nt + 3) / 4, (ns + ch - 1) / ch);
     }

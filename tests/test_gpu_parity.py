@@ -150,6 +150,28 @@ def test_step_parity_with_phase_change(pc):
         assert d.step_index == 3
 
 
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 0, 1)])
+def test_nonconservative_energy_flux_parity(pc, bc):
+    """The ablation mode of section 3.4.1 (eq. disc_et_adv_noncons) with water-like heat
+    capacities: three steps, with phase change on the outflow domain."""
+    wl = W.random_drops_3d(n=24, ndrops=5, seed=45, rmin=2.0, rmax=4.0, cp=(4039.0, 1.248))
+    mdot = None
+    if bc != (0, 0, 0):
+        mdot = np.random.default_rng(4).uniform(-0.3, 0.8, size=wl.shape)
+    spec, cfg = _specs(pc, wl, bc=bc)
+    spec.energy_flux = "nonconservative"
+    cfg.energy_flux = 1
+    d = _domain(pc, spec, wl, mdot)
+    c, e = wl.c, wl.e
+    for n in range(3):
+        st = d.step(wl.dt, 1.0, stats=True)
+        c, e, st_ref = oracle.step(cfg, c, e, wl.u, wl.v, wl.w, mdot, wl.dt, 1.0, n)
+        _assert_close(d.vof().cpu().numpy(), c, 1.0, f"step {n} c")
+        _assert_close(d.energy().cpu().numpy(), e, 0.0, f"step {n} e")
+        assert st["energy"] == pytest.approx(st_ref["energy"], rel=1e-12)
+        assert st["energy_bnd_out"] == pytest.approx(st_ref["energy_bnd_out"], abs=1e-12 * abs(st_ref["energy"]))
+
+
 def test_circle2d_trajectory_parity(pc):
     """The 2D 64x64 circle (uniform velocity (1, 0.5), CFL 0.25, m'' = 0.01): all 100
     steps from identical inputs."""
