@@ -81,6 +81,9 @@ def lib():
         L.or_step.restype = C.c_int
         L.or_step.argtypes = [C.POINTER(Grid), C.POINTER(Params), _dp, _dp, _dp, _dp, _dp, _dp,
                               C.c_double, C.c_double, C.c_long, _dp, _dp, C.POINTER(Stats)]
+        L.or_mass_flux.restype = C.c_int
+        L.or_mass_flux.argtypes = [C.POINTER(Grid), C.POINTER(Params), _dp, _dp, C.c_double,
+                                   C.c_double, C.c_double, _dp, _dp]
         _lib = L
     return _lib
 
@@ -239,3 +242,18 @@ def step(cfg: Config, c, e, u, v, w=None, mdot=None, dt: float = 0.0, u_scale: f
     if rc != 0:
         raise ValueError(f"or_step failed ({rc})")
     return co, eo, st.as_dict()
+
+
+def mass_flux(cfg: Config, c, T, k_l: float, k_g: float, h_fg: float):
+    """Mass-transfer rate from the PLIC reconstruction (section 3.2): returns (mdot, dist),
+    m'' per cell (0 outside mixed cells) and the distance from each first or second pure
+    neighbour of a mixed cell to its selected plane (NaN elsewhere)."""
+    c, T = map(_f64, (c, T))
+    md = np.empty_like(c)
+    dist = np.empty_like(c)
+    g, p = cfg.grid(), cfg.params()
+    rc = lib().or_mass_flux(C.byref(g), C.byref(p), _ptr(c), _ptr(T), float(k_l), float(k_g),
+                            float(h_fg), _ptr(md), _ptr(dist))
+    if rc != 0:
+        raise ValueError(f"or_mass_flux failed ({rc})")
+    return md, dist

@@ -628,3 +628,143 @@ int or_step(const or_grid* g, const or_params* p, const double* c, const double*
     free(cc); free(ec); free(ca); free(ea); free(cb); free(eb);
     return 0;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Mass-transfer rate from the PLIC reconstruction (section 3.2).             */
+/* ------------------------------------------------------------------------- */
+
+/* Candidates whose collinearity differs by at most this much count as equal (the
+   first in the scan order is kept), and pure cells whose node lies closer than this
+   to the selected plane (cell units) give no finite-difference gradient. */
+#define MASS_FLUX_TIE 1e-12
+#define MASS_FLUX_MIN_DIST 1e-6
+
+/* Stencil position (x+ox, y+oy, z+oz) of the 5x5(x5) neighbourhood: periodic axes
+   wrap, positions beyond an outflow boundary do not exist (returns -1). */
+static long stencil_id(const or_grid* g, int x, int y, int z, int ox, int oy, int oz) {
+    int q[3] = {x + ox, y + oy, z + oz};
+    for (int a = 0; a < 3; ++a) {
+        int n = ncell(g, a);
+        if (q[a] >= 0 && q[a] < n) continue;
+        if (a == 2 && g->ndim == 2) return -1;
+        if (g->bc[a] == 1) return -1;
+        q[a] = ((q[a] % n) + n) % n;
+    }
+    return ((long)q[2] * g->ny + q[1]) * g->nx + q[0];
+}
+
+/* Translation from the origin of a cell (its corner nearest the domain origin) to the
+   centre (node) of the cell at stencil offset (ox, oy, oz), in cell units; 2D grids
+   have no z component. */
+static void node_offset(const or_grid* g, int ox, int oy, int oz, double dx[3]) {
+    dx[0] = ox + 0.5;
+    dx[1] = oy + 0.5;
+    dx[2] = g->ndim == 2 ? 0.0 : oz + 0.5;
+}
+
+/* n . dx in the fixed order x, y, z. */
+static double dot3(const double n[3], const double dx[3]) {
+    double s = n[0] * dx[0];
+    s += n[1] * dx[1];
+    s += n[2] * dx[2];
+    return s;
+}
+
+int or_mass_flux(const or_grid* g, const or_params* p, const double* c, const double* T,
+                 double k_l, double k_g, double h_fg, double* mdot, double* dist) {
+    if (check_grid(g) || !(h_fg != 0.0)) return -1;
+    const long n = (long)g->nx * g->ny * g->nz;
+    const int R = 2;                       /* first and second neighbours */
+    const int rz = g->ndim == 2 ? 0 : R;
+    /* Plane of every mixed cell (eq. plane_m, eq. cell_d): unit normal n = m/|m|_2
+       (liquid towards gas) and distance d = alpha/|m|_2 from the cell origin. */
+    double* pn = (double*)calloc((size_t)n * 4, sizeof(double));
+    double* q = (double*)malloc((size_t)n * sizeof(double));
+    if (!pn || !q) {
+        free(pn);
+        free(q);
+        return -2;
+    }
+    for (int z = 0; z < g->nz; ++z)
+        for (int y = 0; y < g->ny; ++y)
+            for (int x = 0; x < g->nx; ++x) {
+                long id = ((long)z * g->ny + y) * g->nx + x;
+                if (!is_mixed(p, c[id])) continue;
+                double c27[27], m[3];
+                gather27(g, c, x, y, z, c27);
+                or_normal(c27, p->normal, m);
+                double alpha = or_alpha(m, c[id]);
+                double norm = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+                pn[4 * id + 0] = m[0] / norm;
+                pn[4 * id + 1] = m[1] / norm;
+                pn[4 * id + 2] = m[2] / norm;
+                pn[4 * id + 3] = alpha / norm;
+            }
+    /* Pure cells within two cells of a mixed cell: the distance to the plane of the
+       neighbouring mixed cell whose normal is most collinear with the translation to
+       the pure cell's node, xi = |n . dx| (eq. dint_trans; ties keep the first in the
+       scan order), and the finite-difference normal gradient into the pure cell's phase,
+       (T - T_Gamma) / d_Gamma (eq. grad_n_T). */
+    for (long i = 0; i < n; ++i) {
+        q[i] = NAN;
+        if (dist) dist[i] = NAN;
+    }
+    for (int z = 0; z < g->nz; ++z)
+        for (int y = 0; y < g->ny; ++y)
+            for (int x = 0; x < g->nx; ++x) {
+                long id = ((long)z * g->ny + y) * g->nx + x;
+                if (is_mixed(p, c[id])) continue;
+                int found = 0;
+                double best = 0.0, dbest = 0.0;
+                for (int oz = -rz; oz <= rz; ++oz)
+                    for (int oy = -R; oy <= R; ++oy)
+                        for (int ox = -R; ox <= R; ++ox) {
+                            long mid = stencil_id(g, x, y, z, ox, oy, oz);
+                            if (mid < 0 || !is_mixed(p, c[mid])) continue;
+                            double dx[3];
+                            node_offset(g, -ox, -oy, -oz, dx);  /* from the mixed cell's origin */
+                            double xi = fabs(dot3(pn + 4 * mid, dx));
+                            if (!found || xi > best + MASS_FLUX_TIE) {
+                                found = 1;
+                                best = xi;
+                                dbest = pn[4 * mid + 3] - dot3(pn + 4 * mid, dx);
+                            }
+                        }
+                if (!found) continue;
+                double d = fabs(dbest) * g->h;
+                if (dist) dist[id] = d;
+                if (fabs(dbest) > MASS_FLUX_MIN_DIST) q[id] = (T[id] - p->T_gamma) / d;
+            }
+    /* Mixed cells: per phase, the weighted average of the pure neighbours' gradients in
+       the 5x5(x5) block, chi = gamma / sum gamma with gamma = xi / |dx|^2 relative to the
+       mixed cell's own plane (eq. normTgrad), and m'' = (k_g G_g + k_l G_l) / h_fg
+       (eq. mdot_calc with both gradients taken into their phase). */
+    for (int z = 0; z < g->nz; ++z)
+        for (int y = 0; y < g->ny; ++y)
+            for (int x = 0; x < g->nx; ++x) {
+                long id = ((long)z * g->ny + y) * g->nx + x;
+                mdot[id] = 0.0;
+                if (!is_mixed(p, c[id])) continue;
+                double wsum[2] = {0.0, 0.0}, gsum[2] = {0.0, 0.0};
+                for (int oz = -rz; oz <= rz; ++oz)
+                    for (int oy = -R; oy <= R; ++oy)
+                        for (int ox = -R; ox <= R; ++ox) {
+                            long pid = stencil_id(g, x, y, z, ox, oy, oz);
+                            if (pid < 0 || is_mixed(p, c[pid]) || isnan(q[pid])) continue;
+                            double dx[3];
+                            node_offset(g, ox, oy, oz, dx);
+                            double xi = fabs(dot3(pn + 4 * id, dx));
+                            double r2 = dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2];
+                            double gam = xi / r2;
+                            int ph = c[pid] >= 0.5 ? 1 : 0; /* 1 liquid, 0 gas */
+                            wsum[ph] += gam;
+                            gsum[ph] += gam * q[pid];
+                        }
+                double Gg = wsum[0] > 0.0 ? gsum[0] / wsum[0] : 0.0;
+                double Gl = wsum[1] > 0.0 ? gsum[1] / wsum[1] : 0.0;
+                mdot[id] = (k_g * Gg + k_l * Gl) / h_fg;
+            }
+    free(pn);
+    free(q);
+    return 0;
+}

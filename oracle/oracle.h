@@ -84,6 +84,18 @@ int or_step(const or_grid* g, const or_params* p, const double* c, const double*
             double dt, double u_scale, long step_index, double* c_out, double* e_out,
             or_stats* st);
 
+/* Mass-transfer rate from the PLIC reconstruction (section 3.2), from the fractions c
+   and the cell temperatures T: for every pure cell within two cells (first and second
+   neighbours) of a mixed cell, the distance |d_Gamma| (physical units) from its centre
+   to the plane of the neighbouring mixed cell whose normal is most collinear with the
+   translation to that centre, and its normal gradient (T - T_Gamma) / |d_Gamma|; for
+   every mixed cell, m'' = (k_g G_g + k_l G_l) / h_fg from the collinearity- and
+   distance-weighted averages G of those gradients over its 5x5(x5) block, per phase.
+   mdot (every cell; 0 outside mixed cells) and dist (NULL or every cell; NaN where no
+   distance is defined). Returns 0, -1 on bad arguments, -2 if out of memory. */
+int or_mass_flux(const or_grid* g, const or_params* p, const double* c, const double* T,
+                 double k_l, double k_g, double h_fg, double* mdot, double* dist);
+
 #ifdef __cplusplus
 }
 #endif
