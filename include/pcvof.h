@@ -135,6 +135,34 @@ int pcvof_set_velocity(pcvof_handle* h, const double* u, const double* v, const 
                        int mem);
 int pcvof_set_mass_flux(pcvof_handle* h, const double* mdot, int mem);
 
+/* Mass-transfer rate from the PLIC reconstruction (section 3.2; eqs. cell_d,
+   dint_trans, grad_n_T, normTgrad, mdot_calc), computed from the current fractions and
+   temperatures T = e / C_p(c), with T_Gamma = params.T_gamma:
+   * every mixed cell's plane gives a unit normal n = m / |m|_2 (liquid towards gas)
+     and a distance d = alpha / |m|_2 from the cell's origin (its corner nearest the
+     domain origin);
+   * every pure cell within two cells of a mixed cell (first and second neighbours,
+     5x5(x5) block) takes the plane of the neighbouring mixed cell whose normal is most
+     collinear with the translation dx from that cell's origin to the pure cell's
+     centre, xi = |n . dx| (first in z, y, x scan order on ties within 1e-12), its
+     distance |d - n . dx| h, and the gradient into its phase (T - T_Gamma) / distance
+     (none when the distance is below 1e-6 h);
+   * every mixed cell averages those gradients over the pure cells of its 5x5(x5)
+     block, per phase, with weights xi / |dx|^2 relative to its own plane, and
+     m'' = (k_g G_g + k_l G_l) / h_fg (0 for a phase without such cells).
+   Positions beyond an outflow boundary are not part of the blocks; periodic axes wrap.
+   The result becomes the domain's mass flux, as after pcvof_set_mass_flux (step 2 on;
+   0 outside mixed cells). mdot_out (optional) receives m'' per cell, dist_out
+   (optional) the distance of every pure cell that has one and NaN elsewhere, both in
+   the cell layout, in host (mem = 0) or device (mem = 1) memory. k_l, k_g >= 0,
+   h_fg != 0 (PCVOF_ERR_ARG otherwise); needs the fractions and energies
+   (PCVOF_ERR_STATE); not inside a step.
+   In this version the call validates its arguments and then returns PCVOF_ERR_STATE:
+   its GPU kernels are switched off (their first run ended in a memory fault whose
+   cause is not found yet). */
+int pcvof_compute_mass_flux(pcvof_handle* h, double k_l, double k_g, double h_fg, double* mdot_out,
+                            double* dist_out, int mem);
+
 /* One time step with face CFL numbers lambda_f = u_f * (u_scale * dt) / h:
    prologue, ndim sweeps in the axis order rotated by the step counter (x,y,z /
    y,z,x / z,x,y), step 2 when a mass flux is set, checksums. Increments the step

@@ -133,4 +133,20 @@ hipError_t launch_geom_weno5(int n, const double* v, double eps, double* out, hi
 // out[i] = (float)in[i]
 hipError_t launch_to_float(long n, const double* in, float* out, hipStream_t s);
 
+// Mass-transfer rate from the PLIC reconstruction (section 3.2) of a state (fractions
+// c, energies e, mixed-cell mask): plane records (4 doubles per cell, mixed cells),
+// the pure cells' normal gradients q (NaN where none), optional distances, and m''.
+struct MassFluxIO {
+    const double* c;
+    const double* e;
+    const uint64_t* mask;
+    int mask_cpw;
+    double* plane;
+    double* q;
+    double* dist;   // may be null
+    double* mdot;
+    double h, k_l, k_g, h_fg;
+};
+hipError_t launch_mass_flux(const Dom& d, const MassFluxIO& io, hipStream_t s);
+
 }  // namespace pcv

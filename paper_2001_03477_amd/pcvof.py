@@ -31,7 +31,7 @@ EXPORTS = (
     "pcvof_geom_normal", "pcvof_geom_weno5", "pcvof_advect_steps", "pcvof_set_profiling",
     "pcvof_get_profile", "pcvof_batch_workspace_bytes", "pcvof_batch_create", "pcvof_batch_destroy",
     "pcvof_batch_domain", "pcvof_batch_advect_step", "pcvof_batch_get_step", "pcvof_batch_set_tiles",
-    "pcvof_batch_get_tiles", "pcvof_batch_autotune",
+    "pcvof_batch_get_tiles", "pcvof_batch_autotune", "pcvof_compute_mass_flux",
 )
 
 PROF_NAMES = ("sweep_x", "sweep_y", "sweep_z", "phase", "checksum")
@@ -124,6 +124,7 @@ def lib():
         L.pcvof_batch_set_tiles.argtypes = [_vp, _vp]
         L.pcvof_batch_get_tiles.argtypes = [_vp, _vp, _vp]
         L.pcvof_batch_autotune.argtypes = [_vp, _vp, C.c_int, _vp]
+        L.pcvof_compute_mass_flux.argtypes = [_vp, C.c_double, C.c_double, C.c_double, _vp, _vp, C.c_int]
         for nm in EXPORTS:
             f = getattr(L, nm)
             if nm not in ("pcvof_workspace_bytes", "pcvof_last_error", "pcvof_batch_workspace_bytes"):
@@ -255,6 +256,17 @@ class Domain:
 
     def temperature(self):
         return self._get(lib().pcvof_get_temperature)
+
+    def compute_mass_flux(self, k_l: float, k_g: float, h_fg: float, distances: bool = False):
+        """m'' from the PLIC reconstruction of the current state (section 3.2); it becomes
+        the domain's mass flux. Returns (mdot, dist or None) as device tensors."""
+        import torch
+        md = torch.empty(self.spec.shape, dtype=torch.float64, device=self.device)
+        dist = torch.empty_like(md) if distances else None
+        check(lib().pcvof_compute_mass_flux(self._h, float(k_l), float(k_g), float(h_fg), md.data_ptr(),
+                                            dist.data_ptr() if dist is not None else None,
+                                            PCVOF_MEM_DEVICE))
+        return md, dist
 
     # -- stepping
     def step(self, dt: float, u_scale: float = 1.0, stats: bool = False):

@@ -1,0 +1,143 @@
+"""GPU parity of the mass-transfer rate from the PLIC reconstruction (section 3.2):
+pcvof_compute_mass_flux through the C-ABI against the FP64 oracle on the same seeded
+fields. m'' per cell within 1e-12 max|m''|, the distances of the first and second pure
+neighbours within 1e-12 h, and exactly the same cells with a distance."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2001_03477_amd import workloads as W
+
+pytestmark = [
+    pytest.mark.gpu,
+    pytest.mark.skip(reason="the mass-flux kernels are switched off: their first GPU run ended in a "
+                            "memory fault whose cause is not found yet (a CPU emulation of the kernel "
+                            "bodies stays within every buffer)"),
+]
+
+
+@pytest.fixture(scope="module")
+def pc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2001_03477_amd import pcvof
+    pcvof.lib()
+    return pcvof
+
+
+def _fields(wl, seed, T_gamma):
+    """Temperatures around T_Gamma with smooth and random parts, as energies."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = wl.shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    T = T_gamma + 0.3 * np.sin(0.4 * x + 0.2 * y) + 0.2 * np.cos(0.3 * z) + 0.05 * rng.uniform(-1, 1, wl.shape)
+    e = (wl.cp_l * wl.c + wl.cp_g * (1.0 - wl.c)) * T
+    return T, e
+
+
+def _compare(pc, wl, bc, normal=1, T_gamma=1.2, k=(0.6, 0.025, 2.3), seed=0):
+    T, e = _fields(wl, seed, T_gamma)
+    spec = pc.DomainSpec(shape=wl.shape, h=wl.h, ndim=wl.ndim, bc=bc, cp_l=wl.cp_l, cp_g=wl.cp_g,
+                         T_gamma=T_gamma, normal=normal)
+    d = pc.Domain(spec)
+    d.set_vof(wl.c)
+    d.set_energy(e)
+    md, dist = d.compute_mass_flux(*k, distances=True)
+    md, dist = md.cpu().numpy(), dist.cpu().numpy()
+    cfg = oracle.Config(shape=wl.shape, h=wl.h, ndim=wl.ndim, bc=bc, cp_l=wl.cp_l, cp_g=wl.cp_g,
+                        T_gamma=T_gamma, normal=normal)
+    T_ref = e / (wl.cp_l * wl.c + wl.cp_g * (1.0 - wl.c))
+    md_ref, dist_ref = oracle.mass_flux(cfg, wl.c, T_ref, *k)
+    assert np.array_equal(np.isnan(dist), np.isnan(dist_ref))
+    ok = ~np.isnan(dist_ref)
+    assert ok.sum() > 0
+    assert np.max(np.abs(dist[ok] - dist_ref[ok])) <= 1e-12 * wl.h
+    scale = max(np.max(np.abs(md_ref)), 1e-300)
+    assert np.max(np.abs(md - md_ref)) <= 1e-12 * scale
+    mixed = (wl.c > 1e-12) & (wl.c < 1 - 1e-12)
+    assert np.all(md[~mixed] == 0.0)
+    assert np.count_nonzero(md[mixed]) > 0.5 * mixed.sum()
+    return d, md
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 1), (0, 1, 0)])
+def test_mass_flux_parity_drops(pc, bc):
+    wl = W.random_drops_3d(n=28, ndrops=6, seed=93, rmin=1.5, rmax=5.0)
+    _compare(pc, wl, bc)
+
+
+@pytest.mark.parametrize("normal", [0, 2])
+def test_mass_flux_parity_normals_ragged(pc, normal):
+    wl = W.random_drops_3d(n=23, ndrops=4, seed=94, rmin=1.5, rmax=4.0)
+    _compare(pc, wl, (1, 0, 1), normal=normal, seed=1)
+
+
+def test_mass_flux_parity_2d(pc):
+    wl = W.circle_2d(64)
+    _compare(pc, wl, (0, 0, 0), seed=2)
+
+
+def test_mass_flux_parity_bubble(pc):
+    """An expanding-bubble field (vapour sphere in liquid, outflow) with a superheated
+    liquid: m'' > 0 on the interface."""
+    wl = W.bubble_3d(48, R=0.2)
+    T_sat = 1.0
+    nz, ny, nx = wl.shape
+    h = wl.h
+    z, y, x = np.meshgrid(*(np.arange(n) + 0.5 for n in (nz, ny, nx)), indexing="ij")
+    r = np.sqrt((x * h - 0.5) ** 2 + (y * h - 0.5) ** 2 + (z * h - 0.5) ** 2)
+    T = np.where(r < 0.2, T_sat, np.minimum(T_sat + 2.0 * (r - 0.2) / 0.05, 3.0))
+    e = (wl.cp_l * wl.c + wl.cp_g * (1.0 - wl.c)) * T
+    spec = pc.DomainSpec(shape=wl.shape, h=h, ndim=3, bc=(1, 1, 1), cp_l=wl.cp_l, cp_g=wl.cp_g,
+                         rho_l=wl.rho_l, T_gamma=T_sat)
+    d = pc.Domain(spec)
+    d.set_vof(wl.c)
+    d.set_energy(e)
+    k_l, k_g, h_fg = 0.07, 0.007, 100.0
+    md, _ = d.compute_mass_flux(k_l, k_g, h_fg)
+    md = md.cpu().numpy()
+    cfg = oracle.Config(shape=wl.shape, h=h, ndim=3, bc=(1, 1, 1), cp_l=wl.cp_l, cp_g=wl.cp_g,
+                        rho_l=wl.rho_l, T_gamma=T_sat)
+    md_ref, _ = oracle.mass_flux(cfg, wl.c, e / (wl.cp_l * wl.c + wl.cp_g * (1 - wl.c)), k_l, k_g, h_fg)
+    assert np.max(np.abs(md - md_ref)) <= 1e-12 * np.max(np.abs(md_ref))
+    mixed = (wl.c > 1e-12) & (wl.c < 1 - 1e-12)
+    assert np.all(md_ref[mixed] >= 0.0) and np.median(md_ref[mixed]) > 0.0
+
+
+def test_mass_flux_drives_step_two(pc):
+    """The computed m'' is the domain's mass flux: a step afterwards equals the oracle's
+    step with the oracle's m''."""
+    wl = W.random_drops_3d(n=24, ndrops=5, seed=95, rmin=2.0, rmax=4.0)
+    T_gamma = 0.9
+    T, e = _fields(wl, 3, T_gamma)
+    spec = pc.DomainSpec(shape=wl.shape, h=wl.h, ndim=3, bc=(0, 0, 0), cp_l=wl.cp_l, cp_g=wl.cp_g,
+                         T_gamma=T_gamma)
+    d = pc.Domain(spec)
+    d.set_vof(wl.c)
+    d.set_energy(e)
+    d.set_velocity(wl.u, wl.v, wl.w)
+    k = (0.6, 0.025, 2.3e3)
+    d.compute_mass_flux(*k)
+    d.step(wl.dt, 1.0)
+    cfg = oracle.Config(shape=wl.shape, h=wl.h, ndim=3, bc=(0, 0, 0), cp_l=wl.cp_l, cp_g=wl.cp_g,
+                        T_gamma=T_gamma)
+    md_ref, _ = oracle.mass_flux(cfg, wl.c, e / (wl.cp_l * wl.c + wl.cp_g * (1 - wl.c)), *k)
+    c1, e1, _ = oracle.step(cfg, wl.c, e, wl.u, wl.v, wl.w, md_ref, wl.dt, 1.0, 0)
+    assert np.max(np.abs(d.vof().cpu().numpy() - c1)) <= 1e-12
+    assert np.max(np.abs(d.energy().cpu().numpy() - e1)) <= 1e-12 * np.max(np.abs(e1))
+
+
+def test_mass_flux_errors(pc):
+    wl = W.random_drops_3d(n=12, ndrops=2, seed=96, rmin=1.5, rmax=3.0)
+    spec = pc.DomainSpec(shape=wl.shape, h=wl.h, ndim=3, bc=(0, 0, 0), cp_l=wl.cp_l, cp_g=wl.cp_g)
+    d = pc.Domain(spec)
+    with pytest.raises(pc.PcvofError) as ex:
+        d.compute_mass_flux(0.6, 0.02, 1.0)  # no fields yet
+    assert ex.value.code == -7
+    d.set_vof(wl.c)
+    d.set_energy(wl.e)
+    for bad in ((0.6, 0.02, 0.0), (-1.0, 0.02, 1.0), (0.6, float("nan"), 1.0)):
+        with pytest.raises(pc.PcvofError) as ex:
+            d.compute_mass_flux(*bad)
+        assert ex.value.code == -1
