@@ -346,11 +346,11 @@ __device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a, c
             if (lam != 0.0) {
                 const int q = lane;
                 const double cd = lam > 0.0 ? s_c[wave][q + XH - 1] : s_c[wave][q + XH];
-                const double Tf = lam > 0.0
-                                      ? weno5(s_T[wave][q], s_T[wave][q + 1], s_T[wave][q + 2],
-                                              s_T[wave][q + 3], s_T[wave][q + 4], d.weno_eps)
-                                      : weno5(s_T[wave][q + 5], s_T[wave][q + 4], s_T[wave][q + 3],
-                                              s_T[wave][q + 2], s_T[wave][q + 1], d.weno_eps);
+                // upwind stencil selected first (cells q .. q+4, or q+5 .. q+1 mirrored), so
+                // that one WENO5 evaluation serves both signs
+                const int b = lam > 0.0 ? q : q + 5, st = lam > 0.0 ? 1 : -1;
+                const double Tf = weno5(s_T[wave][b], s_T[wave][b + st], s_T[wave][b + 2 * st],
+                                        s_T[wave][b + 3 * st], s_T[wave][b + 4 * st], d.weno_eps);
                 const double F = mixed(d, cd) ? s_F[wave][r][lane] : fabs(lam) * cd;
                 face_energy(d, lam, F, Tf, Phi, E);
             }
@@ -521,8 +521,10 @@ __device__ __forceinline__ void sweep_t_body(const Dom& d, const SweepArgs& a, i
                 const unsigned idx = s_idx[tr][f - s0][lane];
                 F = idx < TFCAP ? s_F[tr][idx] : a.fgeo[fbase + (long)f * fstride];
             }
-            const double Tf = lam > 0.0 ? weno5(Tw[J0], Tw[J1], Tw[J2], Tw[J3], Tw[J4], d.weno_eps)
-                                        : weno5(Tw[J5], Tw[J4], Tw[J3], Tw[J2], Tw[J1], d.weno_eps);
+            // upwind stencil selected first, so that one WENO5 evaluation serves both signs
+            const bool pos = lam > 0.0;
+            const double Tf = weno5(pos ? Tw[J0] : Tw[J5], pos ? Tw[J1] : Tw[J4], pos ? Tw[J2] : Tw[J3],
+                                    pos ? Tw[J3] : Tw[J2], pos ? Tw[J4] : Tw[J1], d.weno_eps);
             face_energy(d, lam, F, Tf, Phi, E);
         }
         bool mx = false;
