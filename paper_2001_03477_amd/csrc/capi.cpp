@@ -506,6 +506,8 @@ int pcvof_phase_change(pcvof_handle* h, double dt) {
     pcv::PhaseIO io;
     io.c = h->c(h->cur);
     io.e = h->e(h->cur);
+    io.mask = h->mask(h->cur);
+    io.mask_cpw = h->mask_cpw;
     io.mask_out = h->mask(nxt);
     io.mdot = h->mdot();
     io.dt = dt;
@@ -894,9 +896,12 @@ int batch_enqueue(pcvof_batch* b, int k, const double* dt, hipStream_t s_) {
         pcvof_handle* h = b->dom[i];
         if (!h->has_mdot) continue;
         const int cur = b->ndim % 2 ? 1 - h->cur : h->cur;  // state after the sweeps
+        const int last_axis = (int)((b->step + b->ndim - 1) % b->ndim);
         pcv::PhaseIO io;
         io.c = h->c(cur);
         io.e = h->e(cur);
+        io.mask = h->mask(cur);
+        io.mask_cpw = last_axis == 0 ? pcv::kMaskCpwX : pcv::kMaskCpw;
         io.mask_out = h->mask(1 - cur);
         io.mdot = h->mdot();
         io.dt = dt[i];

@@ -90,11 +90,19 @@ __device__ __forceinline__ void block_sum8(const double (&v)[8], double* out, lo
     }
 }
 
-// Bit of the mixed-cell mask (cells per word cpw) for cell x of the row starting at
-// word rowword.
+// Bit of the mixed-cell mask (cells per word cpw, 63 or 64) for cell x of the row
+// starting at word rowword. The word index uses constant divisors (cpw is uniform over
+// the launch, so only one branch runs), not a division by a run-time value.
 __device__ __forceinline__ bool mask_bit(const uint64_t* __restrict__ mask, long rowword, int x, int cpw) {
-    const int k = x / cpw;
-    return (mask[rowword + k] >> (x - k * cpw)) & 1ull;
+    int k, b;
+    if (cpw == 64) {
+        k = x >> 6;
+        b = x & 63;
+    } else {
+        k = x / 63;
+        b = x - 63 * k;
+    }
+    return (mask[rowword + k] >> b) & 1ull;
 }
 
 // Index of face f along axis of the face row through transverse cell coordinates.

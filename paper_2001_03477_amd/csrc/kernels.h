@@ -90,6 +90,8 @@ int min_chunk();
 struct PhaseIO {
     const double* c;
     const double* e;
+    const uint64_t* mask;      // mixed cells of c, cells per word mask_cpw
+    int mask_cpw;
     uint64_t* mask_out;        // mixed cells of c_out (cpw kMaskCpw)
     const double* mdot;
     double dt, h;

@@ -684,16 +684,18 @@ k_sweep_t_batch_mixed(const Dom* doms, const SweepArgs* args, const BatchTile* t
 // flux: the reconstruction and the moved plane constant, rec = (m, alpha~, alpha*)
 // with alpha* = alpha~ + |m|_2 Delta d and Delta d = -(m''/rho_l) dt / h.
 __global__ void __launch_bounds__(256)
-k_phase_recon(Dom d, const double* __restrict__ c, const double* __restrict__ mdot, double dt_h,
-              double* __restrict__ rec) {
+k_phase_recon(Dom d, const double* __restrict__ c, const uint64_t* __restrict__ mask, int cpw,
+              const double* __restrict__ mdot, double dt_h, double* __restrict__ rec) {
     const int x = blockIdx.x * 64 + threadIdx.x;
     const int y = blockIdx.y * 4 + threadIdx.y;
     const int z = blockIdx.z;
     if (x >= d.n[0] || y >= d.n[1]) return;
-    const long id = ((long)z * d.n[1] + y) * d.n[0] + x;
+    const long row = (long)z * d.n[1] + y;
+    if (!mask_bit(mask, row * d.wpr, x, cpw)) return;  // the mixed cells of c
+    const long id = row * d.n[0] + x;
     const double md = mdot[id];
     const double cv = c[id];
-    if (md == 0.0 || !mixed(d, cv)) return;
+    if (md == 0.0) return;
     double c27[27];
     gather27(d, c, x, y, z, c27);
     const Normal nm = normal27(c27, d.normal);
@@ -715,7 +717,8 @@ k_phase_recon(Dom d, const double* __restrict__ c, const double* __restrict__ md
 // (section 3.4.1).
 __global__ void __launch_bounds__(256)
 k_phase_apply(Dom d, const double* __restrict__ c, const double* __restrict__ e,
-              const double* __restrict__ mdot, double dt_h, const double* __restrict__ rec,
+              const uint64_t* __restrict__ mask, int cpw, const double* __restrict__ mdot, double dt_h,
+              const double* __restrict__ rec,
               double* __restrict__ c_out, double* __restrict__ e_out, uint64_t* __restrict__ mask_out,
               double* __restrict__ part, long part_stride) {
     const int x = blockIdx.x * 64 + threadIdx.x;
@@ -724,36 +727,52 @@ k_phase_apply(Dom d, const double* __restrict__ c, const double* __restrict__ e,
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     bool mx = false;
     if (x < d.n[0] && y < d.n[1]) {
-        const long id = ((long)z * d.n[1] + y) * d.n[0] + x;
+        const long row = (long)z * d.n[1] + y;
+        const long id = row * d.n[0] + x;
         const double cj = c[id];
         double cnew = cj;
-        if (mixed(d, cj)) {
+        // mixedness of c from its mask (the same test, without reading the neighbours'
+        // fractions and mass fluxes unless they are mixed)
+        if (mask_bit(mask, row * d.wpr, x, cpw)) {
             if (mdot[id] != 0.0) {
                 const double* r = rec + 5 * id;
                 cnew = volume(r[0], r[1], r[2], r[4]);
             }
         } else {
             const double want = cj >= 1.0 - d.eps ? -1.0 : 1.0;
+            // the six face neighbours (x-, x+, y-, y+, z-, z+): their mask bits are loaded
+            // together, then the mixed ones are visited in that fixed order
+            const int pos[3] = {x, y, z};
+            long nid[6];
+            bool nmix[6];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                const int k = j >> 1, sg = (j & 1) ? 1 : -1;
+                int q[3] = {pos[0], pos[1], pos[2]};
+                q[k] += sg;
+                const bool inside = k < d.ndim && !(d.bc[k] == 1 && (q[k] < 0 || q[k] >= d.n[k]));
+                const long nrow = (long)wrap(q[2], d.ndim == 2 ? 1 : d.n[2], d.bc[2]) * d.n[1] +
+                                  wrap(q[1], d.n[1], d.bc[1]);
+                const int nx_ = wrap(q[0], d.n[0], d.bc[0]);
+                nid[j] = nrow * d.n[0] + nx_;
+                nmix[j] = inside && mask_bit(mask, nrow * d.wpr, nx_, cpw);
+            }
             double sum = 0.0;
             int cnt = 0;
-            const int pos[3] = {x, y, z};
-            for (int k = 0; k < d.ndim; ++k)
-                for (int s = -1; s <= 1; s += 2) {
-                    int q[3] = {pos[0], pos[1], pos[2]};
-                    q[k] += s;
-                    if (d.bc[k] == 1 && (q[k] < 0 || q[k] >= d.n[k])) continue;
-                    const long nid = ((long)wrap(q[2], d.ndim == 2 ? 1 : d.n[2], d.bc[2]) * d.n[1] +
-                                      wrap(q[1], d.n[1], d.bc[1])) * d.n[0] + wrap(q[0], d.n[0], d.bc[0]);
-                    const double mdn = mdot[nid];
-                    if (mdn == 0.0 || !mixed(d, c[nid])) continue;
-                    const double dd = -(mdn / d.rho_l) * dt_h;
-                    const double motion = dd > 0.0 ? 1.0 : -1.0;
-                    if (motion != want) continue;
-                    const double* r = rec + 5 * nid;
-                    const double mo = -s * r[k];
-                    sum += volume(r[0], r[1], r[2], r[3] - mo) - volume(r[0], r[1], r[2], r[4] - mo);
-                    ++cnt;
-                }
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                if (!nmix[j]) continue;
+                const int k = j >> 1, sg = (j & 1) ? 1 : -1;
+                const double mdn = mdot[nid[j]];
+                if (mdn == 0.0) continue;
+                const double dd = -(mdn / d.rho_l) * dt_h;
+                const double motion = dd > 0.0 ? 1.0 : -1.0;
+                if (motion != want) continue;
+                const double* r = rec + 5 * nid[j];
+                const double mo = -sg * r[k];
+                sum += volume(r[0], r[1], r[2], r[3] - mo) - volume(r[0], r[1], r[2], r[4] - mo);
+                ++cnt;
+            }
             if (cnt) cnew = cj - sum / cnt;
         }
         const double dc = cnew - cj;
@@ -903,11 +922,11 @@ hipError_t launch_sweep(const Dom& d, int axis, const SweepIO& io, hipStream_t s
 hipError_t launch_phase(const Dom& d, const PhaseIO& io, hipStream_t s) {
     const double dt_h = io.dt / io.h;
     const Launch L = cell_launch(d);
-    hipLaunchKernelGGL(k_phase_recon, L.grid, L.block, 0, s, d, io.c, io.mdot, dt_h, io.rec);
+    hipLaunchKernelGGL(k_phase_recon, L.grid, L.block, 0, s, d, io.c, io.mask, io.mask_cpw, io.mdot, dt_h, io.rec);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k_phase_apply, L.grid, L.block, 0, s, d, io.c, io.e, io.mdot, dt_h, io.rec, io.c_out,
-                       io.e_out, io.mask_out, io.part, io.part_stride);
+    hipLaunchKernelGGL(k_phase_apply, L.grid, L.block, 0, s, d, io.c, io.e, io.mask, io.mask_cpw, io.mdot, dt_h,
+                       io.rec, io.c_out, io.e_out, io.mask_out, io.part, io.part_stride);
     *io.nblocks = L.nblocks;
     return hipGetLastError();
 }
