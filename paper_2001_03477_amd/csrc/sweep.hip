@@ -726,6 +726,36 @@ k_phase_apply(Dom d, const double* __restrict__ c, const double* __restrict__ e,
     const int z = blockIdx.z;
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     bool mx = false;
+    // Wavefront shortcut: when the mask words around the wavefront's 64 cells (its row and
+    // the face-neighbour rows, over cells x0-1 .. x0+64) hold no mixed cell, no cell of
+    // the wavefront is mixed or has a mixed face neighbour, so none changes. Taken only
+    // away from the x ends of the domain; the words are read with wavefront-uniform
+    // (scalar) addresses.
+    bool quiet = false;
+    {
+        const int x0 = blockIdx.x * 64;
+        const int yu = __builtin_amdgcn_readfirstlane(y);
+        if (yu < d.n[1] && x0 > 0 && x0 + 64 < d.n[0]) {
+            const int klo = (x0 - 1) / cpw, khi = (x0 + 64) / cpw;  // at most 3 words
+            uint64_t any = 0;
+            auto row_or = [&](int yy, int zz) {
+                const long rw = ((long)zz * d.n[1] + yy) * d.wpr;
+                for (int k = klo; k <= khi; ++k) any |= mask[rw + k];
+            };
+            row_or(yu, z);
+            for (int sg = -1; sg <= 1; sg += 2) {
+                const int yy = yu + sg;
+                if (yy >= 0 && yy < d.n[1]) row_or(yy, z);
+                else if (d.bc[1] == 0) row_or(yy < 0 ? yy + d.n[1] : yy - d.n[1], z);
+                if (d.ndim == 3) {
+                    const int zz = z + sg;
+                    if (zz >= 0 && zz < d.n[2]) row_or(yu, zz);
+                    else if (d.bc[2] == 0) row_or(yu, zz < 0 ? zz + d.n[2] : zz - d.n[2]);
+                }
+            }
+            quiet = any == 0ull;
+        }
+    }
     if (x < d.n[0] && y < d.n[1]) {
         const long row = (long)z * d.n[1] + y;
         const long id = row * d.n[0] + x;
@@ -733,7 +763,8 @@ k_phase_apply(Dom d, const double* __restrict__ c, const double* __restrict__ e,
         double cnew = cj;
         // mixedness of c from its mask (the same test, without reading the neighbours'
         // fractions and mass fluxes unless they are mixed)
-        if (mask_bit(mask, row * d.wpr, x, cpw)) {
+        if (quiet) {
+        } else if (mask_bit(mask, row * d.wpr, x, cpw)) {
             if (mdot[id] != 0.0) {
                 const double* r = rec + 5 * id;
                 cnew = volume(r[0], r[1], r[2], r[4]);
