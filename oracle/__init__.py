@@ -28,7 +28,7 @@ class Grid(C.Structure):
 class Params(C.Structure):
     _fields_ = [("cp_l", C.c_double), ("cp_g", C.c_double), ("rho_l", C.c_double),
                 ("T_gamma", C.c_double), ("eps_mixed", C.c_double), ("weno_eps", C.c_double),
-                ("normal", C.c_int), ("energy_flux", C.c_int)]
+                ("normal", C.c_int), ("energy_flux", C.c_int), ("split", C.c_int)]
 
 
 STAT_NAMES = ("vol", "energy", "vol_clip", "energy_clip", "vol_phase", "energy_phase",
@@ -175,6 +175,7 @@ class Config:
     weno_eps: float = 1e-6
     normal: int = 1
     energy_flux: int = 0  # 0 conservative (eq. disc_et_adv), 1 non-conservative (eq. disc_et_adv_noncons)
+    split: int = 0        # 0 Weymouth-Yue (section 3.3), 1 Lagrangian-explicit sweeps of Li (CIAM)
 
     def grid(self) -> Grid:
         nz, ny, nx = self.shape
@@ -185,7 +186,7 @@ class Config:
 
     def params(self) -> Params:
         return Params(self.cp_l, self.cp_g, self.rho_l, self.T_gamma, self.eps_mixed,
-                      self.weno_eps, int(self.normal), int(self.energy_flux))
+                      self.weno_eps, int(self.normal), int(self.energy_flux), int(self.split))
 
 
 def prologue(cfg: Config, c, e):

@@ -377,15 +377,39 @@ void or_prologue(const or_grid* g, const or_params* p, const double* c, const do
     }
 }
 
+/* CFL number of the face at position f along axis a (between cells f-1 and f) of the
+   face row through pos. Faces beyond the domain: periodic axes wrap (face n is face
+   0); outflow axes repeat the boundary face, so a ghost cell's two faces carry the
+   same velocity. */
+static double face_lam(const or_grid* g, int a, const double* vel, double kfac, const int* pos, int f) {
+    int n = ncell(g, a);
+    if (g->bc[a] == 0) {
+        while (f < 0) f += n;
+        while (f > n) f -= n;
+    } else {
+        f = f < 0 ? 0 : (f > n ? n : f);
+    }
+    int q[3] = {pos[0], pos[1], pos[2]};
+    q[a] = f;
+    return vel[face_id(g, a, q[0], q[1], q[2])] * kfac;
+}
+
 /* Face flux of one sweep: the liquid volume F through the face (section 3.3) and the
    energy flux E = sgn(lam) [C_pl F + C_pg (|lam| - F)] T_f, i.e. the fluxed heat
    capacity weighted by the fluxed liquid and gas volumes times the WENO5 face
    temperature (section 3.4.1, eq. disc_et_adv). With the non-conservative energy flux
    (eq. disc_et_adv_noncons) the face carries only lam T_f; each cell multiplies it by
-   its own heat capacity in or_sweep. Position (x,y,z) is the cell right of the face. */
+   its own heat capacity in or_sweep. Position (x,y,z) is the cell right of the face.
+
+   Weymouth-Yue sweeps: F is the liquid in the donor's slab of width |lam| next to the
+   face. Lagrangian-explicit sweeps (Li): every point of the donor moves with the
+   velocity interpolated linearly between its two faces, so the donor is stretched by
+   s = 1 + (lam_R - lam_L) and the part that crosses the face is the slab of width
+   |lam| / s next to it, whose liquid volume is multiplied by s. A pure donor gives
+   |lam| c_D in both schemes. */
 static void face_flux(const or_grid* g, const or_params* p, int a, const double* c,
-                      const double* e, double lam, int x, int y, int z, double* Phi,
-                      double* E) {
+                      const double* e, const double* vel, double kfac, double lam, int x,
+                      int y, int z, double* Phi, double* E) {
     *Phi = 0.0;
     *E = 0.0;
     if (lam == 0.0) return;
@@ -399,7 +423,15 @@ static void face_flux(const or_grid* g, const or_params* p, int a, const double*
         gather27(g, c, dpos[0], dpos[1], dpos[2], c27);
         or_normal(c27, p->normal, m);
         double alpha = or_alpha(m, cd);
-        F = or_slab(m, alpha, a, lam);
+        if (p->split == 1) {
+            /* the donor's faces are dpos[a] and dpos[a] + 1 */
+            double lamL = face_lam(g, a, vel, kfac, pos, dpos[a]);
+            double lamR = face_lam(g, a, vel, kfac, pos, dpos[a] + 1);
+            double s = 1.0 + (lamR - lamL);
+            F = s * or_slab(m, alpha, a, lam / s);
+        } else {
+            F = or_slab(m, alpha, a, lam);
+        }
     } else {
         F = L * cd;
     }
@@ -436,8 +468,8 @@ int or_sweep(const or_grid* g, const or_params* p, int a, const double* c, const
                 double lamL = vel[face_id(g, a, pos[0], pos[1], pos[2])] * kfac;
                 double lamR = vel[face_id(g, a, posR[0], posR[1], posR[2])] * kfac;
                 double PhiL, EL, PhiR, ER;
-                face_flux(g, p, a, c, e, lamL, pos[0], pos[1], pos[2], &PhiL, &EL);
-                face_flux(g, p, a, c, e, lamR, posR[0], posR[1], posR[2], &PhiR, &ER);
+                face_flux(g, p, a, c, e, vel, kfac, lamL, pos[0], pos[1], pos[2], &PhiL, &EL);
+                face_flux(g, p, a, c, e, vel, kfac, lamR, posR[0], posR[1], posR[2], &PhiR, &ER);
                 long id = cell_id(g, x, y, z);
                 if (p->energy_flux == 1) {
                     /* eq. disc_et_adv_noncons: the cell's own heat capacity (of the
@@ -447,10 +479,14 @@ int or_sweep(const or_grid* g, const or_params* p, int a, const double* c, const
                     ER *= k;
                 }
                 double dl = lamR - lamL;
-                double cn = c[id] - (PhiR - PhiL) + cc[id] * dl;
-                double en = e[id] - (ER - EL) + ec[id] * dl;
-                kadd(&s_src, cc[id] * dl);
-                kadd(&s_esrc, ec[id] * dl);
+                /* dilatation term: the frozen c_c, e_c (Weymouth-Yue), or the cell's own
+                   current c, e, i.e. c' = s c - (PhiR - PhiL) (Lagrangian-explicit) */
+                double fc = p->split == 1 ? c[id] : cc[id];
+                double fe = p->split == 1 ? e[id] : ec[id];
+                double cn = c[id] - (PhiR - PhiL) + fc * dl;
+                double en = e[id] - (ER - EL) + fe * dl;
+                kadd(&s_src, fc * dl);
+                kadd(&s_esrc, fe * dl);
                 if (cn < 0.0 || cn > 1.0) {
                     /* clip into [0,1] keeping the cell temperature */
                     double T = en / cp_of(p, cn);

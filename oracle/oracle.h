@@ -37,6 +37,9 @@ typedef struct {
     int normal;          /* 0 Youngs, 1 mixed Youngs-centred (MYC), 2 centred columns only */
     int energy_flux;     /* 0 conservative fluxes (section 3.4.1, eq. disc_et_adv); 1 the
                             non-conservative approximation of eq. disc_et_adv_noncons */
+    int split;           /* 0 Weymouth-Yue Eulerian-implicit sweeps with the frozen c_c, e_c
+                            dilatation terms; 1 Lagrangian-explicit sweeps of Li (CIAM, the
+                            other scheme section 3.3 names), dilatation with the current c, e */
 } or_params;
 
 typedef struct {
@@ -44,7 +47,8 @@ typedef struct {
     double vol_clip, energy_clip;    /* sweep clipping of c into [0,1] (energy keeps T) */
     double vol_phase, energy_phase;  /* step-2 change of c and of e (latent correction) */
     double vol_bnd_out, energy_bnd_out; /* net outflow through outflow boundaries */
-    double vol_src, energy_src;      /* split dilatation terms cc*dlam, ec*dlam */
+    double vol_src, energy_src;      /* split dilatation terms cc*dlam, ec*dlam (Lagrangian-
+                                        explicit sweeps: c*dlam, e*dlam) */
     double max_cfl;                  /* max |u_f| * u_scale * dt / h over the faces used */
 } or_stats;
 
