@@ -78,6 +78,19 @@ enum { PCVOF_PREC_FP64 = 0, PCVOF_PREC_MIXED = 1 };
    conserved (stats.energy no longer obeys the bookkeeping identity) and temperatures
    near the interface drift. Provided as an ablation of the conservative scheme. */
 enum { PCVOF_EFLUX_CONSERVATIVE = 0, PCVOF_EFLUX_NONCONSERVATIVE = 1 };
+/* Direction-split scheme of the sweeps (section 3.3 names both). WY: the Eulerian-
+   implicit sweeps of Weymouth and Yue that the paper builds on; the face flux is the
+   liquid of the donor slab of width |lambda| and the dilatation terms use c_c and e_c
+   frozen over the step, so volume and energy are conserved in a divergence-free field.
+   LE: the Lagrangian-explicit sweeps of Li (CIAM); every point of the donor moves with
+   the velocity interpolated linearly between the donor's two faces, which stretches
+   the donor by s = 1 + (lambda_R - lambda_L): the face flux is s times the liquid of the
+   donor slab of width |lambda| / s, and the dilatation terms use the current c and e
+   (c' = s c - (Phi_R - Phi_L)). Fractions then stay in [0, 1] without clipping, but the
+   dilatation terms do not cancel over the sweeps of a step: volume and energy are not
+   conserved (stats.vol_src and stats.energy_src report the change). Beyond an outflow
+   boundary the ghost donor is not stretched (s = 1). Provided as an ablation. */
+enum { PCVOF_SPLIT_WY = 0, PCVOF_SPLIT_LE = 1 };
 
 typedef struct {
     int ndim;        /* 2 or 3 */
@@ -97,6 +110,7 @@ typedef struct {
     int normal;         /* PCVOF_NORMAL_*: interface normal estimator (MYC per section 3.2) */
     int precision;      /* PCVOF_PREC_* */
     int energy_flux;    /* PCVOF_EFLUX_* (CONSERVATIVE is the paper's scheme) */
+    int split;          /* PCVOF_SPLIT_* (WY is the paper's scheme) */
 } pcvof_params;
 
 /* Checksums of one step (cell volume hv = h^ndim). The change of total volume obeys

@@ -78,6 +78,7 @@ bool params_ok(const pcvof_params* p) {
     if (p->normal < 0 || p->normal > 2) return false;
     if (p->precision != PCVOF_PREC_FP64 && p->precision != PCVOF_PREC_MIXED) return false;
     if (p->energy_flux != PCVOF_EFLUX_CONSERVATIVE && p->energy_flux != PCVOF_EFLUX_NONCONSERVATIVE) return false;
+    if (p->split != PCVOF_SPLIT_WY && p->split != PCVOF_SPLIT_LE) return false;
     return true;
 }
 
@@ -101,6 +102,7 @@ pcv::Dom make_dom(const pcvof_grid& g, const pcvof_params& p) {
     d.normal = p.normal;
     d.wpr = (g.nx + pcv::kMaskCpwX - 1) / pcv::kMaskCpwX;
     d.ncons = p.energy_flux == PCVOF_EFLUX_NONCONSERVATIVE ? 1 : 0;
+    d.split = p.split == PCVOF_SPLIT_LE ? 1 : 0;
     return d;
 }
 

@@ -16,6 +16,7 @@ struct Dom {
     int normal;
     int wpr;       // words per row of the mixed-cell masks: ceil(n[0] / 63)
     int ncons;     // 1: non-conservative energy flux (cells scale lambda T_f by their C_p)
+    int split;     // 1: Lagrangian-explicit sweeps (donor stretched by 1 + lam_R - lam_L)
 };
 
 // Mixed-cell mask of a state: one bit per cell, rows of wpr 64-bit words, word k of a

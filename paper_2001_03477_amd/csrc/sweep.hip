@@ -57,14 +57,33 @@ __global__ void __launch_bounds__(256) k_classify(Dom d, const double* __restric
 // sweep along AX with CFL number lam; cd is the donor's fraction (mixed). The plane is
 // reconstructed from the donor's own 3x3x3 block, so a periodic face computed from
 // either side, or a ghost donor beyond an outflow boundary, gives the same value.
+// Weymouth-Yue sweeps: the donor slab of width |lam| next to the face. Lagrangian-
+// explicit sweeps: the donor is stretched by s = 1 + (lam_R - lam_L) (its own faces),
+// and the flux is s times the liquid of its slab of width |lam| / s.
 template <int AX>
 __device__ double donor_fraction(const Dom& d, const double* __restrict__ c, int x, int y, int z, double cd,
-                                 double lam) {
+                                 double lam, double s) {
     double c27[27];
     gather27(d, c, x, y, z, c27);
     const Normal nm = normal27(c27, d.normal);
     const double alpha = alpha_of(nm.m[0], nm.m[1], nm.m[2], cd);
+    if (d.split) return s * slab(nm.m[0], nm.m[1], nm.m[2], alpha, AX, lam / s);
     return slab(nm.m[0], nm.m[1], nm.m[2], alpha, AX, lam);
+}
+
+// Face position f (between cells f-1 and f) of an axis with n cells beyond the domain:
+// periodic axes wrap (face n is face 0), outflow axes repeat the boundary face, so a
+// ghost donor has the same velocity on both faces and is not stretched.
+__device__ __forceinline__ int face_wrap(int f, int n, int bc) {
+    if (bc == 0) return f < 0 ? f + n : (f > n ? f - n : f);
+    return f < 0 ? 0 : (f > n ? n : f);
+}
+
+// Stretch s = 1 + (lam_R - lam_L) of the donor of a face with CFL number lam, given
+// the CFL number lo of the donor's other face (the face before it when lam > 0, after
+// it otherwise).
+__device__ __forceinline__ double donor_stretch(double lam, double lo) {
+    return lam > 0.0 ? 1.0 + (lam - lo) : 1.0 + (lo - lam);
 }
 
 // Mixed-precision mode: face velocities and e_c are stored in single precision; the
@@ -97,24 +116,26 @@ __device__ __forceinline__ typename Prec<MP>::T ec_at(const SweepArgs& a, long i
 
 template <int AX, bool MP>
 __device__ double donor_flux(const Dom& d, const double* __restrict__ c, int x, int y, int z, double cd,
-                             double lam) {
-    if (!MP) return donor_fraction<AX>(d, c, x, y, z, cd, lam);
+                             double lam, double s) {
+    if (!MP) return donor_fraction<AX>(d, c, x, y, z, cd, lam, s);
     double c27[27];
     gather27(d, c, x, y, z, c27);
     float c27f[27];
 #pragma unroll
     for (int q = 0; q < 27; ++q) c27f[q] = (float)c27[q];
     const NormalF nm = normal27_f(c27f, d.normal);
-    const double L = fabs(lam);
+    const double lw = d.split ? lam / s : lam;  // slab width (Lagrangian-explicit: |lam| / s)
+    const double L = fabs(lw);
     double F;
     if (fmin(cd, 1.0 - cd) < kMixedFp64Band) {
         const double alpha = alpha_of(nm.m[0], nm.m[1], nm.m[2], cd);
-        F = slab(nm.m[0], nm.m[1], nm.m[2], alpha, AX, lam);
+        F = slab(nm.m[0], nm.m[1], nm.m[2], alpha, AX, lw);
     } else {
         const float alpha = alpha_of_f(nm.m[0], nm.m[1], nm.m[2], (float)cd, (float)(1.0 - cd));
-        F = (double)slab_f(nm.m[0], nm.m[1], nm.m[2], alpha, AX, (float)lam);
+        F = (double)slab_f(nm.m[0], nm.m[1], nm.m[2], alpha, AX, (float)lw);
     }
-    return fmin(fmax(F, fmax(0.0, cd - (1.0 - L))), fmin(L, cd));
+    F = fmin(fmax(F, fmax(0.0, cd - (1.0 - L))), fmin(L, cd));
+    return d.split ? s * F : F;
 }
 
 // Appends item to a wavefront's work list in LDS where take is true; n is the
@@ -152,6 +173,10 @@ __device__ __forceinline__ double update_cell(const Dom& d, const SweepArgs& a, 
     } else {
         flag = (double)cc_in;
         ecv = ec_in;
+    }
+    if (d.split) {  // Lagrangian-explicit sweeps: c' = s c - (PhiR - PhiL), likewise e
+        flag = cv;
+        ecv = ev;
     }
     const double dl = lamR - lamL;
     double cn = cv - (PhiR - PhiL) + flag * dl;
@@ -293,7 +318,12 @@ __device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a, c
         const int xd = lam > 0.0 ? xf - 1 : xf;
         const double cd = a.c[(long)R * nx + wrap(xd, nx, d.bc[0])];
         if (!mixed(d, cd)) continue;
-        s_F[wave][r][l] = donor_flux<0, MP>(d, a.c, xd, y0 + r, tl.bz, cd, lam);
+        double s = 1.0;
+        if (d.split) {
+            const int fo = face_wrap(lam > 0.0 ? xf - 1 : xf + 1, nx, d.bc[0]);
+            s = donor_stretch(lam, vel_at<MP>(a, (long)R * (nx + 1) + fo) * a.kfac);
+        }
+        s_F[wave][r][l] = donor_flux<0, MP>(d, a.c, xd, y0 + r, tl.bz, cd, lam, s);
     }
     __builtin_amdgcn_wave_barrier();
     using T = typename Prec<MP>::T;
@@ -453,8 +483,13 @@ __device__ __forceinline__ void sweep_t_body(const Dom& d, const SweepArgs& a, i
         const int sd = lam > 0.0 ? f - 1 : f;
         const double cd = a.c[bw + (long)wrap(sd, ns, d.bc[AX]) * stride];
         if (!mixed(d, cd)) continue;
-        const double F = AX == 1 ? donor_flux<1, MP>(d, a.c, xw, sd, t, cd, lam)
-                                 : donor_flux<2, MP>(d, a.c, xw, t, sd, cd, lam);
+        double s = 1.0;
+        if (d.split) {
+            const int fo = face_wrap(lam > 0.0 ? f - 1 : f + 1, ns, d.bc[AX]);
+            s = donor_stretch(lam, vel_at<MP>(a, fw + (long)fo * fstride) * a.kfac);
+        }
+        const double F = AX == 1 ? donor_flux<1, MP>(d, a.c, xw, sd, t, cd, lam, s)
+                                 : donor_flux<2, MP>(d, a.c, xw, t, sd, cd, lam, s);
         if (i < TFCAP) s_F[tr][i] = F;
         else a.fgeo[fw + (long)f * fstride] = F;
     }

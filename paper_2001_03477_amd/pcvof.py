@@ -52,7 +52,7 @@ class Params(C.Structure):
     _fields_ = [("cp_l", C.c_double), ("cp_g", C.c_double), ("rho_l", C.c_double),
                 ("T_gamma", C.c_double), ("eps_mixed", C.c_double), ("weno_eps", C.c_double),
                 ("cfl_max", C.c_double), ("normal", C.c_int), ("precision", C.c_int),
-                ("energy_flux", C.c_int)]
+                ("energy_flux", C.c_int), ("split", C.c_int)]
 
 
 STAT_NAMES = ("vol", "energy", "vol_clip", "energy_clip", "vol_phase", "energy_phase",
@@ -146,6 +146,7 @@ def _stream_ptr(stream=None) -> int:
 
 PRECISIONS = {"fp64": 0, "mixed": 1}
 ENERGY_FLUXES = {"conservative": 0, "nonconservative": 1}  # section 3.4.1: eq. disc_et_adv / disc_et_adv_noncons
+SPLITS = {"wy": 0, "le": 1}  # section 3.3: Weymouth-Yue split / Lagrangian-explicit sweeps of Li (CIAM)
 
 
 @dataclass
@@ -164,6 +165,7 @@ class DomainSpec:
     normal: int = NORMAL_MYC
     precision: str = "fp64"   # "fp64" or "mixed"
     energy_flux: str = "conservative"  # or "nonconservative" (ablation)
+    split: str = "wy"         # Weymouth-Yue, or "le": Lagrangian-explicit sweeps of Li (ablation)
 
     def grid(self) -> Grid:
         nz, ny, nx = self.shape
@@ -175,7 +177,7 @@ class DomainSpec:
     def params(self) -> Params:
         return Params(self.cp_l, self.cp_g, self.rho_l, self.T_gamma, self.eps_mixed,
                       self.weno_eps, self.cfl_max, int(self.normal), PRECISIONS[self.precision],
-                      ENERGY_FLUXES[self.energy_flux])
+                      ENERGY_FLUXES[self.energy_flux], SPLITS[self.split])
 
 
 def workspace_bytes(spec: DomainSpec) -> int:

@@ -87,6 +87,36 @@ def sphere_fraction(shape, h, centres, radii, inside_liquid=True, sub=8, nd=3, d
     return frac if inside_liquid else 1.0 - frac
 
 
+def line_fraction(xl, yl, h, x_at_y0, slope):
+    """Exact area fraction of the square [xl, xl+h] x [yl, yl+h] left of the line
+    x = x_at_y0 + slope * y: the mean over y of clamp(x_line(y) - xl, 0, h) / h. The
+    integrand is piecewise linear with kinks where it reaches 0 or h, so the trapezoid
+    rule is exact between the kinks."""
+    def g(y):
+        return min(max(x_at_y0 + slope * y - xl, 0.0), h)
+
+    knots = {yl, yl + h}
+    if slope != 0.0:
+        for level in (0.0, h):
+            yk = (xl + level - x_at_y0) / slope
+            if yl < yk < yl + h:
+                knots.add(yk)
+    ks = sorted(knots)
+    area = sum(0.5 * (g(a) + g(b)) * (b - a) for a, b in zip(ks[:-1], ks[1:]))
+    return min(max(area / (h * h), 0.0), 1.0)  # rounding of the sum may step past 0 or 1
+
+
+def line_fraction_field(shape, h, x_at_y0, slope):
+    """Fractions of a 2D grid (shape (1, ny, nx)) of the region left of the line
+    x = x_at_y0 + slope * y."""
+    _, ny, nx = shape
+    out = np.zeros(shape)
+    for j in range(ny):
+        for i in range(nx):
+            out[0, j, i] = line_fraction(i * h, j * h, h, x_at_y0, slope)
+    return out
+
+
 def _disjoint_sphere_fraction(shape, h, centres, radii, inside_liquid, sub, nd):
     import torch  # multithreaded sampling on the host
     nz, ny, nx = shape

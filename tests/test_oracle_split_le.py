@@ -25,34 +25,12 @@ import numpy as np
 from paper_2001_03477_amd import workloads as W
 
 
-def _line_fraction(xl, yl, h, x_at_y0, slope):
-    """Fraction of the square [xl, xl+h] x [yl, yl+h] left of the line
-    x = x_at_y0 + slope * y: the mean over y of clamp(x_line(y) - xl, 0, h) / h. The
-    integrand is piecewise linear with kinks where it reaches 0 or h; the trapezoid
-    rule is exact between the kinks."""
-    def g(y):
-        return min(max(x_at_y0 + slope * y - xl, 0.0), h)
-
-    knots = {yl, yl + h}
-    if slope != 0.0:
-        for level in (0.0, h):
-            yk = (xl + level - x_at_y0) / slope
-            if yl < yk < yl + h:
-                knots.add(yk)
-    ks = sorted(knots)
-    area = sum(0.5 * (g(a) + g(b)) * (b - a) for a, b in zip(ks[:-1], ks[1:]))
-    return area / (h * h)
-
-
 def _linear_setup(n, ny, slope, x_gamma, a_lam, x0):
     """2D grid n x ny, outflow; liquid left of the line x = x_gamma + slope y; face CFL
     numbers lam(x) = a_lam (x - x0) / h along x, none along y."""
     h = 1.0 / n
     shape = (1, ny, n)
-    c = np.zeros(shape)
-    for j in range(ny):
-        for i in range(n):
-            c[0, j, i] = _line_fraction(i * h, j * h, h, x_gamma, slope)
+    c = W.line_fraction_field(shape, h, x_gamma, slope)
     xf = np.arange(n + 1) * h
     lam = a_lam * (xf - x0) / h
     u = np.broadcast_to(lam, (1, ny, n + 1)).copy()
@@ -64,12 +42,7 @@ def _mapped_fractions(h, shape, x_gamma, slope, a_lam, x0):
     x = x_gamma + slope y goes to x = x_gamma + a_lam (x_gamma - x0) + slope (1 + a_lam) y."""
     k = 1.0 + a_lam
     xg = x_gamma + a_lam * (x_gamma - x0)
-    _, ny, n = shape
-    out = np.zeros(shape)
-    for j in range(ny):
-        for i in range(n):
-            out[0, j, i] = _line_fraction(i * h, j * h, h, xg, slope * k)
-    return out
+    return W.line_fraction_field(shape, h, xg, slope * k)
 
 
 def _sweep(orc, cfg, c, e, u, axis=0):
