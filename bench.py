@@ -338,6 +338,45 @@ def energy_flux_ablation(pcvof, torch, steps=10, timed_steps=50):
     return out
 
 
+def split_ablation(pcvof, torch, wl, steps=200, timed_steps=50):
+    """Weymouth-Yue split (the scheme the paper builds on) against the Lagrangian-
+    explicit sweeps of Li (CIAM), which section 3.3 names as the other scheme, on the
+    benchmark's LeVeque deformation field: the relative change of total volume and
+    energy after `steps` steps (walls with no normal flow: the exact change is zero),
+    the volume clipped into [0, 1] on the way, and the throughput of `timed_steps`
+    more steps."""
+    hv = wl.h ** wl.ndim
+    v0 = math.fsum(wl.c.ravel().tolist()) * hv
+    e0 = math.fsum(wl.e.ravel().tolist()) * hv
+    out = {"workload": wl.name, "steps": steps, "timed_steps": timed_steps}
+    for split in ("wy", "le"):
+        spec = pcvof.DomainSpec(shape=wl.shape, h=wl.h, ndim=wl.ndim, bc=wl.bc, cp_l=wl.cp_l, cp_g=wl.cp_g,
+                                normal=wl.normal, split=split)
+        d = pcvof.Domain(spec)
+        d.set_vof(wl.c)
+        d.set_energy(wl.e)
+        d.set_velocity(wl.u, wl.v, wl.w)
+        clip = 0.0
+        for k in range(steps):
+            st = d.step(wl.dt, wl.u_scale(k), stats=True)
+            clip += abs(st["vol_clip"])
+        c = d.vof().cpu().numpy()
+        stream = torch.cuda.current_stream()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for k in range(timed_steps):
+            d.step(wl.dt, wl.u_scale(steps + k))
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1)
+        out[split] = {"vol_change_rel": (st["vol"] - v0) / v0, "energy_change_rel": (st["energy"] - e0) / e0,
+                      "vol_clipped_rel": clip / v0, "c_min": float(c.min()), "c_max": float(c.max()),
+                      "value": wl.ncells * timed_steps / (ms * 1e-3), "unit": "cell-updates/s"}
+        del d
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(wl, budget_s=15.0, max_side=128):
     """The oracle on the host: whole steps of the workload until the budget is used (at
     least one step). Domains larger than max_side per axis are sampled: the oracle
@@ -377,7 +416,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64-only", action="store_true", help="skip the mixed-precision run")
     ap.add_argument("--no-ablation", action="store_true",
-                    help="skip the conservative / non-conservative energy flux comparison")
+                    help="skip the energy-flux and split-scheme ablations")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="first copy this many MiB device to device, a kernel of known traffic "
                          "for scaling the HBM byte counters of a profiler run")
@@ -458,6 +497,7 @@ def main():
         }
     if not args.no_ablation and args.workload == "leveque128":
         out["energy_flux_ablation"] = energy_flux_ablation(pcvof, torch)
+        out["split_ablation"] = split_ablation(pcvof, torch, wl)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)
