@@ -1,0 +1,202 @@
+"""Pins of the oracle's liquid-velocity extension (section 3.3.1, eq. press_inv and the
+correction u~ = -(dt / rho) grad p~).
+
+* A planar front (one layer of mixed cells): the correction is one-dimensional, and
+  conservation fixes it whatever the densities: u~ = -m'' (1/rho_g - 1/rho_l) A on the
+  mixed cell's gas-side face and on every face up to the fixed-pressure face between
+  the second and third gas neighbours, zero on the wall face to the liquid and
+  everywhere else; mirrored fronts and fronts along y give the mirrored results.
+* The discrete divergence of u~ is -m'' (1/rho_g - 1/rho_l) A in every sub-domain
+  cell and zero in the liquid, and the total source is fed through the fixed-pressure
+  faces (third gas layer and outflow boundaries).
+* A tilted straight front: each plane area is the exact length of the front's segment
+  in the cell.
+* Mirror and axis-swap symmetry of a sphere's correction.
+* Linear in m''; zero without a density jump.
+* A gas pocket with fewer than three gas layers, enclosed by liquid, is refused."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import extension as X
+
+
+def _cfg(shape, ndim, bc, rho_l=2.5, normal=1):
+    return oracle.Config(shape=shape, h=1.0 / shape[2], ndim=ndim, bc=bc, rho_l=rho_l, normal=normal)
+
+
+def _faces(shape, ndim):
+    nz, ny, nx = shape
+    u = np.zeros((nz, ny, nx + 1))
+    v = np.zeros((nz, ny + 1, nx))
+    w = np.zeros((nz + 1, ny, nx)) if ndim == 3 else None
+    return u, v, w
+
+
+def _divergence(du, dv, dw, ndim):
+    d = du[:, :, 1:] - du[:, :, :-1] + dv[:, 1:, :] - dv[:, :-1, :]
+    if ndim == 3:
+        d = d + dw[1:, :, :] - dw[:-1, :, :]
+    return d
+
+
+def _front_x(shape, xg, liquid_left=True):
+    nz, ny, nx = shape
+    c = np.zeros(shape)
+    for i in range(nx):
+        left = min(max(xg - i, 0.0), 1.0)  # fraction of cell i left of x = xg (cell units)
+        c[:, :, i] = left if liquid_left else 1.0 - left
+    return c
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+@pytest.mark.parametrize("liquid_left", [True, False])
+@pytest.mark.parametrize("bcx", [0, 1])
+def test_planar_front_exact_correction(ndim, liquid_left, bcx):
+    shape = (1 if ndim == 2 else 4, 5, 24)
+    xg = 10.4
+    c = _front_x(shape, xg, liquid_left)
+    rho_l, rho_g, md = 2.5, 0.25, 0.7
+    S = md * (1.0 / rho_g - 1.0 / rho_l)
+    cfg = _cfg(shape, ndim, (bcx, 0, 0), rho_l)
+    u, v, w = _faces(shape, ndim)
+    mdot = np.full(shape, md)
+    ul, vl, wl, (du, dv, dw), lab, _ = X.extend_velocity(cfg, c, u, v, w, mdot, rho_g)
+    want = np.zeros_like(du)
+    if liquid_left:
+        want[:, :, 11:14] = -S  # faces 10|11, 11|12, 12|13: mixed cell 10 to the third gas cell 13
+    else:
+        want[:, :, 8:11] = S    # faces 7|8, 8|9, 9|10: mixed cell 10 to the third gas cell 7
+    assert np.max(np.abs(du - want)) <= 1e-14 * S
+    assert np.max(np.abs(dv)) <= 1e-14 * S  # rows of the front are identical up to the solve's round-off
+    if ndim == 3:
+        assert np.max(np.abs(dw)) <= 1e-14 * S
+    assert np.array_equal(ul, u + du)
+    assert set(np.unique(lab[0, 0])) == {-1, 0, 1, 2, 3, X.FAR}
+
+
+def test_front_along_y():
+    shape = (1, 20, 6)
+    c = np.zeros(shape)
+    c[:, :8, :] = 1.0
+    c[:, 8, :] = 0.25
+    rho_l, rho_g, md = 1.0, 0.1, -0.4  # condensation
+    S = md * (1.0 / rho_g - 1.0 / rho_l)
+    cfg = _cfg(shape, 2, (0, 1, 0), rho_l)
+    u, v, w = _faces(shape, 2)
+    _, _, _, (du, dv, _), _, _ = X.extend_velocity(cfg, c, u, v, w, np.full(shape, md), rho_g)
+    want = np.zeros_like(dv)
+    want[:, 9:12, :] = -S
+    assert np.max(np.abs(dv - want)) <= 1e-14 * abs(S)
+    assert np.max(np.abs(du)) <= 1e-14 * abs(S)
+
+
+def _sphere(n, r, centre=None, inside_liquid=True):
+    from paper_2001_03477_amd import workloads as W
+    centre = [0.5, 0.5, 0.5] if centre is None else centre
+    return W.sphere_fraction((n, n, n), 1.0 / n, [np.array(centre)], [r], inside_liquid=inside_liquid)
+
+
+def test_divergence_and_total_flux():
+    n = 14
+    c = _sphere(n, 0.27, centre=[0.47, 0.52, 0.5])
+    rng = np.random.default_rng(5)
+    mdot = rng.uniform(-0.5, 1.0, size=c.shape)
+    rho_l, rho_g = 2.5, 0.25
+    for bc in ((0, 0, 0), (1, 1, 1)):
+        cfg = _cfg(c.shape, 3, bc, rho_l)
+        u, v, w = _faces(c.shape, 3)
+        _, _, _, (du, dv, dw), lab, _ = X.extend_velocity(cfg, c, u, v, w, mdot, rho_g)
+        div = _divergence(du, dv, dw, 3)
+        src = np.zeros(c.shape)
+        for idx in zip(*np.nonzero(lab == 0)):
+            src[idx] = mdot[idx] * (1 / rho_g - 1 / rho_l) * X.plane_area(oracle, cfg, c, idx)
+        sub = (lab >= 0) & (lab <= 2)
+        scale = np.max(np.abs(src))
+        assert np.max(np.abs(div[sub] + src[sub])) <= 1e-12 * scale
+        assert np.max(np.abs(div[lab == X.LIQUID])) <= 1e-12 * scale
+        assert np.all(div[lab == X.FAR] == 0.0)
+        # the source of the sub-domain is fed from the third gas layer and through the
+        # outflow boundaries (periodic axes: the last face is the first, the terms cancel)
+        out = sum(math.fsum(a.take(-1, axis=k).ravel()) - math.fsum(a.take(0, axis=k).ravel())
+                  for a, k in ((du, 2), (dv, 1), (dw, 0)))
+        assert math.fsum(div[lab == 3].ravel()) - out == pytest.approx(math.fsum(src[sub].ravel()), rel=1e-12)
+        if bc == (1, 1, 1):
+            assert abs(out) > 1e-3 * abs(math.fsum(src[sub].ravel()))  # the sphere's layers reach x = 0
+
+
+def test_tilted_front_plane_areas_are_segment_lengths():
+    """A straight front x = 9.3 + 0.3 y (cell units) in a strip with outflow walls: the
+    centred-column normals are exact on the rows whose 3x3 blocks stay inside the strip,
+    so each mixed cell's plane area there is the exact length of the front's segment in
+    that cell; the flux balance holds with the areas of all mixed cells."""
+    from paper_2001_03477_amd import workloads as W
+    nx, ny = 28, 10
+    shape = (1, ny, nx)
+    h = 1.0 / nx
+    slope = 0.3
+    c = W.line_fraction_field(shape, h, 9.3 * h, slope)
+    md, rho_l, rho_g = 0.6, 3.0, 0.5
+    S = md * (1 / rho_g - 1 / rho_l)
+    cfg = _cfg(shape, 2, (1, 1, 0), rho_l, normal=2)
+    u, v, w = _faces(shape, 2)
+    _, _, _, (du, dv, _), lab, _ = X.extend_velocity(cfg, c, u, v, w, np.full(shape, md), rho_g)
+    total = 0.0
+    checked = 0
+    for idx in zip(*np.nonzero(lab == 0)):
+        a = X.plane_area(oracle, cfg, c, idx)
+        total += a
+        _, j, i = idx
+        if 1 <= j <= ny - 2:
+            ylo, yhi = max(j, (i - 9.3) / slope), min(j + 1, (i + 1 - 9.3) / slope)
+            assert a == pytest.approx(max(0.0, yhi - ylo) * math.sqrt(1 + slope ** 2), rel=1e-13, abs=1e-14)
+            checked += 1
+    assert checked >= ny - 2
+    div = _divergence(du, dv, None, 2)
+    out = (math.fsum(du[:, :, -1].ravel()) - math.fsum(du[:, :, 0].ravel())
+           + math.fsum(dv[:, -1, :].ravel()) - math.fsum(dv[:, 0, :].ravel()))
+    assert math.fsum(div[lab == 3].ravel()) - out == pytest.approx(S * total, rel=1e-12)
+
+
+def test_sphere_symmetries():
+    n = 12
+    c = _sphere(n, 0.26)
+    rho_l, rho_g = 2.0, 0.2
+    cfg = _cfg(c.shape, 3, (0, 0, 0), rho_l, normal=0)
+    u, v, w = _faces(c.shape, 3)
+    _, _, _, (du, dv, dw), _, _ = X.extend_velocity(cfg, c, u, v, w, np.full(c.shape, 0.3), rho_g)
+    scale = np.max(np.abs(du))
+    assert scale > 0.0
+    # mirror x -> 1 - x: face f goes to face n - f and the x component changes sign
+    assert np.max(np.abs(du + du[:, :, ::-1])) <= 1e-12 * scale
+    # swapping the x and y axes swaps the components
+    assert np.max(np.abs(np.transpose(du, (0, 2, 1)) - dv)) <= 1e-12 * scale
+    assert np.max(np.abs(np.transpose(du, (2, 1, 0)) - dw)) <= 1e-12 * scale
+
+
+def test_linear_in_mdot_and_zero_without_density_jump():
+    n = 16
+    c = _sphere(n, 0.34, inside_liquid=False)  # a bubble wide enough for three gas layers
+    cfg = _cfg(c.shape, 3, (0, 0, 0), 2.5)
+    u, v, w = _faces(c.shape, 3)
+    md = np.random.default_rng(6).uniform(0.0, 1.0, size=c.shape)
+    _, _, _, d1, _, _ = X.extend_velocity(cfg, c, u, v, w, md, 0.25)
+    _, _, _, d2, _, _ = X.extend_velocity(cfg, c, u, v, w, 2.0 * md, 0.25)
+    for a, b in zip(d1, d2):
+        assert np.max(np.abs(b - 2.0 * a)) <= 1e-13 * np.max(np.abs(b))
+    _, _, _, d0, _, _ = X.extend_velocity(cfg, c, u, v, w, md, 2.5)
+    for a in d0:
+        assert np.all(a == 0.0)
+
+
+def test_enclosed_gas_pocket_is_refused():
+    n = 10
+    c = np.ones((n, n, n))
+    c[5, 5, 5] = 0.0
+    c[5, 5, 4] = c[5, 5, 6] = c[5, 4, 5] = c[5, 6, 5] = c[4, 5, 5] = c[6, 5, 5] = 0.5
+    cfg = _cfg(c.shape, 3, (0, 0, 0), 2.5)
+    u, v, w = _faces(c.shape, 3)
+    with pytest.raises(ValueError):
+        X.extend_velocity(cfg, c, u, v, w, np.full(c.shape, 0.1), 0.25)
