@@ -177,6 +177,43 @@ int pcvof_set_mass_flux(pcvof_handle* h, const double* mdot, int mem);
 int pcvof_compute_mass_flux(pcvof_handle* h, double k_l, double k_g, double h_fg, double* mdot_out,
                             double* dist_out, int mem);
 
+/* Liquid-velocity extension (section 3.3.1, eq. press_inv and the correction after
+   it). The stored face velocity u is taken as the one-fluid velocity, whose
+   divergence carries the phase-change source m'' (1/rho_g - 1/rho_l) delta_Gamma; the
+   call replaces it by the liquid velocity u_l = u + u~, which is divergence-free
+   where u carried that source:
+   * sub-domain: the mixed cells (eps < c < 1 - eps) and the gas cells that are first
+     or second face neighbours of them through gas (shortest path of face steps);
+     faces to liquid cells are walls (no correction), the faces to the third gas
+     neighbours and faces on outflow boundaries hold a fixed pressure;
+   * on it, sum over non-wall faces of (phi_j - phi_i) / rho_f = S a_i with
+     S = m'' (1/rho_g - 1/rho_l), a_i the area of the cell's PLIC plane (cell units,
+     the step's normal method and alpha from c), rho_f the mean of the two cells'
+     rho(c) = rho_l c + rho_g (1 - c) (a ghost beyond an outflow boundary copies its
+     cell), phi = 0 on the fixed-pressure side (phi = dt p~ / h: dt and h cancel);
+   * u~ = -(phi_R - phi_L) / rho_f on the faces of the sub-domain, zero elsewhere.
+   The system is solved by conjugate gradients (diagonal preconditioner, deterministic
+   reductions) until |r|_2 <= rel_tol |b|_2 (0 < rel_tol < 1), at most max_iter
+   iterations (>= 1). Needs the fractions, the velocity and the mass flux
+   (PCVOF_ERR_STATE otherwise); rho_g > 0. d_workspace: device memory of at least
+   pcvof_extension_workspace_bytes(h) bytes, owned by the caller, only used during the
+   call (PCVOF_ERR_WORKSPACE if smaller). du, dv, dw (optional, dw ignored in 2D)
+   receive u~ per face in the velocity layouts, in host (mem = 0) or device (mem = 1)
+   memory. info (optional) receives the number of unknowns, the iterations and the
+   final relative residual. When the iterations do not converge (a part of the
+   sub-domain with a source but without a fixed-pressure face has no solution), the
+   call returns PCVOF_ERR_STATE and leaves the velocity unchanged. Not inside a step,
+   not on a batch domain, at most 2^31 - 1 cells. */
+typedef struct {
+    long unknowns;
+    int iterations;
+    double rel_residual;
+} pcvof_ext_info;
+size_t pcvof_extension_workspace_bytes(pcvof_handle* h);
+int pcvof_extend_velocity(pcvof_handle* h, double rho_g, double rel_tol, int max_iter, void* d_workspace,
+                          size_t workspace_bytes, double* du, double* dv, double* dw, int mem,
+                          pcvof_ext_info* info);
+
 /* One time step with face CFL numbers lambda_f = u_f * (u_scale * dt) / h:
    prologue, ndim sweeps in the axis order rotated by the step counter (x,y,z /
    y,z,x / z,x,y), step 2 when a mass flux is set, checksums. Increments the step

@@ -31,7 +31,8 @@ Readings (the paper is silent on them):
   with S = m'' (1/rho_g - 1/rho_l), a the plane area in cell units, phi = 0 on the
   fixed-pressure side, and u~_f = -(phi_R - phi_L) / rho_f.
 * A part of the sub-domain with no fixed-pressure face (a gas pocket enclosed by
-  liquid with fewer than three gas layers) makes the problem singular: refused.
+  liquid with fewer than three gas layers) makes the problem singular: without a
+  source there, phi = 0 in it; with one, the extension is refused.
 """
 from __future__ import annotations
 
@@ -148,12 +149,19 @@ def extend_velocity(cfg, c, u, v, w, mdot, rho_g):
     phi_u = np.zeros(n)
     if n:
         A = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
-        # every connected part of the sub-domain must reach a fixed-pressure face
+        # a connected part of the sub-domain without a fixed-pressure face has a
+        # solution only without a source (then phi = 0 there); with one it is refused
         ncomp, comp = csg.connected_components(A, directed=False)
+        active = np.zeros(n, dtype=bool)
         for q in range(ncomp):
-            if not has_fixed[comp == q].any():
-                raise ValueError("a part of the extension sub-domain has no fixed-pressure face")
-        phi_u = spla.spsolve(A.tocsc(), b)
+            part = comp == q
+            if has_fixed[part].any():
+                active |= part
+            elif np.any(b[part] != 0.0):
+                raise ValueError("a part of the extension sub-domain with a source has no fixed-pressure face")
+        if active.any():
+            idx = np.nonzero(active)[0]
+            phi_u[idx] = spla.spsolve(A[idx][:, idx].tocsc(), b[idx])
     phi = np.zeros(c.shape)
     for k, cell in enumerate(cells):
         phi[cell] = phi_u[k]

@@ -8,12 +8,14 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <utility>
 #include <vector>
 
 #include "../../include/pcvof.h"
+#include "ext.h"
 #include "kernels.h"
 
 namespace {
@@ -675,6 +677,96 @@ int pcvof_compute_mass_flux(pcvof_handle* h, double k_l, double k_g, double h_fg
         if (int r = copy_out(h, mdot_out, h->mdot(), h->d.ncell, mem)) return r;
     if (dist_out && mem == PCVOF_MEM_HOST)
         if (int r = copy_out(h, dist_out, dist, h->d.ncell, mem)) return r;
+    return PCVOF_OK;
+}
+
+size_t pcvof_extension_workspace_bytes(pcvof_handle* h) {
+    if (!h || !h->ws) return 0;
+    long maxf = 1;
+    for (int a = 0; a < h->g.ndim; ++a) maxf = std::max(maxf, face_count(h->g, a));
+    return pcv::ext_layout(h->d, maxf).bytes;
+}
+
+int pcvof_extend_velocity(pcvof_handle* h, double rho_g, double rel_tol, int max_iter, void* d_workspace,
+                          size_t workspace_bytes, double* du, double* dv, double* dw, int mem,
+                          pcvof_ext_info* info) {
+    if (int r = check_handle(h)) return r;
+    if (!isfinite(rho_g) || !(rho_g > 0.0)) return fail(PCVOF_ERR_ARG, "rho_g must be positive");
+    if (!(rel_tol > 0.0 && rel_tol < 1.0)) return fail(PCVOF_ERR_ARG, "rel_tol must lie in (0, 1)");
+    if (max_iter < 1) return fail(PCVOF_ERR_ARG, "max_iter must be at least 1");
+    if (mem != PCVOF_MEM_HOST && mem != PCVOF_MEM_DEVICE) return fail(PCVOF_ERR_ARG, "bad mem");
+    if (h->batch_view) return fail(PCVOF_ERR_STATE, "the extension does not run on a batch domain");
+    if (h->in_step) return fail(PCVOF_ERR_STATE, "extend_velocity inside a step");
+    if (!h->has_vof || !h->has_vel || !h->has_mdot)
+        return fail(PCVOF_ERR_STATE, "fractions, velocity and mass flux must be set");
+    if (h->d.ncell > 2147483647L) return fail(PCVOF_ERR_ARG, "the extension handles at most 2^31 - 1 cells");
+    long maxf = 1;
+    for (int a = 0; a < h->g.ndim; ++a) maxf = std::max(maxf, face_count(h->g, a));
+    const pcv::ExtLayout L = pcv::ext_layout(h->d, maxf);
+    if (!d_workspace || workspace_bytes < L.bytes)
+        return fail(PCVOF_ERR_WORKSPACE, "extension workspace of %zu bytes, %zu needed", workspace_bytes, L.bytes);
+    const pcv::ExtIO io = pcv::ext_views(L, d_workspace);
+    const double* c = h->c(h->cur);
+    HIP_TRY(pcv::launch_ext_labels(h->d, c, io, h->stream));
+    int nu = 0;
+    HIP_TRY(hipMemcpyAsync(&nu, io.total, sizeof nu, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    int iters = 0;
+    double rel = 0.0;
+    if (nu > 0) {
+        HIP_TRY(pcv::launch_ext_assemble(h->d, c, h->mdot(), rho_g, nu, io, h->stream));
+        HIP_TRY(pcv::launch_cg_start(nu, io, h->stream));
+        double sc[pcv::kCgScalars];
+        HIP_TRY(hipMemcpyAsync(sc, io.scal, sizeof sc, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        const double gg = sc[pcv::kCgGg];
+        if (!isfinite(gg)) return fail(PCVOF_ERR_NONFINITE, "extension: non-finite source (mass flux or fractions)");
+        if (gg > 0.0) {
+            double rr = sc[pcv::kCgRr];
+            bool conv = sqrt(rr) <= rel_tol * sqrt(gg);
+            while (!conv && iters < max_iter) {
+                HIP_TRY(pcv::launch_cg_iteration(nu, io, h->stream));
+                ++iters;
+                if (iters % 4 == 0 || iters == max_iter) {
+                    HIP_TRY(hipMemcpyAsync(sc, io.scal, sizeof sc, hipMemcpyDeviceToHost, h->stream));
+                    HIP_TRY(hipStreamSynchronize(h->stream));
+                    rr = sc[pcv::kCgRr];
+                    if (!isfinite(rr)) break;
+                    conv = sqrt(rr) <= rel_tol * sqrt(gg);
+                }
+            }
+            rel = sqrt(rr / gg);
+            if (!conv)
+                return fail(PCVOF_ERR_STATE,
+                            "extension: conjugate gradients reached a relative residual of %.3g, not %.3g, in %d "
+                            "iterations (a part of the sub-domain with a source may have no fixed-pressure face)",
+                            rel, rel_tol, iters);
+        }
+    }
+    double* outs[3] = {du, dv, dw};
+    for (int a = 0; a < h->g.ndim; ++a) {
+        const long nf = face_count(h->g, a);
+        double* dev_out = (outs[a] && mem == PCVOF_MEM_DEVICE) ? outs[a] : nullptr;
+        HIP_TRY(pcv::launch_ext_faces(h->d, a, c, rho_g, h->vel(a), h->mixed() ? 1 : 0, dev_out, io, h->stream));
+        if (outs[a] && mem == PCVOF_MEM_HOST)
+            if (int r = copy_out(h, outs[a], io.du, nf, mem)) return r;
+        // the new velocity and its largest magnitude (the CFL check of the steps)
+        HIP_TRY(hipMemsetAsync(h->flags(), 0, 16, h->stream));
+        HIP_TRY(pcv::launch_maxabs(io.ul, nf, h->maxbits(), h->stream));
+        if (h->mixed()) HIP_TRY(pcv::launch_to_float(nf, io.ul, (float*)h->vel(a), h->stream));
+        else HIP_TRY(hipMemcpyAsync(h->vel(a), io.ul, nf * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+        unsigned long long mb = 0;
+        HIP_TRY(hipMemcpyAsync(&mb, h->maxbits(), sizeof mb, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        double m;
+        memcpy(&m, &mb, sizeof m);
+        h->umax[a] = m;
+    }
+    if (info) {
+        info->unknowns = nu;
+        info->iterations = iters;
+        info->rel_residual = rel;
+    }
     return PCVOF_OK;
 }
 

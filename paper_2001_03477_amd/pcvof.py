@@ -32,6 +32,7 @@ EXPORTS = (
     "pcvof_get_profile", "pcvof_batch_workspace_bytes", "pcvof_batch_create", "pcvof_batch_destroy",
     "pcvof_batch_domain", "pcvof_batch_advect_step", "pcvof_batch_get_step", "pcvof_batch_set_tiles",
     "pcvof_batch_get_tiles", "pcvof_batch_autotune", "pcvof_compute_mass_flux",
+    "pcvof_extension_workspace_bytes", "pcvof_extend_velocity",
 )
 
 PROF_NAMES = ("sweep_x", "sweep_y", "sweep_z", "phase", "checksum")
@@ -64,6 +65,13 @@ class Stats(C.Structure):
 
     def as_dict(self):
         return {n: getattr(self, n) for n in STAT_NAMES}
+
+
+class ExtInfo(C.Structure):
+    _fields_ = [("unknowns", C.c_long), ("iterations", C.c_int), ("rel_residual", C.c_double)]
+
+    def as_dict(self):
+        return {"unknowns": self.unknowns, "iterations": self.iterations, "rel_residual": self.rel_residual}
 
 
 class Profile(C.Structure):
@@ -125,9 +133,14 @@ def lib():
         L.pcvof_batch_get_tiles.argtypes = [_vp, _vp, _vp]
         L.pcvof_batch_autotune.argtypes = [_vp, _vp, C.c_int, _vp]
         L.pcvof_compute_mass_flux.argtypes = [_vp, C.c_double, C.c_double, C.c_double, _vp, _vp, C.c_int]
+        L.pcvof_extension_workspace_bytes.restype = C.c_size_t
+        L.pcvof_extension_workspace_bytes.argtypes = [_vp]
+        L.pcvof_extend_velocity.argtypes = [_vp, C.c_double, C.c_double, C.c_int, _vp, C.c_size_t, _vp, _vp,
+                                            _vp, C.c_int, C.POINTER(ExtInfo)]
         for nm in EXPORTS:
             f = getattr(L, nm)
-            if nm not in ("pcvof_workspace_bytes", "pcvof_last_error", "pcvof_batch_workspace_bytes"):
+            if nm not in ("pcvof_workspace_bytes", "pcvof_last_error", "pcvof_batch_workspace_bytes",
+                          "pcvof_extension_workspace_bytes"):
                 f.restype = C.c_int
         _lib = L
     return _lib
@@ -258,6 +271,25 @@ class Domain:
 
     def temperature(self):
         return self._get(lib().pcvof_get_temperature)
+
+    def extend_velocity(self, rho_g: float, rel_tol: float = 1e-13, max_iter: int = 5000,
+                        corrections: bool = False):
+        """Liquid-velocity extension (section 3.3.1): the stored velocity becomes
+        u + u~. Returns (info dict, (du, dv, dw) device tensors or None)."""
+        import torch
+        nbytes = lib().pcvof_extension_workspace_bytes(self._h)
+        ws = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=self.device)
+        outs = [None, None, None]
+        if corrections:
+            nz, ny, nx = self.spec.shape
+            shapes = [(nz, ny, nx + 1), (nz, ny + 1, nx), (nz + 1, ny, nx)]
+            for a in range(self.spec.ndim):
+                outs[a] = torch.empty(shapes[a], dtype=torch.float64, device=self.device)
+        info = ExtInfo()
+        check(lib().pcvof_extend_velocity(self._h, float(rho_g), float(rel_tol), int(max_iter), ws.data_ptr(),
+                                          int(nbytes), *[o.data_ptr() if o is not None else None for o in outs],
+                                          PCVOF_MEM_DEVICE, C.byref(info)))
+        return info.as_dict(), (tuple(outs) if corrections else None)
 
     def compute_mass_flux(self, k_l: float, k_g: float, h_fg: float, distances: bool = False):
         """m'' from the PLIC reconstruction of the current state (section 3.2); it becomes

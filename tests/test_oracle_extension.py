@@ -13,7 +13,8 @@ correction u~ = -(dt / rho) grad p~).
   in the cell.
 * Mirror and axis-swap symmetry of a sphere's correction.
 * Linear in m''; zero without a density jump.
-* A gas pocket with fewer than three gas layers, enclosed by liquid, is refused."""
+* A gas pocket with fewer than three gas layers, enclosed by liquid, is refused when
+  it holds a source, and gets no correction otherwise."""
 import math
 
 import numpy as np
@@ -200,3 +201,7 @@ def test_enclosed_gas_pocket_is_refused():
     u, v, w = _faces(c.shape, 3)
     with pytest.raises(ValueError):
         X.extend_velocity(cfg, c, u, v, w, np.full(c.shape, 0.1), 0.25)
+    # without a source in the pocket its correction is zero
+    _, _, _, d0, _, _ = X.extend_velocity(cfg, c, u, v, w, np.zeros(c.shape), 0.25)
+    for a in d0:
+        assert np.all(a == 0.0)
