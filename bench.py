@@ -377,6 +377,32 @@ def split_ablation(pcvof, torch, wl, steps=200, timed_steps=50):
     return out
 
 
+def extension_timing(pcvof, torch, wl, rho_g, calls=5):
+    """The liquid-velocity extension (section 3.3.1) on the workload's fractions and
+    mass flux: wall time per pcvof_extend_velocity call (labels, compaction, assembly,
+    conjugate gradients with their host convergence checks, face corrections), median
+    of `calls` calls after one untimed call, with the solver's unknowns, iterations and
+    final relative residual. Not part of the advection step that `value` times."""
+    spec = pcvof.DomainSpec(shape=wl.shape, h=wl.h, ndim=wl.ndim, bc=wl.bc, cp_l=wl.cp_l, cp_g=wl.cp_g,
+                            rho_l=wl.rho_l, T_gamma=wl.T_gamma, normal=wl.normal)
+    d = pcvof.Domain(spec)
+    d.set_vof(wl.c)
+    d.set_energy(wl.e)
+    d.set_velocity(wl.u, wl.v, wl.w)
+    d.set_mass_flux(wl.mdot)
+    info, _ = d.extend_velocity(rho_g)
+    times = []
+    for _ in range(calls):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info, _ = d.extend_velocity(rho_g)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    del d
+    torch.cuda.empty_cache()
+    return {"ms": float(np.median(times)), "rho_g": rho_g, **info, "rel_tol": 1e-13}
+
+
 def cpu_baseline(wl, budget_s=15.0, max_side=128):
     """The oracle on the host: whole steps of the workload until the budget is used (at
     least one step). Domains larger than max_side per axis are sampled: the oracle
@@ -498,6 +524,9 @@ def main():
     if not args.no_ablation and args.workload == "leveque128":
         out["energy_flux_ablation"] = energy_flux_ablation(pcvof, torch)
         out["split_ablation"] = split_ablation(pcvof, torch, wl)
+    if args.workload == "bubble256":
+        # vapour density of the paper's superheated-bubble case (its liquid one is rho_l)
+        out["extension"] = extension_timing(pcvof, torch, wl, 0.25)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

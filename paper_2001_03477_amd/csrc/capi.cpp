@@ -727,7 +727,7 @@ int pcvof_extend_velocity(pcvof_handle* h, double rho_g, double rel_tol, int max
             while (!conv && iters < max_iter) {
                 HIP_TRY(pcv::launch_cg_iteration(nu, io, h->stream));
                 ++iters;
-                if (iters % 4 == 0 || iters == max_iter) {
+                if (iters % 8 == 0 || iters == max_iter) {  // one host synchronisation per 8 iterations
                     HIP_TRY(hipMemcpyAsync(sc, io.scal, sizeof sc, hipMemcpyDeviceToHost, h->stream));
                     HIP_TRY(hipStreamSynchronize(h->stream));
                     rr = sc[pcv::kCgRr];
@@ -746,15 +746,14 @@ int pcvof_extend_velocity(pcvof_handle* h, double rho_g, double rel_tol, int max
     double* outs[3] = {du, dv, dw};
     for (int a = 0; a < h->g.ndim; ++a) {
         const long nf = face_count(h->g, a);
-        double* dev_out = (outs[a] && mem == PCVOF_MEM_DEVICE) ? outs[a] : nullptr;
-        HIP_TRY(pcv::launch_ext_faces(h->d, a, c, rho_g, h->vel(a), h->mixed() ? 1 : 0, dev_out, io, h->stream));
+        double* dout = outs[a] ? (mem == PCVOF_MEM_DEVICE ? outs[a] : io.du) : nullptr;
+        // the stored velocity becomes u + u~ in place, with its largest magnitude (the
+        // CFL check of the steps)
+        HIP_TRY(hipMemsetAsync(h->flags(), 0, 16, h->stream));
+        HIP_TRY(pcv::launch_ext_faces(h->d, a, c, rho_g, h->vel(a), h->mixed() ? 1 : 0, dout, h->maxbits(), io,
+                                      h->stream));
         if (outs[a] && mem == PCVOF_MEM_HOST)
             if (int r = copy_out(h, outs[a], io.du, nf, mem)) return r;
-        // the new velocity and its largest magnitude (the CFL check of the steps)
-        HIP_TRY(hipMemsetAsync(h->flags(), 0, 16, h->stream));
-        HIP_TRY(pcv::launch_maxabs(io.ul, nf, h->maxbits(), h->stream));
-        if (h->mixed()) HIP_TRY(pcv::launch_to_float(nf, io.ul, (float*)h->vel(a), h->stream));
-        else HIP_TRY(hipMemcpyAsync(h->vel(a), io.ul, nf * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
         unsigned long long mb = 0;
         HIP_TRY(hipMemcpyAsync(&mb, h->maxbits(), sizeof mb, hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));

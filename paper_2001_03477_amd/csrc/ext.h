@@ -16,7 +16,7 @@ struct ExtIO {
     int8_t* lab;      // per cell: 0 mixed, 1..3 gas layers, -1 liquid, kExtFar other gas
     int* map;         // per cell: index among the unknowns, or -1
     int* list;        // per unknown: its cell
-    int* counts;      // per block of cells: number of unknowns; then exclusive offsets
+    int* counts;      // per run of kExtCells cells: number of unknowns; then exclusive offsets
     int* offs;
     int* total;       // number of unknowns
     int* nbr;         // per unknown, 6 slots: neighbouring unknown or -1
@@ -26,16 +26,17 @@ struct ExtIO {
     double *x, *r, *z, *p, *q;  // conjugate-gradient vectors
     double* part;     // per block: two partial sums
     double* scal;     // scalars of the iteration (kCg*)
-    double* ul;       // face buffer: u + u~ of one axis
-    double* du;       // face buffer: u~ of one axis
+    double* du;       // face buffer: u~ of one axis (for host output)
 };
 
 constexpr int kExtFar = 100;
 constexpr int kExtBlock = 256;
+constexpr int kExtCells = 4096;     // cells per run of the compaction
+constexpr int kExtScanBlock = 1024;
 enum { kCgRz = 0, kCgAlpha = 1, kCgBeta = 2, kCgRr = 3, kCgGg = 4, kCgScalars = 8 };
 
 struct ExtLayout {
-    size_t lab, map, list, counts, offs, total, nbr, coef, dg, g, vec[5], part, scal, ul, du, bytes;
+    size_t lab, map, list, counts, offs, total, nbr, coef, dg, g, vec[5], part, scal, du, bytes;
 };
 ExtLayout ext_layout(const Dom& d, long max_faces);
 ExtIO ext_views(const ExtLayout& L, void* ws);
@@ -49,9 +50,10 @@ hipError_t launch_ext_assemble(const Dom& d, const double* c, const double* mdot
 // iteration; scal[kCgRr] and scal[kCgGg] hold |r|^2 and |g|^2 after each.
 hipError_t launch_cg_start(int nu, const ExtIO& io, hipStream_t s);
 hipError_t launch_cg_iteration(int nu, const ExtIO& io, hipStream_t s);
-// u + u~ (into io.ul) and u~ (into du_out, or io.du when du_out is null) on the faces
-// of axis; vel is the stored velocity (float when mixed).
-hipError_t launch_ext_faces(const Dom& d, int axis, const double* c, double rho_g, const void* vel, int mixed,
-                            double* du_out, const ExtIO& io, hipStream_t s);
+// The stored velocity of axis (float when mixed) becomes u + u~ in place; du (may be
+// null) receives u~ per face; *maxbits (zeroed by the caller) the largest |u + u~| as
+// the bit pattern of a non-negative double.
+hipError_t launch_ext_faces(const Dom& d, int axis, const double* c, double rho_g, void* vel, int mixed, double* du,
+                            unsigned long long* maxbits, const ExtIO& io, hipStream_t s);
 
 }  // namespace pcv

@@ -115,12 +115,15 @@ __global__ void __launch_bounds__(kExtBlock) k_ext_dilate(Dom d, int8_t* __restr
     }
 }
 
-// Unknowns of each block of kExtBlock cells.
+// Unknowns of each run of kExtCells cells (one block walks its run in kExtBlock-cell
+// pieces).
 __global__ void __launch_bounds__(kExtBlock) k_ext_count(Dom d, const int8_t* __restrict__ lab, int* __restrict__ counts) {
     __shared__ int s_n[kExtBlock / 64];
-    const long i = (long)blockIdx.x * kExtBlock + threadIdx.x;
-    const bool u = i < d.ncell && unknown(lab[i]);
-    const int nw = __popcll(__ballot(u));
+    int nw = 0;
+    for (int piece = 0; piece < kExtCells / kExtBlock; ++piece) {
+        const long i = (long)blockIdx.x * kExtCells + piece * kExtBlock + threadIdx.x;
+        nw += __popcll(__ballot(i < d.ncell && unknown(lab[i])));
+    }
     if ((threadIdx.x & 63) == 0) s_n[threadIdx.x >> 6] = nw;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -130,47 +133,52 @@ __global__ void __launch_bounds__(kExtBlock) k_ext_count(Dom d, const int8_t* __
     }
 }
 
-// Exclusive offsets of the block counts (one block walks them in chunks) and the total.
-__global__ void __launch_bounds__(kExtBlock) k_ext_scan(const int* __restrict__ counts, int nb, int* __restrict__ offs,
-                                                        int* __restrict__ total) {
-    __shared__ int s_v[kExtBlock];
+// Exclusive offsets of the run counts (one block walks them in chunks) and the total.
+__global__ void __launch_bounds__(kExtScanBlock) k_ext_scan(const int* __restrict__ counts, int nb, int* __restrict__ offs,
+                                                            int* __restrict__ total) {
+    __shared__ int s_v[kExtScanBlock];
     int carry = 0;
-    for (int base = 0; base < nb; base += kExtBlock) {
+    for (int base = 0; base < nb; base += kExtScanBlock) {
         const int i = base + (int)threadIdx.x;
         const int v = i < nb ? counts[i] : 0;
         s_v[threadIdx.x] = v;
         __syncthreads();
         // inclusive scan in LDS (Hillis-Steele)
-        for (int off = 1; off < kExtBlock; off <<= 1) {
+        for (int off = 1; off < kExtScanBlock; off <<= 1) {
             const int add = threadIdx.x >= (unsigned)off ? s_v[threadIdx.x - off] : 0;
             __syncthreads();
             s_v[threadIdx.x] += add;
             __syncthreads();
         }
         if (i < nb) offs[i] = carry + s_v[threadIdx.x] - v;
-        carry += s_v[kExtBlock - 1];
+        carry += s_v[kExtScanBlock - 1];
         __syncthreads();
     }
     if (threadIdx.x == 0) *total = carry;
 }
 
-// list[offset + rank] = cell for the unknowns of each block, in cell order; map[cell]
-// = its index (or -1).
+// list[offset + rank] = cell for the unknowns of each run, in cell order; map[cell] =
+// its index (or -1).
 __global__ void __launch_bounds__(kExtBlock) k_ext_scatter(Dom d, const int8_t* __restrict__ lab, const int* __restrict__ offs,
                                                            int* __restrict__ list, int* __restrict__ map) {
     __shared__ int s_n[kExtBlock / 64];
-    const long i = (long)blockIdx.x * kExtBlock + threadIdx.x;
-    const bool u = i < d.ncell && unknown(lab[i]);
-    const unsigned long long b = __ballot(u);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane == 0) s_n[w] = __popcll(b);
-    __syncthreads();
-    int pos = offs[blockIdx.x];
-    for (int k = 0; k < w; ++k) pos += s_n[k];
-    pos += __popcll(b & __lanemask_lt());
-    if (i < d.ncell) {
-        map[i] = u ? pos : -1;
-        if (u) list[pos] = (int)i;
+    int base = offs[blockIdx.x];
+    for (int piece = 0; piece < kExtCells / kExtBlock; ++piece) {
+        const long i = (long)blockIdx.x * kExtCells + piece * kExtBlock + threadIdx.x;
+        const bool u = i < d.ncell && unknown(lab[i]);
+        const unsigned long long b = __ballot(u);
+        if (lane == 0) s_n[w] = __popcll(b);
+        __syncthreads();
+        int pos = base;
+        for (int k = 0; k < w; ++k) pos += s_n[k];
+        pos += __popcll(b & __lanemask_lt());
+        if (i < d.ncell) {
+            map[i] = u ? pos : -1;
+            if (u) list[pos] = (int)i;
+        }
+        for (int k = 0; k < kExtBlock / 64; ++k) base += s_n[k];
+        __syncthreads();  // s_n is rewritten by the next piece
     }
 }
 
@@ -346,15 +354,12 @@ __global__ void __launch_bounds__(kExtBlock) k_cg_reduce(const double* __restric
     }
 }
 
-// Face f of axis between cells L = f - 1 and R = f (periodic axes: face n is face 0).
+// The correction of face i of axis; returns the new velocity.
 template <typename T>
-__global__ void __launch_bounds__(kExtBlock) k_ext_faces(Dom d, int axis, long nf, const double* __restrict__ c,
-                                                         double rho_g, const int8_t* __restrict__ lab,
-                                                         const int* __restrict__ map, const double* __restrict__ phi,
-                                                         const T* __restrict__ vel, double* __restrict__ ul,
-                                                         double* __restrict__ du) {
-    const long i = (long)blockIdx.x * kExtBlock + threadIdx.x;
-    if (i >= nf) return;
+__device__ __forceinline__ double face_update(const Dom& d, int axis, long i, const double* __restrict__ c, double rho_g,
+                                              const int8_t* __restrict__ lab, const int* __restrict__ map,
+                                              const double* __restrict__ phi, T* __restrict__ vel,
+                                              double* __restrict__ du) {
     const long nx = d.n[0], ny = d.n[1];
     int q[3], f;
     if (axis == 0) {
@@ -398,11 +403,42 @@ __global__ void __launch_bounds__(kExtBlock) k_ext_faces(Dom d, int axis, long n
         v = -(pR - pL) / (0.5 * (rL + rR));
     }
     const double u0 = (double)vel[i];
-    ul[i] = v != 0.0 ? u0 + v : u0;
-    du[i] = v;
+    if (du) du[i] = v;
+    if (v == 0.0) return u0;
+    const double u1 = u0 + v;
+    vel[i] = (T)u1;
+    return u1;
 }
 
+// Face f of axis between cells L = f - 1 and R = f (periodic axes: face n is face 0):
+// the stored velocity becomes u + u~ in place, du (if not null) receives u~, and the
+// largest |u + u~| of the block goes into *maxbits (atomic max of the bit pattern of a
+// non-negative double).
+template <typename T>
+__global__ void __launch_bounds__(kExtBlock) k_ext_faces(Dom d, int axis, long nf, const double* __restrict__ c,
+                                                         double rho_g, const int8_t* __restrict__ lab,
+                                                         const int* __restrict__ map, const double* __restrict__ phi,
+                                                         T* __restrict__ vel, double* __restrict__ du,
+                                                         unsigned long long* __restrict__ maxbits) {
+    __shared__ double s_m[kExtBlock / 64];
+    double mx = 0.0;
+    // grid-stride over the faces: few blocks, so that few atomics meet on *maxbits
+    for (long i = (long)blockIdx.x * kExtBlock + threadIdx.x; i < nf; i += (long)gridDim.x * kExtBlock)
+        mx = fmax(mx, fabs(face_update(d, axis, i, c, rho_g, lab, map, phi, vel, du)));
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_down(mx, off, 64));
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kExtBlock / 64; ++w) mx = fmax(mx, s_m[w]);
+        if (mx > 0.0) atomicMax(maxbits, (unsigned long long)__double_as_longlong(mx));
+    }
+}
+
+
+constexpr int kExtFaceBlocks = 2048;  // grid of the face pass (eight blocks per compute unit)
+
 int blocks_for(long n) { return (int)((n + kExtBlock - 1) / kExtBlock); }
+int runs_for(long n) { return (int)((n + kExtCells - 1) / kExtCells); }
 
 }  // namespace
 
@@ -410,6 +446,7 @@ ExtLayout ext_layout(const Dom& d, long max_faces) {
     ExtLayout L;
     const size_t n = (size_t)d.ncell;
     const size_t nb = (size_t)blocks_for(d.ncell);
+    const size_t nr = (size_t)runs_for(d.ncell);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t at = off;
@@ -419,8 +456,8 @@ ExtLayout ext_layout(const Dom& d, long max_faces) {
     L.lab = take(n);
     L.map = take(n * sizeof(int));
     L.list = take(n * sizeof(int));
-    L.counts = take(nb * sizeof(int));
-    L.offs = take(nb * sizeof(int));
+    L.counts = take(nr * sizeof(int));
+    L.offs = take(nr * sizeof(int));
     L.total = take(sizeof(int));
     L.nbr = take(n * kNeighbours * sizeof(int));
     L.coef = take(n * kNeighbours * sizeof(double));
@@ -429,7 +466,6 @@ ExtLayout ext_layout(const Dom& d, long max_faces) {
     for (int k = 0; k < 5; ++k) L.vec[k] = take(n * sizeof(double));
     L.part = take(2 * nb * sizeof(double));
     L.scal = take(kCgScalars * sizeof(double));
-    L.ul = take((size_t)max_faces * sizeof(double));
     L.du = take((size_t)max_faces * sizeof(double));
     L.bytes = off;
     return L;
@@ -455,7 +491,6 @@ ExtIO ext_views(const ExtLayout& L, void* ws) {
     io.q = (double*)(b + L.vec[4]);
     io.part = (double*)(b + L.part);
     io.scal = (double*)(b + L.scal);
-    io.ul = (double*)(b + L.ul);
     io.du = (double*)(b + L.du);
     return io;
 }
@@ -463,11 +498,12 @@ ExtIO ext_views(const ExtLayout& L, void* ws) {
 hipError_t launch_ext_labels(const Dom& d, const double* c, const ExtIO& io, hipStream_t s) {
     const int nb = blocks_for(d.ncell);
     const int ng = nb < 8192 ? nb : 8192;  // grid-stride kernels
+    const int nr = runs_for(d.ncell);
     hipLaunchKernelGGL(k_ext_init, dim3(ng), dim3(kExtBlock), 0, s, d, c, io.lab);
     for (int k = 1; k <= 3; ++k) hipLaunchKernelGGL(k_ext_dilate, dim3(ng), dim3(kExtBlock), 0, s, d, io.lab, k);
-    hipLaunchKernelGGL(k_ext_count, dim3(nb), dim3(kExtBlock), 0, s, d, io.lab, io.counts);
-    hipLaunchKernelGGL(k_ext_scan, dim3(1), dim3(kExtBlock), 0, s, io.counts, nb, io.offs, io.total);
-    hipLaunchKernelGGL(k_ext_scatter, dim3(nb), dim3(kExtBlock), 0, s, d, io.lab, io.offs, io.list, io.map);
+    hipLaunchKernelGGL(k_ext_count, dim3(nr), dim3(kExtBlock), 0, s, d, io.lab, io.counts);
+    hipLaunchKernelGGL(k_ext_scan, dim3(1), dim3(kExtScanBlock), 0, s, io.counts, nr, io.offs, io.total);
+    hipLaunchKernelGGL(k_ext_scatter, dim3(nr), dim3(kExtBlock), 0, s, d, io.lab, io.offs, io.list, io.map);
     return hipGetLastError();
 }
 
@@ -498,19 +534,19 @@ hipError_t launch_cg_iteration(int nu, const ExtIO& io, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_ext_faces(const Dom& d, int axis, const double* c, double rho_g, const void* vel, int mixed,
-                            double* du_out, const ExtIO& io, hipStream_t s) {
+hipError_t launch_ext_faces(const Dom& d, int axis, const double* c, double rho_g, void* vel, int mixed, double* du,
+                            unsigned long long* maxbits, const ExtIO& io, hipStream_t s) {
     long nf;
     if (axis == 0) nf = (long)(d.n[0] + 1) * d.n[1] * d.n[2];
     else if (axis == 1) nf = (long)d.n[0] * (d.n[1] + 1) * d.n[2];
     else nf = (long)d.n[0] * d.n[1] * (d.n[2] + 1);
-    double* du = du_out ? du_out : io.du;
+    const int nb = blocks_for(nf) < kExtFaceBlocks ? blocks_for(nf) : kExtFaceBlocks;
     if (mixed)
-        hipLaunchKernelGGL(k_ext_faces<float>, dim3(blocks_for(nf)), dim3(kExtBlock), 0, s, d, axis, nf, c, rho_g,
-                           io.lab, io.map, io.x, (const float*)vel, io.ul, du);
+        hipLaunchKernelGGL(k_ext_faces<float>, dim3(nb), dim3(kExtBlock), 0, s, d, axis, nf, c, rho_g, io.lab,
+                           io.map, io.x, (float*)vel, du, maxbits);
     else
-        hipLaunchKernelGGL(k_ext_faces<double>, dim3(blocks_for(nf)), dim3(kExtBlock), 0, s, d, axis, nf, c, rho_g,
-                           io.lab, io.map, io.x, (const double*)vel, io.ul, du);
+        hipLaunchKernelGGL(k_ext_faces<double>, dim3(nb), dim3(kExtBlock), 0, s, d, axis, nf, c, rho_g, io.lab,
+                           io.map, io.x, (double*)vel, du, maxbits);
     return hipGetLastError();
 }
 
