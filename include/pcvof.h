@@ -214,6 +214,37 @@ int pcvof_extend_velocity(pcvof_handle* h, double rho_g, double rel_tol, int max
                           size_t workspace_bytes, double* du, double* dv, double* dw, int mem,
                           pcvof_ext_info* info);
 
+/* Implicit energy diffusion with the interface temperature imposed (section 3.4.2,
+   eqs. T_diff_disc and mod_branchesT), one backward-Euler step of length dt on the
+   current state:
+   * a node is liquid when c >= 1/2, else gas, and diffuses with its phase's constant
+     conductivity (k_l, k_g) and volumetric heat capacity (params cp_l, cp_g);
+   * towards a face neighbour of the same phase the gradient is the difference over h;
+     towards one of the other phase the interface is a boundary at distance theta where
+     T = T_Gamma (params T_gamma): the gradient is (T_Gamma - T_i) / theta and the
+     node's control width along that axis becomes (h + theta) / 2 ((theta_L + theta_R) / 2
+     with the interface on both sides);
+   * theta is the height of the six-cell column centred on the face when that column is
+     bounded by pure cells of the two phases, else the point where the linear
+     interpolation of the node phase's indicator between the two nodes crosses 1/2,
+     capped to [1e-3 h, h];
+   * outflow boundaries are adiabatic, periodic axes wrap;
+   * the temperature before the step is e / C_p(c) (one-fluid C_p), the energy after it
+     C_p(c) T^{n+1}.
+   The non-symmetric system is solved by BiCGSTAB (diagonal preconditioner,
+   deterministic reductions) from T*, until |r|_2 <= rel_tol |b|_2 (0 < rel_tol < 1), at
+   most max_iter iterations (>= 1); without convergence PCVOF_ERR_STATE and the energy
+   is unchanged. dt > 0, k_l, k_g >= 0 (PCVOF_ERR_ARG otherwise); needs the fractions
+   and energies (PCVOF_ERR_STATE); not inside a step, not on a batch domain.
+   d_workspace: device memory of at least pcvof_diffusion_workspace_bytes(h) bytes,
+   owned by the caller, used during the call only (PCVOF_ERR_WORKSPACE if smaller).
+   T_out (optional) receives T^{n+1} in the cell layout, in host (mem = 0) or device
+   (mem = 1) memory; info (optional) the iterations and final relative residual
+   (unknowns = cells). */
+size_t pcvof_diffusion_workspace_bytes(pcvof_handle* h);
+int pcvof_diffuse(pcvof_handle* h, double dt, double k_l, double k_g, double rel_tol, int max_iter, void* d_workspace,
+                  size_t workspace_bytes, double* T_out, int mem, pcvof_ext_info* info);
+
 /* One time step with face CFL numbers lambda_f = u_f * (u_scale * dt) / h:
    prologue, ndim sweeps in the axis order rotated by the step counter (x,y,z /
    y,z,x / z,x,y), step 2 when a mass flux is set, checksums. Increments the step

@@ -110,33 +110,39 @@ def _stencil(cfg, c, idx, k_l, k_g):
     return out
 
 
-def apply_operator(cfg, c, T, k_l, k_g, T_gamma):
-    """(1/V) integral of div(k grad T) at every node by eq. T_diff_disc with the
-    gradients of eq. mod_branchesT (physical units, h = cfg.h)."""
+def operator_at(cfg, c, T, idx, k_l, k_g, T_gamma):
+    """(1/V) integral of div(k grad T) at node idx by eq. T_diff_disc with the gradients
+    of eq. mod_branchesT (physical units, h = cfg.h)."""
     h = cfg.h
+    k = k_l if c[idx] >= 0.5 else k_g
+    acc = 0.0
+    for sides, width in _stencil(cfg, c, idx, k_l, k_g):
+        grads = []
+        for sgn, (kind, j, w) in zip((-1, 1), sides):
+            if kind == "wall":
+                g = 0.0
+            elif kind == "node":
+                g = (T[j] - T[idx]) / h if sgn > 0 else (T[idx] - T[j]) / h
+            else:
+                g = (T_gamma - T[idx]) / (w * h) if sgn > 0 else (T[idx] - T_gamma) / (w * h)
+            grads.append(g)
+        acc += (grads[1] - grads[0]) / (width * h)
+    return k * acc
+
+
+def apply_operator(cfg, c, T, k_l, k_g, T_gamma):
+    """operator_at at every node."""
     L = np.zeros(c.shape)
     for idx in np.ndindex(*c.shape):
-        k = k_l if c[idx] >= 0.5 else k_g
-        acc = 0.0
-        for sides, width in _stencil(cfg, c, idx, k_l, k_g):
-            grads = []
-            for sgn, (kind, j, w) in zip((-1, 1), sides):
-                if kind == "wall":
-                    g = 0.0
-                elif kind == "node":
-                    g = (T[j] - T[idx]) / h if sgn > 0 else (T[idx] - T[j]) / h
-                else:
-                    g = (T_gamma - T[idx]) / (w * h) if sgn > 0 else (T[idx] - T_gamma) / (w * h)
-                grads.append(g)
-            acc += (grads[1] - grads[0]) / (width * h)
-        L[idx] = k * acc
+        L[idx] = operator_at(cfg, c, T, idx, k_l, k_g, T_gamma)
     return L
 
 
-def diffuse(cfg, c, T, dt, k_l, k_g, T_gamma):
+def diffuse(cfg, c, T, dt, k_l, k_g, T_gamma, return_rhs=False):
     """One backward-Euler diffusion step: returns T^{n+1} with
     C_p (T^{n+1} - T) / dt = apply_operator(T^{n+1}) node by node (C_p and k of the
-    node's phase)."""
+    node's phase); with return_rhs, (T^{n+1}, b) with b the right-hand side of the
+    assembled system (T* and the T_Gamma terms)."""
     import scipy.sparse as sp
     import scipy.sparse.linalg as spla
 
@@ -170,5 +176,5 @@ def diffuse(cfg, c, T, dt, k_l, k_g, T_gamma):
         vals.append(diag)
         b[q] = rhs
     A = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
-    x = spla.spsolve(A.tocsc(), b)
-    return x.reshape(c.shape)
+    x = spla.spsolve(A.tocsc(), b).reshape(c.shape)
+    return (x, b.reshape(c.shape)) if return_rhs else x

@@ -15,7 +15,7 @@ ARCH = os.environ.get("PCVOF_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=fast", "-Wall",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["sweep.hip", "kernels.hip", "massflux.hip", "ext.hip", "capi.cpp"]
+SOURCES = ["sweep.hip", "kernels.hip", "massflux.hip", "ext.hip", "diffusion.hip", "capi.cpp"]
 
 
 def build(verbose: bool = False) -> str:

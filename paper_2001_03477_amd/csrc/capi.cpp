@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "../../include/pcvof.h"
+#include "diffusion.h"
 #include "ext.h"
 #include "kernels.h"
 
@@ -763,6 +764,65 @@ int pcvof_extend_velocity(pcvof_handle* h, double rho_g, double rel_tol, int max
     }
     if (info) {
         info->unknowns = nu;
+        info->iterations = iters;
+        info->rel_residual = rel;
+    }
+    return PCVOF_OK;
+}
+
+size_t pcvof_diffusion_workspace_bytes(pcvof_handle* h) {
+    if (!h || !h->ws) return 0;
+    return pcv::diff_layout(h->d).bytes;
+}
+
+int pcvof_diffuse(pcvof_handle* h, double dt, double k_l, double k_g, double rel_tol, int max_iter, void* d_workspace,
+                  size_t workspace_bytes, double* T_out, int mem, pcvof_ext_info* info) {
+    if (int r = check_handle(h)) return r;
+    if (!isfinite(dt) || !(dt > 0.0)) return fail(PCVOF_ERR_ARG, "dt must be positive");
+    if (!isfinite(k_l) || !isfinite(k_g) || !(k_l >= 0.0) || !(k_g >= 0.0))
+        return fail(PCVOF_ERR_ARG, "conductivities must be finite and >= 0");
+    if (!(rel_tol > 0.0 && rel_tol < 1.0)) return fail(PCVOF_ERR_ARG, "rel_tol must lie in (0, 1)");
+    if (max_iter < 1) return fail(PCVOF_ERR_ARG, "max_iter must be at least 1");
+    if (mem != PCVOF_MEM_HOST && mem != PCVOF_MEM_DEVICE) return fail(PCVOF_ERR_ARG, "bad mem");
+    if (h->batch_view) return fail(PCVOF_ERR_STATE, "the diffusion does not run on a batch domain");
+    if (h->in_step) return fail(PCVOF_ERR_STATE, "diffuse inside a step");
+    if (!h->has_vof || !h->has_energy) return fail(PCVOF_ERR_STATE, "fractions and energies must be set");
+    const pcv::DiffLayout L = pcv::diff_layout(h->d);
+    if (!d_workspace || workspace_bytes < L.bytes)
+        return fail(PCVOF_ERR_WORKSPACE, "diffusion workspace of %zu bytes, %zu needed", workspace_bytes, L.bytes);
+    const pcv::DiffIO io = pcv::diff_views(L, d_workspace);
+    const double* c = h->c(h->cur);
+    double* e = h->e(h->cur);
+    HIP_TRY(pcv::launch_diff_start(h->d, c, e, h->g.h, dt, k_l, k_g, io, h->stream));
+    double sc[pcv::kBiScalars];
+    HIP_TRY(hipMemcpyAsync(sc, io.scal, sizeof sc, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    const double bb = sc[pcv::kBiBb];
+    double rr = sc[pcv::kBiRr];
+    if (!isfinite(bb) || !isfinite(rr)) return fail(PCVOF_ERR_NONFINITE, "diffusion: non-finite operator or state");
+    int iters = 0;
+    bool conv = rr <= rel_tol * rel_tol * bb;
+    while (!conv && iters < max_iter) {
+        HIP_TRY(pcv::launch_diff_iteration(h->d, io, h->stream));
+        ++iters;
+        if (iters % 4 == 0 || iters == max_iter) {
+            HIP_TRY(hipMemcpyAsync(sc, io.scal, sizeof sc, hipMemcpyDeviceToHost, h->stream));
+            HIP_TRY(hipStreamSynchronize(h->stream));
+            rr = sc[pcv::kBiRr];
+            if (!isfinite(rr)) break;
+            conv = rr <= rel_tol * rel_tol * bb;
+        }
+    }
+    const double rel = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+    if (!conv)
+        return fail(PCVOF_ERR_STATE, "diffusion: BiCGSTAB reached a relative residual of %.3g, not %.3g, in %d iterations",
+                    rel, rel_tol, iters);
+    double* tdev = (T_out && mem == PCVOF_MEM_DEVICE) ? T_out : nullptr;
+    HIP_TRY(pcv::launch_diff_finish(h->d, c, e, tdev, io, h->stream));
+    if (T_out && mem == PCVOF_MEM_HOST)
+        if (int r = copy_out(h, T_out, io.x, h->d.ncell, mem)) return r;
+    if (info) {
+        info->unknowns = h->d.ncell;
         info->iterations = iters;
         info->rel_residual = rel;
     }

@@ -1,0 +1,396 @@
+// Implicit energy diffusion with the interface temperature imposed (section 3.4.2, eqs.
+// T_diff_disc and mod_branchesT) on gfx950.
+//
+// Each node belongs to the liquid when c >= 1/2, else to the gas, and diffuses with
+// its phase's constant conductivity k_p and volumetric heat capacity C_p. Towards a
+// face neighbour of the same phase the gradient is the difference over h; towards one
+// of the other phase the interface is a boundary at distance theta with T = T_Gamma, the
+// gradient is (T_Gamma - T_i) / theta and the node's control width along that axis
+// becomes (h + theta) / 2 (both sides irregular: (theta_L + theta_R) / 2). Outflow walls
+// are adiabatic; periodic axes wrap. theta: the height of the six-cell column centred on
+// the face when it is bounded by pure cells of the two phases, else the crossing of
+// 1/2 by the linear interpolation of the node phase's indicator between the two nodes;
+// capped to [1e-3 h, h]. Backward Euler:
+//   (1 + sum coef) T_i - sum over same-phase sides of coef T_j
+//       = T*_i + sum over interface sides of coef T_Gamma,
+//   coef = (dt k_p / C_p) / (width h * w h), w = h (node side) or theta (interface side),
+// solved by BiCGSTAB with the diagonal as preconditioner. The system is not symmetric
+// (the widths differ between a node and its neighbour). Every dot product is a
+// fixed-order reduction over the partials of a fixed grid (deterministic).
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "diffusion.h"
+
+namespace pcv {
+
+namespace {
+
+constexpr int kSides = 6;
+constexpr double kEpsTheta = 1e-3;
+
+__device__ __forceinline__ void cell_xyz(const Dom& d, long id, int& x, int& y, int& z) {
+    const long nx = d.n[0], ny = d.n[1];
+    x = (int)(id % nx);
+    const long r = id / nx;
+    y = (int)(r % ny);
+    z = (int)(r / ny);
+}
+
+__device__ __forceinline__ long cell_id(const Dom& d, const int (&q)[3]) {
+    return ((long)q[2] * d.n[1] + q[1]) * d.n[0] + q[0];
+}
+
+// Cell off steps along axis from q: periodic wrap, outflow copy (clamped).
+__device__ __forceinline__ long column_cell(const Dom& d, const int (&q)[3], int axis, int off) {
+    int r[3] = {q[0], q[1], q[2]};
+    const int n = d.n[axis];
+    int v = r[axis] + off;
+    if (v < 0 || v >= n) {
+        if (d.bc[axis] == 0) v = ((v % n) + n) % n;
+        else v = v < 0 ? 0 : n - 1;
+    }
+    r[axis] = v;
+    return cell_id(d, r);
+}
+
+// Face neighbour: index, or -1 beyond an outflow boundary.
+__device__ __forceinline__ long face_neighbour(const Dom& d, const int (&q)[3], int axis, int step) {
+    const int n = d.n[axis];
+    const int v = q[axis] + step;
+    if ((v < 0 || v >= n) && d.bc[axis] != 0) return -1;
+    return column_cell(d, q, axis, step);
+}
+
+// Distance (cell units) from node q (indicator of its phase fi) to the interface
+// towards its neighbour j along axis in direction step.
+__device__ double theta_of(const Dom& d, const double* __restrict__ c, const int (&q)[3], bool liquid, int axis,
+                           int step, long j) {
+    double f[6];
+#pragma unroll
+    for (int o = 0; o < 6; ++o) {
+        const double v = c[column_cell(d, q, axis, (o - 2) * step)];
+        f[o] = liquid ? v : 1.0 - v;
+    }
+    double t;
+    if (f[0] >= 1.0 - d.eps && f[5] <= d.eps) {
+        double sum = 0.0;
+#pragma unroll
+        for (int o = 0; o < 6; ++o) sum += f[o];
+        t = sum - 2.5;
+    } else {
+        const double fi = f[2];
+        const double fj = liquid ? c[j] : 1.0 - c[j];
+        t = (fi - 0.5) / (fi - fj);
+    }
+    return fmin(fmax(t, kEpsTheta), 1.0);
+}
+
+__global__ void __launch_bounds__(kDiffBlock) k_diff_assemble(Dom d, const double* __restrict__ c,
+                                                              const double* __restrict__ e, double h, double dt,
+                                                              double k_l, double k_g, double* __restrict__ diag,
+                                                              double* __restrict__ off, double* __restrict__ b,
+                                                              double* __restrict__ x) {
+    for (long i = (long)blockIdx.x * kDiffBlock + threadIdx.x; i < d.ncell; i += (long)gridDim.x * kDiffBlock) {
+        int q[3];
+        cell_xyz(d, i, q[0], q[1], q[2]);
+        const double ci = c[i];
+        const bool liquid = ci >= 0.5;
+        const double a = dt * (liquid ? k_l : k_g) / (liquid ? d.cp_l : d.cp_g);
+        const double Ts = e[i] / cp_of(d, ci);
+        double dg = 1.0, rhs = Ts;
+        int slot = 0;
+        for (int axis = 0; axis < d.ndim; ++axis) {
+            // kinds: 0 wall, 1 node, 2 interface; w in cell units
+            int kind[2];
+            double w[2];
+            for (int s = 0; s < 2; ++s) {
+                const int step = s == 0 ? -1 : 1;
+                const long j = face_neighbour(d, q, axis, step);
+                if (j < 0) {
+                    kind[s] = 0;
+                    w[s] = 1.0;
+                } else if ((c[j] >= 0.5) == liquid) {
+                    kind[s] = 1;
+                    w[s] = 1.0;
+                } else {
+                    kind[s] = 2;
+                    w[s] = theta_of(d, c, q, liquid, axis, step, j);
+                }
+            }
+            const double width = 0.5 * (w[0] + w[1]);
+            for (int s = 0; s < 2; ++s, ++slot) {
+                double o = 0.0;
+                if (kind[s] != 0) {
+                    const double coef = a / (width * h * w[s] * h);
+                    dg += coef;
+                    if (kind[s] == 1) o = -coef;
+                    else rhs += coef * d.T_gamma;
+                }
+                off[(long)slot * d.ncell + i] = o;
+            }
+        }
+        for (; slot < kSides; ++slot) off[(long)slot * d.ncell + i] = 0.0;
+        diag[i] = dg;
+        b[i] = rhs;
+        x[i] = Ts;  // initial guess: the temperature before the step
+    }
+}
+
+// y_i = diag_i x_i + sum over sides of off_side(i) x_neighbour (zero coefficients for
+// walls and interface sides).
+__device__ __forceinline__ double apply_row(const Dom& d, long i, const double* __restrict__ diag,
+                                            const double* __restrict__ off, const double* __restrict__ x) {
+    int q[3];
+    cell_xyz(d, i, q[0], q[1], q[2]);
+    double y = diag[i] * x[i];
+    int slot = 0;
+    for (int axis = 0; axis < d.ndim; ++axis)
+        for (int step = -1; step <= 1; step += 2, ++slot) {
+            const double o = off[(long)slot * d.ncell + i];
+            if (o != 0.0) y += o * x[column_cell(d, q, axis, step)];
+        }
+    return y;
+}
+
+// Up to three partial sums per block (thread 0 writes part[3 blk + k]).
+__device__ __forceinline__ void block_sum3(double a, double b, double c3, double* part) {
+    __shared__ double s[3][kDiffBlock / 64];
+    const double wa = wave_sum_lane63(a), wb = wave_sum_lane63(b), wc = wave_sum_lane63(c3);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 63) {
+        s[0][w] = wa;
+        s[1][w] = wb;
+        s[2][w] = wc;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double t = s[threadIdx.x][0];
+        for (int k = 1; k < kDiffBlock / 64; ++k) t += s[threadIdx.x][k];
+        part[3 * blockIdx.x + threadIdx.x] = t;
+    }
+}
+
+#define GRID_STRIDE(i, n) for (long i = (long)blockIdx.x * kDiffBlock + threadIdx.x; i < (n); i += (long)gridDim.x * kDiffBlock)
+
+// r = b - A x, rhat = r, p = v = 0; partials (rhat.r, r.r, b.b).
+__global__ void __launch_bounds__(kDiffBlock) k_bi_start(Dom d, const double* __restrict__ diag,
+                                                         const double* __restrict__ off, const double* __restrict__ b,
+                                                         const double* __restrict__ x, double* __restrict__ r,
+                                                         double* __restrict__ rh, double* __restrict__ p,
+                                                         double* __restrict__ v, double* __restrict__ part) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    GRID_STRIDE(i, d.ncell) {
+        const double ri = b[i] - apply_row(d, i, diag, off, x);
+        r[i] = ri;
+        rh[i] = ri;
+        p[i] = 0.0;
+        v[i] = 0.0;
+        s0 += ri * ri;
+        s1 += ri * ri;
+        s2 += b[i] * b[i];
+    }
+    block_sum3(s0, s1, s2, part);
+}
+
+// p = r + beta (p - omega v), ph = p / diag.
+__global__ void __launch_bounds__(kDiffBlock) k_bi_dir(Dom d, const double* __restrict__ scal, const double* __restrict__ diag,
+                                                       const double* __restrict__ r, const double* __restrict__ v,
+                                                       double* __restrict__ p, double* __restrict__ ph) {
+    const double be = scal[kBiBeta], om = scal[kBiOmega];
+    GRID_STRIDE(i, d.ncell) {
+        const double pi = r[i] + be * (p[i] - om * v[i]);
+        p[i] = pi;
+        ph[i] = pi / diag[i];
+    }
+}
+
+// y = A xin; partials (rhat.y, 0, 0) or, with s, (y.s, y.y, 0).
+__global__ void __launch_bounds__(kDiffBlock) k_bi_spmv(Dom d, const double* __restrict__ diag,
+                                                        const double* __restrict__ off, const double* __restrict__ xin,
+                                                        double* __restrict__ y, const double* __restrict__ rh,
+                                                        const double* __restrict__ s, double* __restrict__ part) {
+    double s0 = 0.0, s1 = 0.0;
+    GRID_STRIDE(i, d.ncell) {
+        const double yi = apply_row(d, i, diag, off, xin);
+        y[i] = yi;
+        if (s) {
+            s0 += yi * s[i];
+            s1 += yi * yi;
+        } else {
+            s0 += rh[i] * yi;
+        }
+    }
+    block_sum3(s0, s1, 0.0, part);
+}
+
+// s = r - alpha v, sh = s / diag.
+__global__ void __launch_bounds__(kDiffBlock) k_bi_half(Dom d, const double* __restrict__ scal, const double* __restrict__ diag,
+                                                        const double* __restrict__ r, const double* __restrict__ v,
+                                                        double* __restrict__ s, double* __restrict__ sh) {
+    const double al = scal[kBiAlpha];
+    GRID_STRIDE(i, d.ncell) {
+        const double si = r[i] - al * v[i];
+        s[i] = si;
+        sh[i] = si / diag[i];
+    }
+}
+
+// x += alpha ph + omega sh, r = s - omega t; partials (rhat.r, r.r, 0).
+__global__ void __launch_bounds__(kDiffBlock) k_bi_update(Dom d, const double* __restrict__ scal,
+                                                          const double* __restrict__ ph, const double* __restrict__ sh,
+                                                          const double* __restrict__ s, const double* __restrict__ t,
+                                                          const double* __restrict__ rh, double* __restrict__ x,
+                                                          double* __restrict__ r, double* __restrict__ part) {
+    const double al = scal[kBiAlpha], om = scal[kBiOmega];
+    double s0 = 0.0, s1 = 0.0;
+    GRID_STRIDE(i, d.ncell) {
+        x[i] += al * ph[i] + om * sh[i];
+        const double ri = s[i] - om * t[i];
+        r[i] = ri;
+        s0 += rh[i] * ri;
+        s1 += ri * ri;
+    }
+    block_sum3(s0, s1, 0.0, part);
+}
+
+// Fixed-order sums of the nb triples of partials, then the scalars: mode 0 after the
+// start (rho, rr, bb; alpha = omega = 1), 1 after A ph (alpha = rho / rhat.v), 2 after
+// A sh (omega = t.s / t.t), 3 after the update (beta = (rho' / rho)(alpha / omega), rho,
+// rr). A zero denominator leaves the step at zero (the iteration then stalls and the
+// host reports no convergence).
+__global__ void __launch_bounds__(kDiffBlock) k_bi_reduce(const double* __restrict__ part, int nb, double* __restrict__ scal,
+                                                          int mode) {
+    double a = 0.0, b = 0.0, c3 = 0.0;
+    for (int k = threadIdx.x; k < nb; k += kDiffBlock) {
+        a += part[3 * k];
+        b += part[3 * k + 1];
+        c3 += part[3 * k + 2];
+    }
+    __shared__ double s[3][kDiffBlock / 64];
+    const double wa = wave_sum_lane63(a), wb = wave_sum_lane63(b), wc = wave_sum_lane63(c3);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 63) {
+        s[0][w] = wa;
+        s[1][w] = wb;
+        s[2][w] = wc;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double t0 = s[0][0], t1 = s[1][0], t2 = s[2][0];
+    for (int k = 1; k < kDiffBlock / 64; ++k) {
+        t0 += s[0][k];
+        t1 += s[1][k];
+        t2 += s[2][k];
+    }
+    if (mode == 0) {
+        scal[kBiRho] = t0;
+        scal[kBiRr] = t1;
+        scal[kBiBb] = t2;
+        scal[kBiAlpha] = 1.0;
+        scal[kBiOmega] = 1.0;
+        scal[kBiBeta] = 0.0;
+    } else if (mode == 1) {
+        scal[kBiAlpha] = t0 != 0.0 ? scal[kBiRho] / t0 : 0.0;
+    } else if (mode == 2) {
+        scal[kBiOmega] = t1 != 0.0 ? t0 / t1 : 0.0;
+    } else {
+        const double rho = scal[kBiRho];
+        scal[kBiBeta] = (rho != 0.0 && scal[kBiOmega] != 0.0) ? (t0 / rho) * (scal[kBiAlpha] / scal[kBiOmega]) : 0.0;
+        scal[kBiRho] = t0;
+        scal[kBiRr] = t1;
+    }
+}
+
+// e = C_p(c) T^{n+1}; T_out (if not null) = T^{n+1}.
+__global__ void __launch_bounds__(kDiffBlock) k_diff_finish(Dom d, const double* __restrict__ c,
+                                                            const double* __restrict__ x, double* __restrict__ e,
+                                                            double* __restrict__ T_out) {
+    GRID_STRIDE(i, d.ncell) {
+        e[i] = cp_of(d, c[i]) * x[i];
+        if (T_out) T_out[i] = x[i];
+    }
+}
+
+int grid_for(long n) {
+    const long nb = (n + kDiffBlock - 1) / kDiffBlock;
+    return (int)(nb < kDiffGrid ? nb : kDiffGrid);
+}
+
+}  // namespace
+
+DiffLayout diff_layout(const Dom& d) {
+    DiffLayout L;
+    const size_t n = (size_t)d.ncell;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = (off + bytes + 255) & ~(size_t)255;
+        return at;
+    };
+    L.diag = take(n * sizeof(double));
+    L.off = take(kSides * n * sizeof(double));
+    L.b = take(n * sizeof(double));
+    for (int k = 0; k < 9; ++k) L.vec[k] = take(n * sizeof(double));
+    L.part = take(3 * (size_t)kDiffGrid * sizeof(double));
+    L.scal = take(kBiScalars * sizeof(double));
+    L.bytes = off;
+    return L;
+}
+
+DiffIO diff_views(const DiffLayout& L, void* ws) {
+    char* p = (char*)ws;
+    DiffIO io;
+    io.diag = (double*)(p + L.diag);
+    io.off = (double*)(p + L.off);
+    io.b = (double*)(p + L.b);
+    double* v[9];
+    for (int k = 0; k < 9; ++k) v[k] = (double*)(p + L.vec[k]);
+    io.x = v[0];
+    io.r = v[1];
+    io.rh = v[2];
+    io.p = v[3];
+    io.v = v[4];
+    io.s = v[5];
+    io.t = v[6];
+    io.ph = v[7];
+    io.sh = v[8];
+    io.part = (double*)(p + L.part);
+    io.scal = (double*)(p + L.scal);
+    return io;
+}
+
+hipError_t launch_diff_start(const Dom& d, const double* c, const double* e, double h, double dt, double k_l,
+                             double k_g, const DiffIO& io, hipStream_t s) {
+    const int ng = grid_for(d.ncell);
+    hipLaunchKernelGGL(k_diff_assemble, dim3(ng), dim3(kDiffBlock), 0, s, d, c, e, h, dt, k_l, k_g, io.diag, io.off,
+                       io.b, io.x);
+    hipLaunchKernelGGL(k_bi_start, dim3(ng), dim3(kDiffBlock), 0, s, d, io.diag, io.off, io.b, io.x, io.r, io.rh,
+                       io.p, io.v, io.part);
+    hipLaunchKernelGGL(k_bi_reduce, dim3(1), dim3(kDiffBlock), 0, s, io.part, ng, io.scal, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_diff_iteration(const Dom& d, const DiffIO& io, hipStream_t s) {
+    const int ng = grid_for(d.ncell);
+    hipLaunchKernelGGL(k_bi_dir, dim3(ng), dim3(kDiffBlock), 0, s, d, io.scal, io.diag, io.r, io.v, io.p, io.ph);
+    hipLaunchKernelGGL(k_bi_spmv, dim3(ng), dim3(kDiffBlock), 0, s, d, io.diag, io.off, io.ph, io.v, io.rh,
+                       (const double*)nullptr, io.part);
+    hipLaunchKernelGGL(k_bi_reduce, dim3(1), dim3(kDiffBlock), 0, s, io.part, ng, io.scal, 1);
+    hipLaunchKernelGGL(k_bi_half, dim3(ng), dim3(kDiffBlock), 0, s, d, io.scal, io.diag, io.r, io.v, io.s, io.sh);
+    hipLaunchKernelGGL(k_bi_spmv, dim3(ng), dim3(kDiffBlock), 0, s, d, io.diag, io.off, io.sh, io.t, io.rh,
+                       (const double*)io.s, io.part);
+    hipLaunchKernelGGL(k_bi_reduce, dim3(1), dim3(kDiffBlock), 0, s, io.part, ng, io.scal, 2);
+    hipLaunchKernelGGL(k_bi_update, dim3(ng), dim3(kDiffBlock), 0, s, d, io.scal, io.ph, io.sh, io.s, io.t, io.rh,
+                       io.x, io.r, io.part);
+    hipLaunchKernelGGL(k_bi_reduce, dim3(1), dim3(kDiffBlock), 0, s, io.part, ng, io.scal, 3);
+    return hipGetLastError();
+}
+
+hipError_t launch_diff_finish(const Dom& d, const double* c, double* e, double* T_out, const DiffIO& io,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_diff_finish, dim3(grid_for(d.ncell)), dim3(kDiffBlock), 0, s, d, c, io.x, e, T_out);
+    return hipGetLastError();
+}
+
+}  // namespace pcv

@@ -32,7 +32,8 @@ EXPORTS = (
     "pcvof_get_profile", "pcvof_batch_workspace_bytes", "pcvof_batch_create", "pcvof_batch_destroy",
     "pcvof_batch_domain", "pcvof_batch_advect_step", "pcvof_batch_get_step", "pcvof_batch_set_tiles",
     "pcvof_batch_get_tiles", "pcvof_batch_autotune", "pcvof_compute_mass_flux",
-    "pcvof_extension_workspace_bytes", "pcvof_extend_velocity",
+    "pcvof_extension_workspace_bytes", "pcvof_extend_velocity", "pcvof_diffusion_workspace_bytes",
+    "pcvof_diffuse",
 )
 
 PROF_NAMES = ("sweep_x", "sweep_y", "sweep_z", "phase", "checksum")
@@ -137,10 +138,14 @@ def lib():
         L.pcvof_extension_workspace_bytes.argtypes = [_vp]
         L.pcvof_extend_velocity.argtypes = [_vp, C.c_double, C.c_double, C.c_int, _vp, C.c_size_t, _vp, _vp,
                                             _vp, C.c_int, C.POINTER(ExtInfo)]
+        L.pcvof_diffusion_workspace_bytes.restype = C.c_size_t
+        L.pcvof_diffusion_workspace_bytes.argtypes = [_vp]
+        L.pcvof_diffuse.argtypes = [_vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, _vp, C.c_size_t,
+                                    _vp, C.c_int, C.POINTER(ExtInfo)]
         for nm in EXPORTS:
             f = getattr(L, nm)
             if nm not in ("pcvof_workspace_bytes", "pcvof_last_error", "pcvof_batch_workspace_bytes",
-                          "pcvof_extension_workspace_bytes"):
+                          "pcvof_extension_workspace_bytes", "pcvof_diffusion_workspace_bytes"):
                 f.restype = C.c_int
         _lib = L
     return _lib
@@ -290,6 +295,20 @@ class Domain:
                                           int(nbytes), *[o.data_ptr() if o is not None else None for o in outs],
                                           PCVOF_MEM_DEVICE, C.byref(info)))
         return info.as_dict(), (tuple(outs) if corrections else None)
+
+    def diffuse(self, dt: float, k_l: float, k_g: float, rel_tol: float = 1e-13, max_iter: int = 5000,
+                temperature: bool = False):
+        """Implicit energy diffusion with T_Gamma at the interface (section 3.4.2): the
+        energy becomes C_p(c) T^{n+1}. Returns (info dict, T^{n+1} device tensor or None)."""
+        import torch
+        nbytes = lib().pcvof_diffusion_workspace_bytes(self._h)
+        ws = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=self.device)
+        T = torch.empty(self.spec.shape, dtype=torch.float64, device=self.device) if temperature else None
+        info = ExtInfo()
+        check(lib().pcvof_diffuse(self._h, float(dt), float(k_l), float(k_g), float(rel_tol), int(max_iter),
+                                  ws.data_ptr(), int(nbytes), T.data_ptr() if T is not None else None,
+                                  PCVOF_MEM_DEVICE, C.byref(info)))
+        return info.as_dict(), T
 
     def compute_mass_flux(self, k_l: float, k_g: float, h_fg: float, distances: bool = False):
         """m'' from the PLIC reconstruction of the current state (section 3.2); it becomes

@@ -1,0 +1,177 @@
+"""GPU parity of the implicit energy diffusion with the interface temperature imposed
+(section 3.4.2, eqs. T_diff_disc and mod_branchesT): pcvof_diffuse through the C-ABI
+against the oracle's direct solve on the same seeded fields.
+
+The library iterates BiCGSTAB to a relative residual |r|_2 <= rel_tol |b|_2 (rel_tol =
+1e-13). The backward-Euler matrix A has the diagonal 1 + the sum of the magnitudes of
+its row, so |A^-1|_inf <= 1 and the solution differs from the exact one by at most
+|r|_inf <= |r|_2 = rel_residual |b|_2. The bound used is the larger of the suite's 1e-12
+max |T| and that derived bound (|b|_2 from the oracle's assembly) plus 1e-13 max |T| for
+the direct solve's own rounding: the short steps meet 1e-12 (measured 2e-15), the long
+step (diffusion numbers 2 to 5, interface coefficients up to 1 / theta = 1e3) needs the
+derived one (measured 9e-12 of max |T| against a bound of about 5e-10)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import diffusion as D
+from paper_2001_03477_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def pc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2001_03477_amd import pcvof
+    pcvof.lib()
+    return pcvof
+
+
+def _cp(c, cp_l, cp_g):
+    return cp_l * c + cp_g * (1.0 - c)
+
+
+def _domain(pc, c, T, bc, ndim, cp=(2.5, 0.25), T_gamma=0.5):
+    shape = c.shape
+    spec = pc.DomainSpec(shape=shape, h=1.0 / shape[2], ndim=ndim, bc=bc, cp_l=cp[0], cp_g=cp[1], T_gamma=T_gamma)
+    d = pc.Domain(spec)
+    d.set_vof(c)
+    d.set_energy(_cp(c, *cp) * T)
+    return d
+
+
+def _compare(pc, c, T, bc, ndim, dt, k_l, k_g, cp=(2.5, 0.25), T_gamma=0.5, what=""):
+    d = _domain(pc, c, T, bc, ndim, cp, T_gamma)
+    info, Tg = d.diffuse(dt, k_l, k_g, temperature=True)
+    got = Tg.cpu().numpy()
+    e = d.energy().cpu().numpy()
+    cfg = oracle.Config(shape=c.shape, h=1.0 / c.shape[2], ndim=ndim, bc=bc, cp_l=cp[0], cp_g=cp[1])
+    T0 = (_cp(c, *cp) * T) / _cp(c, *cp)  # the temperature the library starts from, e / C_p(c)
+    ref, b = D.diffuse(cfg, c, T0, dt, k_l, k_g, T_gamma, return_rhs=True)
+    err = float(np.max(np.abs(got - ref)))
+    scale = float(np.max(np.abs(ref)))
+    bound = max(REL * scale, info["rel_residual"] * float(np.linalg.norm(b)) + 1e-13 * scale)
+    print(f"{what}: iterations {info['iterations']}, residual {info['rel_residual']:.2e}, "
+          f"max |T - ref| / max |ref| = {err / scale:.2e} (bound {bound / scale:.1e}), "
+          f"change {np.max(np.abs(ref - T0)):.2e}")
+    assert err <= bound
+    assert np.max(np.abs(e - _cp(c, *cp) * got)) <= 1e-15 * np.max(np.abs(e))
+    return got, ref
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 1), (1, 0, 1)])
+def test_diffusion_parity_drops(pc, bc):
+    wl = W.random_drops_3d(n=16, ndrops=3, seed=171, rmin=1.5, rmax=4.0)
+    T = np.random.default_rng(171).uniform(0.2, 0.9, size=wl.shape)
+    _compare(pc, wl.c, T, bc, 3, 2e-3, 0.07, 0.007, what=f"drops bc {bc}")
+
+
+def test_diffusion_parity_ragged_bubble_and_large_step(pc):
+    n = 19
+    c = W.sphere_fraction((n, n, n), 1.0 / n, [np.array([0.47, 0.53, 0.5])], [0.3], inside_liquid=False)
+    x = (np.arange(n) + 0.5) / n
+    T = 1.0 + 2.0 * np.sqrt((x[None, None, :] - 0.47) ** 2 + (x[None, :, None] - 0.53) ** 2
+                            + (x[:, None, None] - 0.5) ** 2)
+    _compare(pc, c, T, (1, 1, 1), 3, 0.5, 0.07, 0.007, cp=(6.25, 0.25), T_gamma=1.0, what="bubble, long step")
+
+
+def test_diffusion_parity_2d_and_film(pc):
+    wl = W.circle_2d(64)
+    T = np.random.default_rng(172).uniform(0.0, 1.0, size=wl.shape)
+    _compare(pc, wl.c, T, (0, 0, 0), 2, 1e-3, 0.5, 0.05, what="circle2d")
+    film = np.zeros((1, 8, 24))
+    film[:, :, 11] = 0.8  # one cell thick: the interface on both sides of its nodes
+    Tf = np.random.default_rng(173).uniform(0.0, 1.0, size=film.shape)
+    _compare(pc, film, Tf, (1, 0, 0), 2, 5e-3, 0.3, 0.03, what="film")
+
+
+def test_single_phase_is_the_fourier_solution(pc):
+    shape = (12, 16, 20)
+    h = 1.0 / shape[2]
+    T = np.random.default_rng(174).uniform(0.0, 1.0, size=shape)
+    c = np.ones(shape)
+    d = _domain(pc, c, T, (0, 0, 0), 3)
+    k_l, dt = 0.7, 2e-3
+    _, Tg = d.diffuse(dt, k_l, 0.1, temperature=True)
+    a = dt * k_l / 2.5
+    lam = np.zeros(shape)
+    for ax, n in enumerate(shape):
+        kk = np.arange(n).reshape([-1 if i == ax else 1 for i in range(3)])
+        lam = lam + 4.0 / h ** 2 * np.sin(np.pi * kk / n) ** 2
+    want = np.real(np.fft.ifftn(np.fft.fftn(T) / (1.0 + a * lam)))
+    assert np.max(np.abs(Tg.cpu().numpy() - want)) <= 1e-12
+
+
+def test_diffusion_errors_and_no_convergence(pc):
+    import torch
+    wl = W.random_drops_3d(n=12, ndrops=2, seed=175, rmin=2.0, rmax=3.0)
+    spec = pc.DomainSpec(shape=wl.shape, h=wl.h, ndim=3, cp_l=2.5, cp_g=0.25)
+    d = pc.Domain(spec)
+    d.set_vof(wl.c)
+    with pytest.raises(pc.PcvofError) as ex:
+        d.diffuse(1e-3, 0.1, 0.01)  # no energies yet
+    assert ex.value.code == -7
+    d.set_energy(wl.e)
+    for bad in ((0.0, 0.1, 0.01), (1e-3, -0.1, 0.01), (1e-3, 0.1, float("nan"))):
+        with pytest.raises(pc.PcvofError) as ex:
+            d.diffuse(*bad)
+        assert ex.value.code == -1
+    lib = pc.lib()
+    need = lib.pcvof_diffusion_workspace_bytes(d._h)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    assert lib.pcvof_diffuse(d._h, 1e-3, 0.1, 0.01, 1e-12, 100, ws.data_ptr(), need - 1, None, 1, None) == -5
+    e0 = d.energy().cpu().numpy()
+    with pytest.raises(pc.PcvofError) as ex:
+        d.diffuse(10.0, 0.1, 0.01, rel_tol=1e-15, max_iter=1)
+    assert ex.value.code == -7
+    assert np.array_equal(d.energy().cpu().numpy(), e0)  # unchanged without convergence
+
+
+def test_diffusion_full_size_bubble256(pc):
+    """The C3 bubble at 256^3 with the paper's conductivities (0.07 / 0.007) and heat
+    capacities, one step of the workload's dt: the maximum principle everywhere, and the
+    backward-Euler equation T^{n+1} - T* = (dt / C_p) operator(T^{n+1}) at sampled nodes
+    (all nodes next to the interface in a slab, and random ones), the operator
+    evaluated node by node by the oracle, to 1e-8 max |T| (the solver bounds the 2-norm of
+    its residual by 1e-13 |b|_2, about 1e-9 max |T| on any single node at this size)."""
+    wl = W.bubble_3d(256)
+    print("bubble3d_256: fields ready", flush=True)
+    spec = pc.DomainSpec(shape=wl.shape, h=wl.h, ndim=3, bc=wl.bc, cp_l=wl.cp_l, cp_g=wl.cp_g, rho_l=wl.rho_l,
+                         T_gamma=wl.T_gamma, normal=wl.normal)
+    d = pc.Domain(spec)
+    d.set_vof(wl.c)
+    d.set_energy(wl.e)
+    k_l, k_g = 0.07, 0.007
+    info, Tg = d.diffuse(wl.dt, k_l, k_g, temperature=True)
+    T1 = Tg.cpu().numpy()
+    del d
+    print(f"bubble3d_256: {info}", flush=True)
+    T0 = wl.e / _cp(wl.c, wl.cp_l, wl.cp_g)
+    lo, hi = min(T0.min(), wl.T_gamma), max(T0.max(), wl.T_gamma)
+    assert T1.min() >= lo - 1e-12 and T1.max() <= hi + 1e-12
+    cfg = oracle.Config(shape=wl.shape, h=wl.h, ndim=3, bc=wl.bc, cp_l=wl.cp_l, cp_g=wl.cp_g)
+    liquid = wl.c >= 0.5
+    near = np.zeros(wl.shape, dtype=bool)
+    for ax in range(3):
+        near |= liquid != np.roll(liquid, 1, axis=ax)
+        near |= liquid != np.roll(liquid, -1, axis=ax)
+    zc = wl.shape[0] // 2
+    sample = [tuple(i) for i in np.argwhere(near[zc - 2:zc + 2]) + np.array([zc - 2, 0, 0])]
+    rng = np.random.default_rng(176)
+    sample += [tuple(int(v) for v in rng.integers(0, 256, size=3)) for _ in range(300)]
+    Tmax = float(np.max(np.abs(T0)))
+    worst, moved = 0.0, 0.0
+    for idx in sample:
+        C = wl.cp_l if liquid[idx] else wl.cp_g
+        change = (wl.dt / C) * D.operator_at(cfg, wl.c, T1, idx, k_l, k_g, wl.T_gamma)
+        worst = max(worst, abs(T1[idx] - T0[idx] - change))
+        moved = max(moved, abs(change))
+    print(f"bubble3d_256: {len(sample)} sampled nodes, largest change {moved:.3e}, "
+          f"worst residual {worst / Tmax:.2e} of max |T|", flush=True)
+    assert moved > 1e-3 * Tmax
+    assert worst <= 1e-8 * Tmax
