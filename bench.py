@@ -403,6 +403,30 @@ def extension_timing(pcvof, torch, wl, rho_g, calls=5):
     return {"ms": float(np.median(times)), "rho_g": rho_g, **info, "rel_tol": 1e-13}
 
 
+def diffusion_timing(pcvof, torch, wl, k_l, k_g, calls=5):
+    """The implicit energy diffusion (section 3.4.2) on the workload's state: wall time
+    per pcvof_diffuse call (assembly with the height-function distances, BiCGSTAB with
+    its host convergence checks, the energy written back), median of `calls` calls after
+    one untimed call, with the iterations and final relative residual. Not part of the
+    advection step that `value` times."""
+    spec = pcvof.DomainSpec(shape=wl.shape, h=wl.h, ndim=wl.ndim, bc=wl.bc, cp_l=wl.cp_l, cp_g=wl.cp_g,
+                            rho_l=wl.rho_l, T_gamma=wl.T_gamma, normal=wl.normal)
+    d = pcvof.Domain(spec)
+    d.set_vof(wl.c)
+    d.set_energy(wl.e)
+    info, _ = d.diffuse(wl.dt, k_l, k_g)
+    times = []
+    for _ in range(calls):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info, _ = d.diffuse(wl.dt, k_l, k_g)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    del d
+    torch.cuda.empty_cache()
+    return {"ms": float(np.median(times)), "k_l": k_l, "k_g": k_g, "dt": wl.dt, **info, "rel_tol": 1e-13}
+
+
 def cpu_baseline(wl, budget_s=15.0, max_side=128):
     """The oracle on the host: whole steps of the workload until the budget is used (at
     least one step). Domains larger than max_side per axis are sampled: the oracle
@@ -527,6 +551,8 @@ def main():
     if args.workload == "bubble256":
         # vapour density of the paper's superheated-bubble case (its liquid one is rho_l)
         out["extension"] = extension_timing(pcvof, torch, wl, 0.25)
+        # conductivities of the same case
+        out["diffusion"] = diffusion_timing(pcvof, torch, wl, 0.07, 0.007)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)
