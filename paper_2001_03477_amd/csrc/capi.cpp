@@ -790,7 +790,7 @@ int pcvof_diffuse(pcvof_handle* h, double dt, double k_l, double k_g, double rel
     const pcv::DiffLayout L = pcv::diff_layout(h->d);
     if (!d_workspace || workspace_bytes < L.bytes)
         return fail(PCVOF_ERR_WORKSPACE, "diffusion workspace of %zu bytes, %zu needed", workspace_bytes, L.bytes);
-    const pcv::DiffIO io = pcv::diff_views(L, d_workspace);
+    pcv::DiffIO io = pcv::diff_views(L, d_workspace);
     const double* c = h->c(h->cur);
     double* e = h->e(h->cur);
     HIP_TRY(pcv::launch_diff_start(h->d, c, e, h->g.h, dt, k_l, k_g, io, h->stream));

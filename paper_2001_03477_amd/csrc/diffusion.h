@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stddef.h>
+#include <stdint.h>
 
 #include "kernels.h"
 
@@ -13,18 +14,34 @@ constexpr int kDiffBlock = 256;
 constexpr int kDiffGrid = 2048;  // blocks of the grid-stride kernels (and partials per reduction)
 enum { kBiRho = 0, kBiAlpha = 1, kBiOmega = 2, kBiBeta = 3, kBiRr = 4, kBiBb = 5, kBiScalars = 8 };
 
+// Diagonal and neighbour coefficient of a phase's regular row (a node of that phase
+// with a node of the same phase on every side); index 0 gas, 1 liquid.
+struct RowConst {
+    double c[2], dg[2];
+};
+// The operator: per cell a kind byte (bit 0 liquid, bit 1 stored row), the stored rows'
+// diagonal and coefficients, the regular rows' constants.
+struct Rows {
+    const uint8_t* kind;
+    const double* diag;
+    const double* off;
+    RowConst rc;
+};
+
 // Views into the caller's diffusion workspace (diff_layout gives the offsets).
 struct DiffIO {
-    double* diag;   // per cell: diagonal of the backward-Euler operator
+    uint8_t* kind;  // per cell: bit 0 liquid, bit 1 row stored (a wall or interface side)
+    double* diag;   // per cell: diagonal of the backward-Euler operator (stored rows)
     double* off;    // 6 slots x cells (slot-major): coefficient of the face neighbour (0: wall or interface)
     double* b;      // per cell: right-hand side (T* and the T_Gamma terms)
     double *x, *r, *rh, *p, *v, *s, *t, *ph, *sh;  // BiCGSTAB vectors (x: T^{n+1})
     double* part;   // 3 partial sums per block of the fixed grid
     double* scal;   // kBi* scalars
+    Rows rows;      // the operator as the kernels read it (rc set by launch_diff_start)
 };
 
 struct DiffLayout {
-    size_t diag, off, b, vec[9], part, scal, bytes;
+    size_t kind, diag, off, b, vec[9], part, scal, bytes;
 };
 DiffLayout diff_layout(const Dom& d);
 DiffIO diff_views(const DiffLayout& L, void* ws);
@@ -32,7 +49,7 @@ DiffIO diff_views(const DiffLayout& L, void* ws);
 // Operator, right-hand side and x = T* from the state (c, e); BiCGSTAB start:
 // scal[kBiRr] = |r|^2, scal[kBiBb] = |b|^2.
 hipError_t launch_diff_start(const Dom& d, const double* c, const double* e, double h, double dt, double k_l,
-                             double k_g, const DiffIO& io, hipStream_t s);
+                             double k_g, DiffIO& io, hipStream_t s);
 // One BiCGSTAB iteration (scal[kBiRr] updated).
 hipError_t launch_diff_iteration(const Dom& d, const DiffIO& io, hipStream_t s);
 // e = C_p(c) T^{n+1}; T_out (may be null) = T^{n+1}.

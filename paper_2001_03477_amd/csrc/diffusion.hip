@@ -29,13 +29,34 @@ namespace {
 constexpr int kSides = 6;
 constexpr double kEpsTheta = 1e-3;
 
-__device__ __forceinline__ void cell_xyz(const Dom& d, long id, int& x, int& y, int& z) {
+// Coordinates of cell base + t: the block-uniform base is divided once, the lane's
+// offset t (< the block size) carried forward without divisions.
+__device__ __forceinline__ void cell_at(const Dom& d, long base, int t, int (&q)[3]) {
     const long nx = d.n[0], ny = d.n[1];
-    x = (int)(id % nx);
-    const long r = id / nx;
-    y = (int)(r % ny);
-    z = (int)(r / ny);
+    int x = (int)(base % nx);
+    const long r = base / nx;
+    int y = (int)(r % ny);
+    int z = (int)(r / ny);
+    x += t;
+    while (x >= d.n[0]) {
+        x -= d.n[0];
+        if (++y == d.n[1]) {
+            y = 0;
+            ++z;
+        }
+    }
+    q[0] = x;
+    q[1] = y;
+    q[2] = z;
 }
+
+// Grid-stride loop over the cells in runs of kDiffBlock (the same cells per block in
+// every launch, so the block partials are deterministic): i is the lane's cell, q its
+// coordinates.
+#define FOR_CELLS(d, i, q)                                                                          \
+    for (long base_ = (long)blockIdx.x * kDiffBlock; base_ < (d).ncell; base_ += (long)gridDim.x * kDiffBlock) \
+        if (const long i = base_ + threadIdx.x; i < (d).ncell)                                         \
+            if (int q[3]; (cell_at((d), base_, (int)threadIdx.x, q), true))
 
 __device__ __forceinline__ long cell_id(const Dom& d, const int (&q)[3]) {
     return ((long)q[2] * d.n[1] + q[1]) * d.n[0] + q[0];
@@ -88,68 +109,84 @@ __device__ double theta_of(const Dom& d, const double* __restrict__ c, const int
 
 __global__ void __launch_bounds__(kDiffBlock) k_diff_assemble(Dom d, const double* __restrict__ c,
                                                               const double* __restrict__ e, double h, double dt,
-                                                              double k_l, double k_g, double* __restrict__ diag,
-                                                              double* __restrict__ off, double* __restrict__ b,
-                                                              double* __restrict__ x) {
-    for (long i = (long)blockIdx.x * kDiffBlock + threadIdx.x; i < d.ncell; i += (long)gridDim.x * kDiffBlock) {
-        int q[3];
-        cell_xyz(d, i, q[0], q[1], q[2]);
+                                                              double k_l, double k_g, uint8_t* __restrict__ kindo,
+                                                              double* __restrict__ diag, double* __restrict__ off,
+                                                              double* __restrict__ b, double* __restrict__ x) {
+    FOR_CELLS(d, i, q) {
         const double ci = c[i];
         const bool liquid = ci >= 0.5;
         const double a = dt * (liquid ? k_l : k_g) / (liquid ? d.cp_l : d.cp_g);
         const double Ts = e[i] / cp_of(d, ci);
         double dg = 1.0, rhs = Ts;
+        bool irregular = false;
+        double ok[kSides];
         int slot = 0;
         for (int axis = 0; axis < d.ndim; ++axis) {
             // kinds: 0 wall, 1 node, 2 interface; w in cell units
-            int kind[2];
+            int sk[2];
             double w[2];
             for (int s = 0; s < 2; ++s) {
                 const int step = s == 0 ? -1 : 1;
                 const long j = face_neighbour(d, q, axis, step);
                 if (j < 0) {
-                    kind[s] = 0;
+                    sk[s] = 0;
                     w[s] = 1.0;
                 } else if ((c[j] >= 0.5) == liquid) {
-                    kind[s] = 1;
+                    sk[s] = 1;
                     w[s] = 1.0;
                 } else {
-                    kind[s] = 2;
+                    sk[s] = 2;
                     w[s] = theta_of(d, c, q, liquid, axis, step, j);
                 }
             }
             const double width = 0.5 * (w[0] + w[1]);
             for (int s = 0; s < 2; ++s, ++slot) {
                 double o = 0.0;
-                if (kind[s] != 0) {
+                if (sk[s] != 0) {
                     const double coef = a / (width * h * w[s] * h);
                     dg += coef;
-                    if (kind[s] == 1) o = -coef;
+                    if (sk[s] == 1) o = -coef;
                     else rhs += coef * d.T_gamma;
                 }
-                off[(long)slot * d.ncell + i] = o;
+                if (sk[s] != 1) irregular = true;
+                ok[slot] = o;
             }
         }
-        for (; slot < kSides; ++slot) off[(long)slot * d.ncell + i] = 0.0;
-        diag[i] = dg;
+        // a row with a same-phase node on every side is its phase's regular row
+        // (RowConst); the others are stored
+        kindo[i] = (uint8_t)((liquid ? 1 : 0) | (irregular ? 2 : 0));
+        if (irregular) {
+            for (int q2 = 0; q2 < kSides; ++q2) off[(long)q2 * d.ncell + i] = q2 < slot ? ok[q2] : 0.0;
+            diag[i] = dg;
+        }
         b[i] = rhs;
         x[i] = Ts;  // initial guess: the temperature before the step
     }
 }
 
 // y_i = diag_i x_i + sum over sides of off_side(i) x_neighbour (zero coefficients for
-// walls and interface sides).
-__device__ __forceinline__ double apply_row(const Dom& d, long i, const double* __restrict__ diag,
-                                            const double* __restrict__ off, const double* __restrict__ x) {
-    int q[3];
-    cell_xyz(d, i, q[0], q[1], q[2]);
-    double y = diag[i] * x[i];
+// walls and interface sides). Regular rows take their phase's diagonal and coefficient
+// (the same values the assembly computes), the others the stored ones.
+__device__ __forceinline__ double row_diag(const Rows& m, long i, uint8_t k) {
+    return (k & 2) ? m.diag[i] : m.rc.dg[k & 1];
+}
+
+__device__ __forceinline__ double apply_row(const Dom& d, long i, const int (&q)[3], const Rows& m,
+                                            const double* __restrict__ x) {
+    const uint8_t k = m.kind[i];
+    double y = row_diag(m, i, k) * x[i];
     int slot = 0;
-    for (int axis = 0; axis < d.ndim; ++axis)
-        for (int step = -1; step <= 1; step += 2, ++slot) {
-            const double o = off[(long)slot * d.ncell + i];
-            if (o != 0.0) y += o * x[column_cell(d, q, axis, step)];
-        }
+    if (k & 2) {
+        for (int axis = 0; axis < d.ndim; ++axis)
+            for (int step = -1; step <= 1; step += 2, ++slot) {
+                const double o = m.off[(long)slot * d.ncell + i];
+                if (o != 0.0) y += o * x[column_cell(d, q, axis, step)];
+            }
+    } else {
+        const double o = -m.rc.c[k & 1];
+        for (int axis = 0; axis < d.ndim; ++axis)
+            for (int step = -1; step <= 1; step += 2) y += o * x[column_cell(d, q, axis, step)];
+    }
     return y;
 }
 
@@ -174,14 +211,13 @@ __device__ __forceinline__ void block_sum3(double a, double b, double c3, double
 #define GRID_STRIDE(i, n) for (long i = (long)blockIdx.x * kDiffBlock + threadIdx.x; i < (n); i += (long)gridDim.x * kDiffBlock)
 
 // r = b - A x, rhat = r, p = v = 0; partials (rhat.r, r.r, b.b).
-__global__ void __launch_bounds__(kDiffBlock) k_bi_start(Dom d, const double* __restrict__ diag,
-                                                         const double* __restrict__ off, const double* __restrict__ b,
+__global__ void __launch_bounds__(kDiffBlock) k_bi_start(Dom d, Rows m, const double* __restrict__ b,
                                                          const double* __restrict__ x, double* __restrict__ r,
                                                          double* __restrict__ rh, double* __restrict__ p,
                                                          double* __restrict__ v, double* __restrict__ part) {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    GRID_STRIDE(i, d.ncell) {
-        const double ri = b[i] - apply_row(d, i, diag, off, x);
+    FOR_CELLS(d, i, q) {
+        const double ri = b[i] - apply_row(d, i, q, m, x);
         r[i] = ri;
         rh[i] = ri;
         p[i] = 0.0;
@@ -194,25 +230,24 @@ __global__ void __launch_bounds__(kDiffBlock) k_bi_start(Dom d, const double* __
 }
 
 // p = r + beta (p - omega v), ph = p / diag.
-__global__ void __launch_bounds__(kDiffBlock) k_bi_dir(Dom d, const double* __restrict__ scal, const double* __restrict__ diag,
+__global__ void __launch_bounds__(kDiffBlock) k_bi_dir(Dom d, const double* __restrict__ scal, Rows m,
                                                        const double* __restrict__ r, const double* __restrict__ v,
                                                        double* __restrict__ p, double* __restrict__ ph) {
     const double be = scal[kBiBeta], om = scal[kBiOmega];
     GRID_STRIDE(i, d.ncell) {
         const double pi = r[i] + be * (p[i] - om * v[i]);
         p[i] = pi;
-        ph[i] = pi / diag[i];
+        ph[i] = pi / row_diag(m, i, m.kind[i]);
     }
 }
 
 // y = A xin; partials (rhat.y, 0, 0) or, with s, (y.s, y.y, 0).
-__global__ void __launch_bounds__(kDiffBlock) k_bi_spmv(Dom d, const double* __restrict__ diag,
-                                                        const double* __restrict__ off, const double* __restrict__ xin,
+__global__ void __launch_bounds__(kDiffBlock) k_bi_spmv(Dom d, Rows m, const double* __restrict__ xin,
                                                         double* __restrict__ y, const double* __restrict__ rh,
                                                         const double* __restrict__ s, double* __restrict__ part) {
     double s0 = 0.0, s1 = 0.0;
-    GRID_STRIDE(i, d.ncell) {
-        const double yi = apply_row(d, i, diag, off, xin);
+    FOR_CELLS(d, i, q) {
+        const double yi = apply_row(d, i, q, m, xin);
         y[i] = yi;
         if (s) {
             s0 += yi * s[i];
@@ -225,14 +260,14 @@ __global__ void __launch_bounds__(kDiffBlock) k_bi_spmv(Dom d, const double* __r
 }
 
 // s = r - alpha v, sh = s / diag.
-__global__ void __launch_bounds__(kDiffBlock) k_bi_half(Dom d, const double* __restrict__ scal, const double* __restrict__ diag,
+__global__ void __launch_bounds__(kDiffBlock) k_bi_half(Dom d, const double* __restrict__ scal, Rows m,
                                                         const double* __restrict__ r, const double* __restrict__ v,
                                                         double* __restrict__ s, double* __restrict__ sh) {
     const double al = scal[kBiAlpha];
     GRID_STRIDE(i, d.ncell) {
         const double si = r[i] - al * v[i];
         s[i] = si;
-        sh[i] = si / diag[i];
+        sh[i] = si / row_diag(m, i, m.kind[i]);
     }
 }
 
@@ -328,6 +363,7 @@ DiffLayout diff_layout(const Dom& d) {
         off = (off + bytes + 255) & ~(size_t)255;
         return at;
     };
+    L.kind = take(n);
     L.diag = take(n * sizeof(double));
     L.off = take(kSides * n * sizeof(double));
     L.b = take(n * sizeof(double));
@@ -341,6 +377,7 @@ DiffLayout diff_layout(const Dom& d) {
 DiffIO diff_views(const DiffLayout& L, void* ws) {
     char* p = (char*)ws;
     DiffIO io;
+    io.kind = (uint8_t*)(p + L.kind);
     io.diag = (double*)(p + L.diag);
     io.off = (double*)(p + L.off);
     io.b = (double*)(p + L.b);
@@ -357,28 +394,48 @@ DiffIO diff_views(const DiffLayout& L, void* ws) {
     io.sh = v[8];
     io.part = (double*)(p + L.part);
     io.scal = (double*)(p + L.scal);
+    io.rows.kind = io.kind;
+    io.rows.diag = io.diag;
+    io.rows.off = io.off;
     return io;
 }
 
+// The regular row of each phase, computed as the assembly computes it (width and
+// distances of one cell on every side).
+RowConst row_const(const Dom& d, double h, double dt, double k_l, double k_g) {
+    RowConst rc;
+    for (int p = 0; p < 2; ++p) {
+        const double a = dt * (p ? k_l : k_g) / (p ? d.cp_l : d.cp_g);
+        const double width = 0.5 * (1.0 + 1.0);
+        const double coef = a / (width * h * 1.0 * h);
+        double dg = 1.0;
+        for (int side = 0; side < 2 * d.ndim; ++side) dg += coef;
+        rc.c[p] = coef;
+        rc.dg[p] = dg;
+    }
+    return rc;
+}
+
 hipError_t launch_diff_start(const Dom& d, const double* c, const double* e, double h, double dt, double k_l,
-                             double k_g, const DiffIO& io, hipStream_t s) {
+                             double k_g, DiffIO& io, hipStream_t s) {
     const int ng = grid_for(d.ncell);
-    hipLaunchKernelGGL(k_diff_assemble, dim3(ng), dim3(kDiffBlock), 0, s, d, c, e, h, dt, k_l, k_g, io.diag, io.off,
-                       io.b, io.x);
-    hipLaunchKernelGGL(k_bi_start, dim3(ng), dim3(kDiffBlock), 0, s, d, io.diag, io.off, io.b, io.x, io.r, io.rh,
-                       io.p, io.v, io.part);
+    io.rows.rc = row_const(d, h, dt, k_l, k_g);
+    hipLaunchKernelGGL(k_diff_assemble, dim3(ng), dim3(kDiffBlock), 0, s, d, c, e, h, dt, k_l, k_g, io.kind, io.diag,
+                       io.off, io.b, io.x);
+    hipLaunchKernelGGL(k_bi_start, dim3(ng), dim3(kDiffBlock), 0, s, d, io.rows, io.b, io.x, io.r, io.rh, io.p, io.v,
+                       io.part);
     hipLaunchKernelGGL(k_bi_reduce, dim3(1), dim3(kDiffBlock), 0, s, io.part, ng, io.scal, 0);
     return hipGetLastError();
 }
 
 hipError_t launch_diff_iteration(const Dom& d, const DiffIO& io, hipStream_t s) {
     const int ng = grid_for(d.ncell);
-    hipLaunchKernelGGL(k_bi_dir, dim3(ng), dim3(kDiffBlock), 0, s, d, io.scal, io.diag, io.r, io.v, io.p, io.ph);
-    hipLaunchKernelGGL(k_bi_spmv, dim3(ng), dim3(kDiffBlock), 0, s, d, io.diag, io.off, io.ph, io.v, io.rh,
+    hipLaunchKernelGGL(k_bi_dir, dim3(ng), dim3(kDiffBlock), 0, s, d, io.scal, io.rows, io.r, io.v, io.p, io.ph);
+    hipLaunchKernelGGL(k_bi_spmv, dim3(ng), dim3(kDiffBlock), 0, s, d, io.rows, io.ph, io.v, io.rh,
                        (const double*)nullptr, io.part);
     hipLaunchKernelGGL(k_bi_reduce, dim3(1), dim3(kDiffBlock), 0, s, io.part, ng, io.scal, 1);
-    hipLaunchKernelGGL(k_bi_half, dim3(ng), dim3(kDiffBlock), 0, s, d, io.scal, io.diag, io.r, io.v, io.s, io.sh);
-    hipLaunchKernelGGL(k_bi_spmv, dim3(ng), dim3(kDiffBlock), 0, s, d, io.diag, io.off, io.sh, io.t, io.rh,
+    hipLaunchKernelGGL(k_bi_half, dim3(ng), dim3(kDiffBlock), 0, s, d, io.scal, io.rows, io.r, io.v, io.s, io.sh);
+    hipLaunchKernelGGL(k_bi_spmv, dim3(ng), dim3(kDiffBlock), 0, s, d, io.rows, io.sh, io.t, io.rh,
                        (const double*)io.s, io.part);
     hipLaunchKernelGGL(k_bi_reduce, dim3(1), dim3(kDiffBlock), 0, s, io.part, ng, io.scal, 2);
     hipLaunchKernelGGL(k_bi_update, dim3(ng), dim3(kDiffBlock), 0, s, d, io.scal, io.ph, io.sh, io.s, io.t, io.rh,
