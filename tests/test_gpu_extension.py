@@ -325,3 +325,18 @@ def test_extension_full_size_bubble256(pc):
     assert np.all(div[lab == X.LIQUID] == 0.0) and np.all(div[lab == X.FAR] == 0.0)
     total = float(np.sum(src[sub]))
     assert float(np.sum(div[lab == 3])) == pytest.approx(total, rel=1e-10)
+
+
+def test_extension_without_interface(pc):
+    """No mixed cell (a liquid slab with faces on cell faces, and an all-gas box): the
+    sub-domain holds only gas layers next to no interface or nothing at all; no
+    correction anywhere and the velocity unchanged."""
+    shape = (6, 8, 10)
+    for c in (np.ones(shape), np.zeros(shape), np.concatenate([np.ones((6, 8, 5)), np.zeros((6, 8, 5))], axis=2)):
+        uvw = _faces(shape, 3, np.random.default_rng(7), 0.2)
+        for a in range(3):
+            _periodic_faces(uvw[a], 2 - a)
+        d, info, du = _run(pc, c, uvw, np.full(shape, 0.5), (0, 0, 0), 3, 2.5, 0.25)
+        assert info["unknowns"] == 0
+        for t in du:
+            assert np.all(t == 0.0)

@@ -166,3 +166,18 @@ def test_le_volume_drift_against_the_conservative_split(pc):
         drift[split] = abs(st["vol"] - v0) / v0
     assert drift["wy"] <= 1e-13
     assert drift["le"] > 1e-7
+
+
+def test_le_full_size_leveque128(pc):
+    """The configuration of the benchmark's split ablation: the 128^3 LeVeque field, one
+    full Lagrangian-explicit step, every cell compared with the oracle, with the oracle's
+    dilatation term and total volume."""
+    wl = W.leveque_3d(128)
+    spec, cfg = _specs(pc, wl)
+    d = _domain(pc, spec, wl.c, wl.e, wl.u, wl.v, wl.w)
+    st = d.step(wl.dt, wl.u_scale(0), stats=True)
+    c, e, st_ref = oracle.step(cfg, wl.c, wl.e, wl.u, wl.v, wl.w, None, wl.dt, wl.u_scale(0), 0)
+    _assert_close(d.vof().cpu().numpy(), c, 1.0, "c")
+    _assert_close(d.energy().cpu().numpy(), e, 0.0, "e")
+    assert st["vol_src"] == pytest.approx(st_ref["vol_src"], abs=1e-13)
+    assert st["vol"] == pytest.approx(st_ref["vol"], rel=1e-13)
