@@ -27,6 +27,7 @@ namespace pcv {
 namespace {
 
 constexpr int kSides = 6;
+constexpr int kMarch = 16;  // cells per column of a product block along z
 constexpr double kEpsTheta = 1e-3;
 
 // Coordinates of cell base + t: the block-uniform base is divided once, the lane's
@@ -171,63 +172,104 @@ __device__ __forceinline__ double row_diag(const Rows& m, long i, uint8_t k) {
     return (k & 2) ? m.diag[i] : m.rc.dg[k & 1];
 }
 
-__device__ __forceinline__ double apply_row(const Dom& d, long i, const int (&q)[3], const Rows& m,
-                                            const double* __restrict__ x) {
-    const uint8_t k = m.kind[i];
-    double y = row_diag(m, i, k) * x[i];
-    int slot = 0;
-    if (k & 2) {
-        for (int axis = 0; axis < d.ndim; ++axis)
-            for (int step = -1; step <= 1; step += 2, ++slot) {
-                const double o = m.off[(long)slot * d.ncell + i];
-                if (o != 0.0) y += o * x[column_cell(d, q, axis, step)];
-            }
-    } else {
-        const double o = -m.rc.c[k & 1];
-        for (int axis = 0; axis < d.ndim; ++axis)
-            for (int step = -1; step <= 1; step += 2) y += o * x[column_cell(d, q, axis, step)];
-    }
-    return y;
-}
-
-// Up to three partial sums per block (thread 0 writes part[3 blk + k]).
-__device__ __forceinline__ void block_sum3(double a, double b, double c3, double* part) {
+// Up to three partial sums per block of kDiffBlock threads (tid the linear thread
+// index; thread 0..2 writes part[3 blk + k]).
+__device__ __forceinline__ void block_sum3(double a, double b, double c3, double* part, int tid, long blk) {
     __shared__ double s[3][kDiffBlock / 64];
     const double wa = wave_sum_lane63(a), wb = wave_sum_lane63(b), wc = wave_sum_lane63(c3);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = tid & 63, w = tid >> 6;
     if (lane == 63) {
         s[0][w] = wa;
         s[1][w] = wb;
         s[2][w] = wc;
     }
     __syncthreads();
-    if (threadIdx.x < 3) {
-        double t = s[threadIdx.x][0];
-        for (int k = 1; k < kDiffBlock / 64; ++k) t += s[threadIdx.x][k];
-        part[3 * blockIdx.x + threadIdx.x] = t;
+    if (tid < 3) {
+        double t = s[tid][0];
+        for (int k = 1; k < kDiffBlock / 64; ++k) t += s[tid][k];
+        part[3 * blk + tid] = t;
     }
+}
+__device__ __forceinline__ void block_sum3(double a, double b, double c3, double* part) {
+    block_sum3(a, b, c3, part, (int)threadIdx.x, (long)blockIdx.x);
+}
+
+// Neighbour position along an axis of n cells: periodic wrap, outflow clamp (the
+// clamped value is never used: wall sides have no coefficient).
+__device__ __forceinline__ int nb_pos(int v, int n, int bc) {
+    if (v >= 0 && v < n) return v;
+    if (bc == 0) return v < 0 ? v + n : v - n;
+    return v < 0 ? 0 : n - 1;
+}
+
+// The products over columns: a thread owns the column (x, y) of a block of 64 x 4
+// columns and marches over kMarch cells along z, keeping x at z - 1, z, z + 1 in
+// registers; the x and y neighbours are rows of the same block (coalesced, in cache).
+// Per row the diagonal first, then the sides in the order x-, x+, y-, y+, z-, z+. MODE 0: start
+// (r = b - A x, rhat = r, p = v = 0; partials rhat.r, r.r, b.b); 1: y = A x with the
+// partial rhat.y; 2: y = A x with the partials y.s, y.y.
+template <int MODE>
+__global__ void __launch_bounds__(kDiffBlock) k_bi_march(Dom d, Rows m, const double* __restrict__ xin,
+                                                         double* __restrict__ y, const double* __restrict__ rh,
+                                                         const double* __restrict__ sv, const double* __restrict__ b,
+                                                         double* __restrict__ rhw, double* __restrict__ p,
+                                                         double* __restrict__ v, double* __restrict__ part) {
+    const int nx = d.n[0], ny = d.n[1], nz = d.n[2];
+    const int x = blockIdx.x * 64 + threadIdx.x, yy = blockIdx.y * 4 + threadIdx.y;
+    const int z0 = blockIdx.z * kMarch, z1 = z0 + kMarch < nz ? z0 + kMarch : nz;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    if (x < nx && yy < ny) {
+        const long plane = (long)nx * ny;
+        const long col = (long)yy * nx + x;
+        const long xm = (long)yy * nx + nb_pos(x - 1, nx, d.bc[0]), xp = (long)yy * nx + nb_pos(x + 1, nx, d.bc[0]);
+        const long ym = (long)nb_pos(yy - 1, ny, d.bc[1]) * nx + x, yp = (long)nb_pos(yy + 1, ny, d.bc[1]) * nx + x;
+        const bool three = d.ndim == 3;
+        double xprev = three ? xin[nb_pos(z0 - 1, nz, d.bc[2]) * plane + col] : 0.0;
+        double xcur = xin[z0 * plane + col];
+        for (int z = z0; z < z1; ++z) {
+            const long zb = z * plane;
+            const long i = zb + col;
+            const double xnext = three ? xin[nb_pos(z + 1, nz, d.bc[2]) * plane + col] : 0.0;
+            const double nbv[6] = {xin[zb + xm], xin[zb + xp], xin[zb + ym], xin[zb + yp], xprev, xnext};
+            const uint8_t k = m.kind[i];
+            double yi = row_diag(m, i, k) * xcur;
+            const int sides = 2 * d.ndim;
+            if (k & 2) {
+                for (int slot = 0; slot < sides; ++slot) {
+                    const double o = m.off[(long)slot * d.ncell + i];
+                    if (o != 0.0) yi += o * nbv[slot];
+                }
+            } else {
+                const double o = -m.rc.c[k & 1];
+                for (int slot = 0; slot < sides; ++slot) yi += o * nbv[slot];
+            }
+            if (MODE == 0) {
+                const double ri = b[i] - yi;
+                y[i] = ri;  // r
+                rhw[i] = ri;
+                p[i] = 0.0;
+                v[i] = 0.0;
+                s0 += ri * ri;
+                s1 += ri * ri;
+                s2 += b[i] * b[i];
+            } else {
+                y[i] = yi;
+                if (MODE == 2) {
+                    s0 += yi * sv[i];
+                    s1 += yi * yi;
+                } else {
+                    s0 += rh[i] * yi;
+                }
+            }
+            xprev = xcur;
+            xcur = xnext;
+        }
+    }
+    const long blk = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    block_sum3(s0, s1, s2, part, (int)(threadIdx.y * 64 + threadIdx.x), blk);
 }
 
 #define GRID_STRIDE(i, n) for (long i = (long)blockIdx.x * kDiffBlock + threadIdx.x; i < (n); i += (long)gridDim.x * kDiffBlock)
-
-// r = b - A x, rhat = r, p = v = 0; partials (rhat.r, r.r, b.b).
-__global__ void __launch_bounds__(kDiffBlock) k_bi_start(Dom d, Rows m, const double* __restrict__ b,
-                                                         const double* __restrict__ x, double* __restrict__ r,
-                                                         double* __restrict__ rh, double* __restrict__ p,
-                                                         double* __restrict__ v, double* __restrict__ part) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    FOR_CELLS(d, i, q) {
-        const double ri = b[i] - apply_row(d, i, q, m, x);
-        r[i] = ri;
-        rh[i] = ri;
-        p[i] = 0.0;
-        v[i] = 0.0;
-        s0 += ri * ri;
-        s1 += ri * ri;
-        s2 += b[i] * b[i];
-    }
-    block_sum3(s0, s1, s2, part);
-}
 
 // p = r + beta (p - omega v), ph = p / diag.
 __global__ void __launch_bounds__(kDiffBlock) k_bi_dir(Dom d, const double* __restrict__ scal, Rows m,
@@ -239,24 +281,6 @@ __global__ void __launch_bounds__(kDiffBlock) k_bi_dir(Dom d, const double* __re
         p[i] = pi;
         ph[i] = pi / row_diag(m, i, m.kind[i]);
     }
-}
-
-// y = A xin; partials (rhat.y, 0, 0) or, with s, (y.s, y.y, 0).
-__global__ void __launch_bounds__(kDiffBlock) k_bi_spmv(Dom d, Rows m, const double* __restrict__ xin,
-                                                        double* __restrict__ y, const double* __restrict__ rh,
-                                                        const double* __restrict__ s, double* __restrict__ part) {
-    double s0 = 0.0, s1 = 0.0;
-    FOR_CELLS(d, i, q) {
-        const double yi = apply_row(d, i, q, m, xin);
-        y[i] = yi;
-        if (s) {
-            s0 += yi * s[i];
-            s1 += yi * yi;
-        } else {
-            s0 += rh[i] * yi;
-        }
-    }
-    block_sum3(s0, s1, 0.0, part);
 }
 
 // s = r - alpha v, sh = s / diag.
@@ -347,6 +371,11 @@ __global__ void __launch_bounds__(kDiffBlock) k_diff_finish(Dom d, const double*
     }
 }
 
+dim3 march_grid(const Dom& d) {
+    const int nz = d.ndim == 3 ? d.n[2] : 1;
+    return dim3((d.n[0] + 63) / 64, (d.n[1] + 3) / 4, (nz + kMarch - 1) / kMarch);
+}
+
 int grid_for(long n) {
     const long nb = (n + kDiffBlock - 1) / kDiffBlock;
     return (int)(nb < kDiffGrid ? nb : kDiffGrid);
@@ -368,7 +397,9 @@ DiffLayout diff_layout(const Dom& d) {
     L.off = take(kSides * n * sizeof(double));
     L.b = take(n * sizeof(double));
     for (int k = 0; k < 9; ++k) L.vec[k] = take(n * sizeof(double));
-    L.part = take(3 * (size_t)kDiffGrid * sizeof(double));
+    const dim3 mg = march_grid(d);
+    const size_t nm = (size_t)mg.x * mg.y * mg.z;
+    L.part = take(3 * (nm > (size_t)kDiffGrid ? nm : (size_t)kDiffGrid) * sizeof(double));
     L.scal = take(kBiScalars * sizeof(double));
     L.bytes = off;
     return L;
@@ -422,22 +453,26 @@ hipError_t launch_diff_start(const Dom& d, const double* c, const double* e, dou
     io.rows.rc = row_const(d, h, dt, k_l, k_g);
     hipLaunchKernelGGL(k_diff_assemble, dim3(ng), dim3(kDiffBlock), 0, s, d, c, e, h, dt, k_l, k_g, io.kind, io.diag,
                        io.off, io.b, io.x);
-    hipLaunchKernelGGL(k_bi_start, dim3(ng), dim3(kDiffBlock), 0, s, d, io.rows, io.b, io.x, io.r, io.rh, io.p, io.v,
-                       io.part);
-    hipLaunchKernelGGL(k_bi_reduce, dim3(1), dim3(kDiffBlock), 0, s, io.part, ng, io.scal, 0);
+    const dim3 mg = march_grid(d);
+    const int nm = (int)(mg.x * mg.y * mg.z);
+    hipLaunchKernelGGL(k_bi_march<0>, mg, dim3(64, 4), 0, s, d, io.rows, io.x, io.r, (const double*)nullptr,
+                       (const double*)nullptr, io.b, io.rh, io.p, io.v, io.part);
+    hipLaunchKernelGGL(k_bi_reduce, dim3(1), dim3(kDiffBlock), 0, s, io.part, nm, io.scal, 0);
     return hipGetLastError();
 }
 
 hipError_t launch_diff_iteration(const Dom& d, const DiffIO& io, hipStream_t s) {
     const int ng = grid_for(d.ncell);
     hipLaunchKernelGGL(k_bi_dir, dim3(ng), dim3(kDiffBlock), 0, s, d, io.scal, io.rows, io.r, io.v, io.p, io.ph);
-    hipLaunchKernelGGL(k_bi_spmv, dim3(ng), dim3(kDiffBlock), 0, s, d, io.rows, io.ph, io.v, io.rh,
-                       (const double*)nullptr, io.part);
-    hipLaunchKernelGGL(k_bi_reduce, dim3(1), dim3(kDiffBlock), 0, s, io.part, ng, io.scal, 1);
+    const dim3 mg = march_grid(d);
+    const int nm = (int)(mg.x * mg.y * mg.z);
+    hipLaunchKernelGGL(k_bi_march<1>, mg, dim3(64, 4), 0, s, d, io.rows, io.ph, io.v, io.rh, (const double*)nullptr,
+                       (const double*)nullptr, (double*)nullptr, (double*)nullptr, (double*)nullptr, io.part);
+    hipLaunchKernelGGL(k_bi_reduce, dim3(1), dim3(kDiffBlock), 0, s, io.part, nm, io.scal, 1);
     hipLaunchKernelGGL(k_bi_half, dim3(ng), dim3(kDiffBlock), 0, s, d, io.scal, io.rows, io.r, io.v, io.s, io.sh);
-    hipLaunchKernelGGL(k_bi_spmv, dim3(ng), dim3(kDiffBlock), 0, s, d, io.rows, io.sh, io.t, io.rh,
-                       (const double*)io.s, io.part);
-    hipLaunchKernelGGL(k_bi_reduce, dim3(1), dim3(kDiffBlock), 0, s, io.part, ng, io.scal, 2);
+    hipLaunchKernelGGL(k_bi_march<2>, mg, dim3(64, 4), 0, s, d, io.rows, io.sh, io.t, io.rh, (const double*)io.s,
+                       (const double*)nullptr, (double*)nullptr, (double*)nullptr, (double*)nullptr, io.part);
+    hipLaunchKernelGGL(k_bi_reduce, dim3(1), dim3(kDiffBlock), 0, s, io.part, nm, io.scal, 2);
     hipLaunchKernelGGL(k_bi_update, dim3(ng), dim3(kDiffBlock), 0, s, d, io.scal, io.ph, io.sh, io.s, io.t, io.rh,
                        io.x, io.r, io.part);
     hipLaunchKernelGGL(k_bi_reduce, dim3(1), dim3(kDiffBlock), 0, s, io.part, ng, io.scal, 3);
