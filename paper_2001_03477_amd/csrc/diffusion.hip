@@ -226,12 +226,24 @@ __global__ void __launch_bounds__(kDiffBlock) k_bi_march(Dom d, Rows m, const do
         const bool three = d.ndim == 3;
         double xprev = three ? xin[nb_pos(z0 - 1, nz, d.bc[2]) * plane + col] : 0.0;
         double xcur = xin[z0 * plane + col];
+        // the plane z's in-plane neighbours and kind, loaded one step ahead
+        double n0 = xin[z0 * plane + xm], n1 = xin[z0 * plane + xp], n2 = xin[z0 * plane + ym],
+               n3 = xin[z0 * plane + yp];
+        uint8_t kn = m.kind[z0 * plane + col];
         for (int z = z0; z < z1; ++z) {
             const long zb = z * plane;
             const long i = zb + col;
             const double xnext = three ? xin[nb_pos(z + 1, nz, d.bc[2]) * plane + col] : 0.0;
-            const double nbv[6] = {xin[zb + xm], xin[zb + xp], xin[zb + ym], xin[zb + yp], xprev, xnext};
-            const uint8_t k = m.kind[i];
+            const double nbv[6] = {n0, n1, n2, n3, xprev, xnext};
+            const uint8_t k = kn;
+            if (z + 1 < z1) {
+                const long zn = zb + plane;
+                n0 = xin[zn + xm];
+                n1 = xin[zn + xp];
+                n2 = xin[zn + ym];
+                n3 = xin[zn + yp];
+                kn = m.kind[zn + col];
+            }
             double yi = row_diag(m, i, k) * xcur;
             const int sides = 2 * d.ndim;
             if (k & 2) {
