@@ -196,8 +196,8 @@ int pcvof_compute_mass_flux(pcvof_handle* h, double k_l, double k_g, double h_fg
    reductions) until |r|_2 <= rel_tol |b|_2 (0 < rel_tol < 1), at most max_iter
    iterations (>= 1). Needs the fractions, the velocity and the mass flux
    (PCVOF_ERR_STATE otherwise); rho_g > 0. d_workspace: device memory of at least
-   pcvof_extension_workspace_bytes(h) bytes, owned by the caller, only used during the
-   call (PCVOF_ERR_WORKSPACE if smaller). du, dv, dw (optional, dw ignored in 2D)
+   pcvof_extension_workspace_bytes(h) bytes, 256-byte aligned, owned by the caller, only
+   used during the call (PCVOF_ERR_WORKSPACE if smaller or misaligned). du, dv, dw (optional, dw ignored in 2D)
    receive u~ per face in the velocity layouts, in host (mem = 0) or device (mem = 1)
    memory. info (optional) receives the number of unknowns, the iterations and the
    final relative residual. When the iterations do not converge (a part of the
@@ -237,7 +237,8 @@ int pcvof_extend_velocity(pcvof_handle* h, double rho_g, double rel_tol, int max
    is unchanged. dt > 0, k_l, k_g >= 0 (PCVOF_ERR_ARG otherwise); needs the fractions
    and energies (PCVOF_ERR_STATE); not inside a step, not on a batch domain.
    d_workspace: device memory of at least pcvof_diffusion_workspace_bytes(h) bytes,
-   owned by the caller, used during the call only (PCVOF_ERR_WORKSPACE if smaller).
+   256-byte aligned, owned by the caller, used during the call only (PCVOF_ERR_WORKSPACE
+   if smaller or misaligned).
    T_out (optional) receives T^{n+1} in the cell layout, in host (mem = 0) or device
    (mem = 1) memory; info (optional) the iterations and final relative residual
    (unknowns = cells). */

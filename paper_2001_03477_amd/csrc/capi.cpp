@@ -706,6 +706,7 @@ int pcvof_extend_velocity(pcvof_handle* h, double rho_g, double rel_tol, int max
     const pcv::ExtLayout L = pcv::ext_layout(h->d, maxf);
     if (!d_workspace || workspace_bytes < L.bytes)
         return fail(PCVOF_ERR_WORKSPACE, "extension workspace of %zu bytes, %zu needed", workspace_bytes, L.bytes);
+    if (((uintptr_t)d_workspace) % kAlign) return fail(PCVOF_ERR_WORKSPACE, "workspace not 256-byte aligned");
     const pcv::ExtIO io = pcv::ext_views(L, d_workspace);
     const double* c = h->c(h->cur);
     HIP_TRY(pcv::launch_ext_labels(h->d, c, io, h->stream));
@@ -790,6 +791,7 @@ int pcvof_diffuse(pcvof_handle* h, double dt, double k_l, double k_g, double rel
     const pcv::DiffLayout L = pcv::diff_layout(h->d);
     if (!d_workspace || workspace_bytes < L.bytes)
         return fail(PCVOF_ERR_WORKSPACE, "diffusion workspace of %zu bytes, %zu needed", workspace_bytes, L.bytes);
+    if (((uintptr_t)d_workspace) % kAlign) return fail(PCVOF_ERR_WORKSPACE, "workspace not 256-byte aligned");
     pcv::DiffIO io = pcv::diff_views(L, d_workspace);
     const double* c = h->c(h->cur);
     double* e = h->e(h->cur);

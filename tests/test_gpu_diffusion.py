@@ -125,6 +125,8 @@ def test_diffusion_errors_and_no_convergence(pc):
     need = lib.pcvof_diffusion_workspace_bytes(d._h)
     ws = torch.empty(need, dtype=torch.uint8, device="cuda")
     assert lib.pcvof_diffuse(d._h, 1e-3, 0.1, 0.01, 1e-12, 100, ws.data_ptr(), need - 1, None, 1, None) == -5
+    big = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    assert lib.pcvof_diffuse(d._h, 1e-3, 0.1, 0.01, 1e-12, 100, big.data_ptr() + 8, need, None, 1, None) == -5
     e0 = d.energy().cpu().numpy()
     with pytest.raises(pc.PcvofError) as ex:
         d.diffuse(10.0, 0.1, 0.01, rel_tol=1e-15, max_iter=1)

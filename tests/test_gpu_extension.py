@@ -221,6 +221,9 @@ def test_extension_errors(pc):
     ws = torch.empty(need, dtype=torch.uint8, device="cuda")
     rc = lib.pcvof_extend_velocity(d._h, 0.25, 1e-12, 100, ws.data_ptr(), need - 1, None, None, None, 1, None)
     assert rc == -5
+    big = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    rc = lib.pcvof_extend_velocity(d._h, 0.25, 1e-12, 100, big.data_ptr() + 8, need, None, None, None, 1, None)
+    assert rc == -5  # misaligned
     # too few iterations: refused
     with pytest.raises(pc.PcvofError) as ex:
         d.extend_velocity(0.25, rel_tol=1e-14, max_iter=1)
