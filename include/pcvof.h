@@ -15,14 +15,20 @@
  *     Delta d = -(m''/rho_l) dt / h in mixed cells, with the capped motion carried
  *     into the neighbours the interface moves into, and the latent energy correction
  *     Delta e = Delta c (C_pl - C_pg) T_Gamma (section 3.4.1).
+ * Around the step: pcvof_extend_velocity turns a one-fluid velocity into the liquid
+ * velocity of step 1 (section 3.3.1, eq. press_inv), pcvof_diffuse takes one implicit
+ * energy-diffusion step with T_Gamma at the interface (section 3.4.2), and
+ * pcvof_compute_mass_flux would give m'' from the reconstruction (section 3.2; its
+ * kernels are switched off in this version).
  *
  * Layout. Cell arrays are [nz][ny][nx] doubles, x fastest. MAC face velocities:
  * u [nz][ny][nx+1] on x-faces, v [nz][ny+1][nx] on y-faces, w [nz+1][ny][nx] on
  * z-faces (face i lies between cells i-1 and i). For a periodic axis the last face
  * must equal the first. 2D grids have ndim = 2, nz = 1 and no w.
  *
- * Ownership. The caller owns all memory: a device workspace of
- * pcvof_workspace_bytes() bytes (for instance a torch uint8 tensor) and the HIP
+ * Ownership. The caller owns all memory: a 256-byte aligned device workspace of
+ * pcvof_workspace_bytes() bytes (for instance a torch uint8 tensor), the workspaces
+ * the extension and the diffusion take per call, and the HIP
  * stream (for instance torch.cuda.current_stream().cuda_stream). The library never
  * allocates device memory, never keeps pointers passed to set_/get_ calls, and
  * enqueues all work on the given stream. Calls with mem = PCVOF_MEM_DEVICE copy
