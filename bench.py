@@ -473,7 +473,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the advection step of one domain is measured on "
-              "one MI355X (multi-GPU sharding is a design note, not part of this build)",
+              "one MI355X; sharding over several GPUs is designed but not implemented",
               file=sys.stderr)
         sys.exit(2)
 
