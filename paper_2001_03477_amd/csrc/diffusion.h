@@ -14,13 +14,13 @@ constexpr int kDiffBlock = 256;
 constexpr int kDiffGrid = 2048;  // blocks of the grid-stride kernels (and partials per reduction)
 enum { kBiRho = 0, kBiAlpha = 1, kBiOmega = 2, kBiBeta = 3, kBiRr = 4, kBiBb = 5, kBiScalars = 8 };
 
-// Diagonal and neighbour coefficient of a phase's regular row (a node of that phase
-// with a node of the same phase on every side); index 0 gas, 1 liquid.
+// Neighbour coefficient of a phase's regular row (a node of that phase whose sides are
+// nodes of the same phase or walls); index 0 gas, 1 liquid.
 struct RowConst {
-    double c[2], dg[2];
+    double c[2];
 };
-// The operator: per cell a kind byte (bit 0 liquid, bit 1 stored row), the stored rows'
-// diagonal and coefficients, the regular rows' constants.
+// The operator: per cell a kind byte (bit 0 liquid, bit 1 stored row, bits 2 to 7 the
+// wall sides), the stored rows' diagonal and coefficients, the regular rows' constants.
 struct Rows {
     const uint8_t* kind;
     const double* diag;
@@ -30,7 +30,7 @@ struct Rows {
 
 // Views into the caller's diffusion workspace (diff_layout gives the offsets).
 struct DiffIO {
-    uint8_t* kind;  // per cell: bit 0 liquid, bit 1 row stored (a wall or interface side)
+    uint8_t* kind;  // per cell: bit 0 liquid, bit 1 row stored (an interface side), bits 2-7 wall sides
     double* diag;   // per cell: diagonal of the backward-Euler operator (stored rows)
     double* off;    // 6 slots x cells (slot-major): coefficient of the face neighbour (0: wall or interface)
     double* b;      // per cell: right-hand side (T* and the T_Gamma terms)

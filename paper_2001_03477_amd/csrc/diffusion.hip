@@ -119,7 +119,8 @@ __global__ void __launch_bounds__(kDiffBlock) k_diff_assemble(Dom d, const doubl
         const double a = dt * (liquid ? k_l : k_g) / (liquid ? d.cp_l : d.cp_g);
         const double Ts = e[i] / cp_of(d, ci);
         double dg = 1.0, rhs = Ts;
-        bool irregular = false;
+        bool iface = false;
+        unsigned walls = 0;  // bit slot: that side is an outflow wall
         double ok[kSides];
         int slot = 0;
         for (int axis = 0; axis < d.ndim; ++axis) {
@@ -149,14 +150,15 @@ __global__ void __launch_bounds__(kDiffBlock) k_diff_assemble(Dom d, const doubl
                     if (sk[s] == 1) o = -coef;
                     else rhs += coef * d.T_gamma;
                 }
-                if (sk[s] != 1) irregular = true;
+                if (sk[s] == 0) walls |= 1u << slot;
+                if (sk[s] == 2) iface = true;
                 ok[slot] = o;
             }
         }
-        // a row with a same-phase node on every side is its phase's regular row
-        // (RowConst); the others are stored
-        kindo[i] = (uint8_t)((liquid ? 1 : 0) | (irregular ? 2 : 0));
-        if (irregular) {
+        // a row without an interface side is its phase's regular row (RowConst) with
+        // the wall sides left out; the others are stored
+        kindo[i] = (uint8_t)((liquid ? 1 : 0) | (iface ? 2 : 0) | walls << 2);
+        if (iface) {
             for (int q2 = 0; q2 < kSides; ++q2) off[(long)q2 * d.ncell + i] = q2 < slot ? ok[q2] : 0.0;
             diag[i] = dg;
         }
@@ -166,10 +168,17 @@ __global__ void __launch_bounds__(kDiffBlock) k_diff_assemble(Dom d, const doubl
 }
 
 // y_i = diag_i x_i + sum over sides of off_side(i) x_neighbour (zero coefficients for
-// walls and interface sides). Regular rows take their phase's diagonal and coefficient
-// (the same values the assembly computes), the others the stored ones.
-__device__ __forceinline__ double row_diag(const Rows& m, long i, uint8_t k) {
-    return (k & 2) ? m.diag[i] : m.rc.dg[k & 1];
+// walls and interface sides). Rows without an interface side take their phase's
+// coefficient on every side that is not a wall, and the diagonal 1 plus those
+// coefficients summed in side order (the same values the assembly computes); the others
+// the stored ones.
+__device__ __forceinline__ double row_diag(const Rows& m, long i, uint8_t k, int sides) {
+    if (k & 2) return m.diag[i];
+    const double c = m.rc.c[k & 1];
+    double dg = 1.0;
+    for (int slot = 0; slot < sides; ++slot)
+        if (!(k >> (2 + slot) & 1)) dg += c;
+    return dg;
 }
 
 // Up to three partial sums per block of kDiffBlock threads (tid the linear thread
@@ -244,8 +253,8 @@ __global__ void __launch_bounds__(kDiffBlock) k_bi_march(Dom d, Rows m, const do
                 n3 = xin[zn + yp];
                 kn = m.kind[zn + col];
             }
-            double yi = row_diag(m, i, k) * xcur;
             const int sides = 2 * d.ndim;
+            double yi = row_diag(m, i, k, sides) * xcur;
             if (k & 2) {
                 for (int slot = 0; slot < sides; ++slot) {
                     const double o = m.off[(long)slot * d.ncell + i];
@@ -253,7 +262,8 @@ __global__ void __launch_bounds__(kDiffBlock) k_bi_march(Dom d, Rows m, const do
                 }
             } else {
                 const double o = -m.rc.c[k & 1];
-                for (int slot = 0; slot < sides; ++slot) yi += o * nbv[slot];
+                for (int slot = 0; slot < sides; ++slot)
+                    if (!(k >> (2 + slot) & 1)) yi += o * nbv[slot];
             }
             if (MODE == 0) {
                 const double ri = b[i] - yi;
@@ -291,7 +301,7 @@ __global__ void __launch_bounds__(kDiffBlock) k_bi_dir(Dom d, const double* __re
     GRID_STRIDE(i, d.ncell) {
         const double pi = r[i] + be * (p[i] - om * v[i]);
         p[i] = pi;
-        ph[i] = pi / row_diag(m, i, m.kind[i]);
+        ph[i] = pi / row_diag(m, i, m.kind[i], 2 * d.ndim);
     }
 }
 
@@ -303,7 +313,7 @@ __global__ void __launch_bounds__(kDiffBlock) k_bi_half(Dom d, const double* __r
     GRID_STRIDE(i, d.ncell) {
         const double si = r[i] - al * v[i];
         s[i] = si;
-        sh[i] = si / row_diag(m, i, m.kind[i]);
+        sh[i] = si / row_diag(m, i, m.kind[i], 2 * d.ndim);
     }
 }
 
@@ -443,18 +453,14 @@ DiffIO diff_views(const DiffLayout& L, void* ws) {
     return io;
 }
 
-// The regular row of each phase, computed as the assembly computes it (width and
-// distances of one cell on every side).
-RowConst row_const(const Dom& d, double h, double dt, double k_l, double k_g) {
+// The neighbour coefficient of each phase's regular row, computed as the assembly
+// computes it (width and distances of one cell on every side).
+RowConst row_const(double h, double dt, double k_l, double k_g, double cp_l, double cp_g) {
     RowConst rc;
     for (int p = 0; p < 2; ++p) {
-        const double a = dt * (p ? k_l : k_g) / (p ? d.cp_l : d.cp_g);
+        const double a = dt * (p ? k_l : k_g) / (p ? cp_l : cp_g);
         const double width = 0.5 * (1.0 + 1.0);
-        const double coef = a / (width * h * 1.0 * h);
-        double dg = 1.0;
-        for (int side = 0; side < 2 * d.ndim; ++side) dg += coef;
-        rc.c[p] = coef;
-        rc.dg[p] = dg;
+        rc.c[p] = a / (width * h * 1.0 * h);
     }
     return rc;
 }
@@ -462,7 +468,7 @@ RowConst row_const(const Dom& d, double h, double dt, double k_l, double k_g) {
 hipError_t launch_diff_start(const Dom& d, const double* c, const double* e, double h, double dt, double k_l,
                              double k_g, DiffIO& io, hipStream_t s) {
     const int ng = grid_for(d.ncell);
-    io.rows.rc = row_const(d, h, dt, k_l, k_g);
+    io.rows.rc = row_const(h, dt, k_l, k_g, d.cp_l, d.cp_g);
     hipLaunchKernelGGL(k_diff_assemble, dim3(ng), dim3(kDiffBlock), 0, s, d, c, e, h, dt, k_l, k_g, io.kind, io.diag,
                        io.off, io.b, io.x);
     const dim3 mg = march_grid(d);
