@@ -27,7 +27,7 @@ namespace pcv {
 namespace {
 
 constexpr int kSides = 6;
-constexpr int kMarch = 16;  // cells per column of a product block along z
+constexpr int kMarch = 8;  // cells per column of a product block along z
 constexpr double kEpsTheta = 1e-3;
 
 // Coordinates of cell base + t: the block-uniform base is divided once, the lane's
