@@ -1,4 +1,4 @@
-"""Text summaries of rocprofv3 output for the sweep kernels.
+"""Text summaries of rocprofv3 output for the library's kernels.
 
 Reads the SQLite database that rocprofv3 writes (``-d DIR -o run`` gives
 ``DIR/run_results.db``) and prints:
@@ -9,7 +9,9 @@ Reads the SQLite database that rocprofv3 writes (``-d DIR -o run`` gives
   run and one ``--pmc WRITE_SIZE`` run of ``bench.py --calibration-copy-mib M``. Both
   counters are scaled by what they read for the calibration copy, whose true traffic is
   M MiB read and M MiB written. The result ends with a ``traffic_json:`` line that
-  bench.py reads back, tagged with a hash of the sweep kernel sources.
+  bench.py reads back, tagged with a hash of the sweep kernel sources;
+* ``kernels``: the same scaled HBM bytes per dispatch for every kernel whose name starts
+  with one of the given prefixes, also per cell of the grid.
 
 Usage::
 
@@ -129,6 +131,36 @@ def traffic_summary(fetch_db, write_db, calib_mib, workload, cmd_fetch, cmd_writ
     return "\n".join(lines)
 
 
+def kernels_summary(fetch_db, write_db, calib_mib, cells, prefixes, cmd_fetch, cmd_write):
+    """HBM bytes per dispatch of every kernel whose short name starts with one of the
+    prefixes, scaled like the sweep summary, with bytes per cell for a grid of cells."""
+    frows, wrows = counter_rows(fetch_db), counter_rows(write_db)
+    true_bytes = calib_mib * (1 << 20)
+    f_fetch = true_bytes / (calib_value(frows, "FETCH_SIZE") * 1024.0)
+    f_write = true_bytes / (calib_value(wrows, "WRITE_SIZE") * 1024.0)
+    per = collections.OrderedDict()
+    for rows, cn in ((frows, "FETCH_SIZE"), (wrows, "WRITE_SIZE")):
+        for n, c in rows:
+            k = short_name(n)
+            if cn in c and any(k.startswith(p) for p in prefixes):
+                per.setdefault(k, {"FETCH_SIZE": [], "WRITE_SIZE": []})[cn].append(c[cn])
+    lines = [f"fetch run: {cmd_fetch}", f"write run: {cmd_write}", "",
+             f"calibration copy: {calib_mib} MiB read + {calib_mib} MiB written",
+             f"scale factors (true bytes / counter bytes): FETCH_SIZE {f_fetch:.4f}, "
+             f"WRITE_SIZE {f_write:.4f}; bytes per cell over {cells} cells", "",
+             f"{'kernel':24s} {'n':>5s} {'read_MB':>10s} {'write_MB':>10s} {'read_B/cell':>12s} "
+             f"{'write_B/cell':>13s}"]
+    for k, v in per.items():
+        fe, wr = v["FETCH_SIZE"], v["WRITE_SIZE"]
+        if not fe or not wr:
+            continue
+        rb = sum(fe) / len(fe) * 1024 * f_fetch
+        wb = sum(wr) / len(wr) * 1024 * f_write
+        lines.append(f"{k[:24]:24s} {len(fe):5d} {rb / 1e6:10.2f} {wb / 1e6:10.2f} {rb / cells:12.2f} "
+                     f"{wb / cells:13.2f}")
+    return "\n".join(lines)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -142,8 +174,19 @@ def main(argv=None):
     f.add_argument("--workload", required=True)
     f.add_argument("--command-fetch", required=True)
     f.add_argument("--command-write", required=True)
+    k = sub.add_parser("kernels")
+    k.add_argument("--fetch", required=True)
+    k.add_argument("--write", required=True)
+    k.add_argument("--calib-mib", type=int, required=True)
+    k.add_argument("--cells", type=int, required=True)
+    k.add_argument("--prefixes", required=True, help="comma-separated kernel name prefixes")
+    k.add_argument("--command-fetch", required=True)
+    k.add_argument("--command-write", required=True)
     args = ap.parse_args(argv)
-    if args.what == "trace":
+    if args.what == "kernels":
+        print(kernels_summary(args.fetch, args.write, args.calib_mib, args.cells, args.prefixes.split(","),
+                              args.command_fetch, args.command_write))
+    elif args.what == "trace":
         print(trace_summary(args.db, args.command))
     else:
         print(traffic_summary(args.fetch, args.write, args.calib_mib, args.workload,
