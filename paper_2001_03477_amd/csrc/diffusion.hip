@@ -317,17 +317,20 @@ __global__ void __launch_bounds__(kDiffBlock) k_bi_half(Dom d, const double* __r
     }
 }
 
-// x += alpha ph + omega sh, r = s - omega t; partials (rhat.r, r.r, 0).
-__global__ void __launch_bounds__(kDiffBlock) k_bi_update(Dom d, const double* __restrict__ scal,
-                                                          const double* __restrict__ ph, const double* __restrict__ sh,
-                                                          const double* __restrict__ s, const double* __restrict__ t,
-                                                          const double* __restrict__ rh, double* __restrict__ x,
-                                                          double* __restrict__ r, double* __restrict__ part) {
+// x += alpha ph + omega sh (sh = s / diag recomputed rather than read), r = s - omega t;
+// partials (rhat.r, r.r, 0).
+__global__ void __launch_bounds__(kDiffBlock) k_bi_update(Dom d, const double* __restrict__ scal, Rows m,
+                                                          const double* __restrict__ ph, const double* __restrict__ s,
+                                                          const double* __restrict__ t, const double* __restrict__ rh,
+                                                          double* __restrict__ x, double* __restrict__ r,
+                                                          double* __restrict__ part) {
     const double al = scal[kBiAlpha], om = scal[kBiOmega];
     double s0 = 0.0, s1 = 0.0;
     GRID_STRIDE(i, d.ncell) {
-        x[i] += al * ph[i] + om * sh[i];
-        const double ri = s[i] - om * t[i];
+        const double si = s[i];
+        const double shi = si / row_diag(m, i, m.kind[i], 2 * d.ndim);  // as k_bi_half stored it
+        x[i] += al * ph[i] + om * shi;
+        const double ri = si - om * t[i];
         r[i] = ri;
         s0 += rh[i] * ri;
         s1 += ri * ri;
@@ -342,12 +345,20 @@ __global__ void __launch_bounds__(kDiffBlock) k_bi_update(Dom d, const double* _
 // host reports no convergence).
 __global__ void __launch_bounds__(kDiffBlock) k_bi_reduce(const double* __restrict__ part, int nb, double* __restrict__ scal,
                                                           int mode) {
-    double a = 0.0, b = 0.0, c3 = 0.0;
-    for (int k = threadIdx.x; k < nb; k += kDiffBlock) {
-        a += part[3 * k];
-        b += part[3 * k + 1];
-        c3 += part[3 * k + 2];
-    }
+    // four interleaved accumulators per quantity (more loads in flight), then a fixed tree
+    double acc[3][4] = {};
+    int k = threadIdx.x;
+    for (; k + 3 * kDiffBlock < nb; k += 4 * kDiffBlock)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) acc[q][u] += part[3 * (k + u * kDiffBlock) + q];
+    for (; k < nb; k += kDiffBlock)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) acc[q][0] += part[3 * k + q];
+    const double a = (acc[0][0] + acc[0][1]) + (acc[0][2] + acc[0][3]);
+    const double b = (acc[1][0] + acc[1][1]) + (acc[1][2] + acc[1][3]);
+    const double c3 = (acc[2][0] + acc[2][1]) + (acc[2][2] + acc[2][3]);
     __shared__ double s[3][kDiffBlock / 64];
     const double wa = wave_sum_lane63(a), wb = wave_sum_lane63(b), wc = wave_sum_lane63(c3);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -491,7 +502,7 @@ hipError_t launch_diff_iteration(const Dom& d, const DiffIO& io, hipStream_t s) 
     hipLaunchKernelGGL(k_bi_march<2>, mg, dim3(64, 4), 0, s, d, io.rows, io.sh, io.t, io.rh, (const double*)io.s,
                        (const double*)nullptr, (double*)nullptr, (double*)nullptr, (double*)nullptr, io.part);
     hipLaunchKernelGGL(k_bi_reduce, dim3(1), dim3(kDiffBlock), 0, s, io.part, nm, io.scal, 2);
-    hipLaunchKernelGGL(k_bi_update, dim3(ng), dim3(kDiffBlock), 0, s, d, io.scal, io.ph, io.sh, io.s, io.t, io.rh,
+    hipLaunchKernelGGL(k_bi_update, dim3(ng), dim3(kDiffBlock), 0, s, d, io.scal, io.rows, io.ph, io.s, io.t, io.rh,
                        io.x, io.r, io.part);
     hipLaunchKernelGGL(k_bi_reduce, dim3(1), dim3(kDiffBlock), 0, s, io.part, ng, io.scal, 3);
     return hipGetLastError();
