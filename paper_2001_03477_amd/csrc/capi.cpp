@@ -727,7 +727,7 @@ int pcvof_extend_velocity(pcvof_handle* h, double rho_g, double rel_tol, int max
             double rr = sc[pcv::kCgRr];
             bool conv = sqrt(rr) <= rel_tol * sqrt(gg);
             while (!conv && iters < max_iter) {
-                HIP_TRY(pcv::launch_cg_iteration(nu, io, h->stream));
+                HIP_TRY(pcv::launch_cg_iteration(nu, iters + 1, io, h->stream));
                 ++iters;
                 if (iters % 8 == 0 || iters == max_iter) {  // one host synchronisation per 8 iterations
                     HIP_TRY(hipMemcpyAsync(sc, io.scal, sizeof sc, hipMemcpyDeviceToHost, h->stream));

@@ -23,8 +23,9 @@ struct ExtIO {
     double* coef;     // per unknown, 6 slots: 1 / rho_f of that neighbour
     double* dg;       // per unknown: sum of 1 / rho_f over its non-wall faces (diagonal)
     double* g;        // per unknown: right-hand side of the symmetric positive system
-    double *x, *r, *z, *p, *q;  // conjugate-gradient vectors
-    double* part;     // per block: two partial sums
+    double *x, *r, *z, *p, *q, *p2;  // conjugate-gradient vectors (p2, p: directions of odd, even iterations)
+    double* part;     // per block: two partial sums (start, product)
+    double* part2;    // per block: two partial sums (update)
     double* scal;     // scalars of the iteration (kCg*)
     double* du;       // face buffer: u~ of one axis (for host output)
 };
@@ -36,7 +37,7 @@ constexpr int kExtScanBlock = 1024;
 enum { kCgRz = 0, kCgAlpha = 1, kCgBeta = 2, kCgRr = 3, kCgGg = 4, kCgScalars = 8 };
 
 struct ExtLayout {
-    size_t lab, map, list, counts, offs, total, nbr, coef, dg, g, vec[5], part, scal, du, bytes;
+    size_t lab, map, list, counts, offs, total, nbr, coef, dg, g, vec[6], part, part2, scal, du, bytes;
 };
 ExtLayout ext_layout(const Dom& d, long max_faces);
 ExtIO ext_views(const ExtLayout& L, void* ws);
@@ -49,7 +50,7 @@ hipError_t launch_ext_assemble(const Dom& d, const double* c, const double* mdot
 // Conjugate gradients with the diagonal as preconditioner: start (x = 0), then one
 // iteration; scal[kCgRr] and scal[kCgGg] hold |r|^2 and |g|^2 after each.
 hipError_t launch_cg_start(int nu, const ExtIO& io, hipStream_t s);
-hipError_t launch_cg_iteration(int nu, const ExtIO& io, hipStream_t s);
+hipError_t launch_cg_iteration(int nu, int iter, const ExtIO& io, hipStream_t s);
 // The stored velocity of axis (float when mixed) becomes u + u~ in place; du (may be
 // null) receives u~ per face; *maxbits (zeroed by the caller) the largest |u + u~| as
 // the bit pattern of a non-negative double.

@@ -272,56 +272,35 @@ __global__ void __launch_bounds__(kExtBlock) k_cg_start(int nu, const double* __
     block_sum2(rz, rr, part);
 }
 
-// q = M p (M the symmetric positive definite operator) and the partials of p . q.
-__global__ void __launch_bounds__(kExtBlock) k_cg_spmv(int nu, const int* __restrict__ nbr, const double* __restrict__ coef,
-                                                       const double* __restrict__ dg, const double* __restrict__ p,
-                                                       double* __restrict__ q, double* __restrict__ part) {
+// The new direction p = z + beta p_old (at the unknown and, recomputed, at its
+// neighbours: p_old and p are separate buffers), q = M p (M the symmetric positive
+// definite operator) and the partials of p . q.
+__global__ void __launch_bounds__(kExtBlock) k_cg_spmv(int nu, const double* __restrict__ scal, const int* __restrict__ nbr,
+                                                       const double* __restrict__ coef, const double* __restrict__ dg,
+                                                       const double* __restrict__ z, const double* __restrict__ p_old,
+                                                       double* __restrict__ p, double* __restrict__ q,
+                                                       double* __restrict__ part) {
     const int i = blockIdx.x * kExtBlock + threadIdx.x;
     double pq = 0.0;
     if (i < nu) {
-        const double pi = p[i];
+        const double be = scal[kCgBeta];
+        const double pi = fma(be, p_old[i], z[i]);  // the same rounding as at the neighbours
         double s = dg[i] * pi;
 #pragma unroll
         for (int k = 0; k < kNeighbours; ++k) {
             const int j = nbr[(long)i * kNeighbours + k];
-            if (j >= 0) s -= coef[(long)i * kNeighbours + k] * p[j];
+            if (j >= 0) s -= coef[(long)i * kNeighbours + k] * fma(be, p_old[j], z[j]);
         }
+        p[i] = pi;
         q[i] = s;
         pq = pi * s;
     }
     block_sum2(pq, 0.0, part);
 }
 
-__global__ void __launch_bounds__(kExtBlock) k_cg_update(int nu, const double* __restrict__ scal, const double* __restrict__ p,
-                                                         const double* __restrict__ q, const double* __restrict__ dg,
-                                                         double* __restrict__ x, double* __restrict__ r,
-                                                         double* __restrict__ z, double* __restrict__ part) {
-    const int i = blockIdx.x * kExtBlock + threadIdx.x;
-    double rz = 0.0, rr = 0.0;
-    if (i < nu) {
-        const double al = scal[kCgAlpha];
-        x[i] += al * p[i];
-        const double ri = r[i] - al * q[i];
-        const double zi = dg[i] > 0.0 ? ri / dg[i] : 0.0;
-        r[i] = ri;
-        z[i] = zi;
-        rz = ri * zi;
-        rr = ri * ri;
-    }
-    block_sum2(rz, rr, part);
-}
-
-__global__ void __launch_bounds__(kExtBlock) k_cg_dir(int nu, const double* __restrict__ scal, const double* __restrict__ z,
-                                                      double* __restrict__ p) {
-    const int i = blockIdx.x * kExtBlock + threadIdx.x;
-    if (i < nu) p[i] = z[i] + scal[kCgBeta] * p[i];
-}
-
-// Sums the nb pairs of partials in a fixed order and updates the scalars: mode 0 after
-// the start (rz, rr, gg = rr), 1 after the product (alpha = rz / pq), 2 after the
-// update (beta = rz' / rz, rz = rz', rr).
-__global__ void __launch_bounds__(kExtBlock) k_cg_reduce(const double* __restrict__ part, int nb, double* __restrict__ scal,
-                                                         int mode) {
+// Fixed-order sums of nb pairs of block partials: every thread of the block gets the
+// same totals (the same order in every block and in k_cg_reduce).
+__device__ __forceinline__ void sum_pairs(const double* __restrict__ part, int nb, double& ta, double& tb) {
     double a = 0.0, b = 0.0;
     for (int k = threadIdx.x; k < nb; k += kExtBlock) {
         a += part[2 * k];
@@ -335,18 +314,52 @@ __global__ void __launch_bounds__(kExtBlock) k_cg_reduce(const double* __restric
         s_b[w] = wb;
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    double ta = s_a[0], tb = s_b[0];
+    ta = s_a[0];
+    tb = s_b[0];
     for (int k = 1; k < kExtBlock / 64; ++k) {
         ta += s_a[k];
         tb += s_b[k];
     }
+}
+
+// alpha = rz / p.q from the product's partials (each block sums them itself), then
+// x += alpha p, r -= alpha q, z = r / diag and the partials of r . z, r . r.
+__global__ void __launch_bounds__(kExtBlock) k_cg_update(int nu, const double* __restrict__ scal,
+                                                         const double* __restrict__ part_pq, int nb,
+                                                         const double* __restrict__ p, const double* __restrict__ q,
+                                                         const double* __restrict__ dg, double* __restrict__ x,
+                                                         double* __restrict__ r, double* __restrict__ z,
+                                                         double* __restrict__ part) {
+    double pq, unused;
+    sum_pairs(part_pq, nb, pq, unused);
+    const double al = pq > 0.0 ? scal[kCgRz] / pq : 0.0;
+    const int i = blockIdx.x * kExtBlock + threadIdx.x;
+    double rz = 0.0, rr = 0.0;
+    if (i < nu) {
+        x[i] += al * p[i];
+        const double ri = r[i] - al * q[i];
+        const double zi = dg[i] > 0.0 ? ri / dg[i] : 0.0;
+        r[i] = ri;
+        z[i] = zi;
+        rz = ri * zi;
+        rr = ri * ri;
+    }
+    block_sum2(rz, rr, part);
+}
+
+// Sums the nb pairs of partials in a fixed order and updates the scalars: mode 0 after
+// the start (rz, rr, gg = rr, beta = 0), otherwise after the update (beta = rz' / rz,
+// rz = rz', rr).
+__global__ void __launch_bounds__(kExtBlock) k_cg_reduce(const double* __restrict__ part, int nb, double* __restrict__ scal,
+                                                         int mode) {
+    double ta, tb;
+    sum_pairs(part, nb, ta, tb);
+    if (threadIdx.x != 0) return;
     if (mode == 0) {
         scal[kCgRz] = ta;
         scal[kCgRr] = tb;
         scal[kCgGg] = tb;
-    } else if (mode == 1) {
-        scal[kCgAlpha] = ta > 0.0 ? scal[kCgRz] / ta : 0.0;
+        scal[kCgBeta] = 0.0;
     } else {
         scal[kCgBeta] = scal[kCgRz] > 0.0 ? ta / scal[kCgRz] : 0.0;
         scal[kCgRz] = ta;
@@ -463,8 +476,9 @@ ExtLayout ext_layout(const Dom& d, long max_faces) {
     L.coef = take(n * kNeighbours * sizeof(double));
     L.dg = take(n * sizeof(double));
     L.g = take(n * sizeof(double));
-    for (int k = 0; k < 5; ++k) L.vec[k] = take(n * sizeof(double));
+    for (int k = 0; k < 6; ++k) L.vec[k] = take(n * sizeof(double));
     L.part = take(2 * nb * sizeof(double));
+    L.part2 = take(2 * nb * sizeof(double));
     L.scal = take(kCgScalars * sizeof(double));
     L.du = take((size_t)max_faces * sizeof(double));
     L.bytes = off;
@@ -489,7 +503,9 @@ ExtIO ext_views(const ExtLayout& L, void* ws) {
     io.z = (double*)(b + L.vec[2]);
     io.p = (double*)(b + L.vec[3]);
     io.q = (double*)(b + L.vec[4]);
+    io.p2 = (double*)(b + L.vec[5]);
     io.part = (double*)(b + L.part);
+    io.part2 = (double*)(b + L.part2);
     io.scal = (double*)(b + L.scal);
     io.du = (double*)(b + L.du);
     return io;
@@ -523,14 +539,17 @@ hipError_t launch_cg_start(int nu, const ExtIO& io, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_cg_iteration(int nu, const ExtIO& io, hipStream_t s) {
+hipError_t launch_cg_iteration(int nu, int iter, const ExtIO& io, hipStream_t s) {
     const int nb = blocks_for(nu);
-    hipLaunchKernelGGL(k_cg_spmv, dim3(nb), dim3(kExtBlock), 0, s, nu, io.nbr, io.coef, io.dg, io.p, io.q, io.part);
-    hipLaunchKernelGGL(k_cg_reduce, dim3(1), dim3(kExtBlock), 0, s, io.part, nb, io.scal, 1);
-    hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(kExtBlock), 0, s, nu, io.scal, io.p, io.q, io.dg, io.x, io.r,
-                       io.z, io.part);
-    hipLaunchKernelGGL(k_cg_reduce, dim3(1), dim3(kExtBlock), 0, s, io.part, nb, io.scal, 2);
-    hipLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(kExtBlock), 0, s, nu, io.scal, io.z, io.p);
+    // the direction of iteration iter (1, 2, ...) goes to p2 for odd iter, p for even;
+    // the first reads the start's p = z (with beta = 0)
+    double* p_new = (iter & 1) ? io.p2 : io.p;
+    const double* p_old = (iter & 1) ? io.p : io.p2;
+    hipLaunchKernelGGL(k_cg_spmv, dim3(nb), dim3(kExtBlock), 0, s, nu, io.scal, io.nbr, io.coef, io.dg, io.z, p_old,
+                       p_new, io.q, io.part);
+    hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(kExtBlock), 0, s, nu, io.scal, io.part, nb, p_new, io.q, io.dg,
+                       io.x, io.r, io.z, io.part2);
+    hipLaunchKernelGGL(k_cg_reduce, dim3(1), dim3(kExtBlock), 0, s, io.part2, nb, io.scal, 2);
     return hipGetLastError();
 }
 
