@@ -8,9 +8,29 @@ namespace pcv {
 
 namespace {
 
+// A thread's share of a column of nb block partials: sixteen strided accumulators while
+// sixteen loads fit, then four, then one (loads in flight for long columns such as the
+// per-cell-block partials of step 2), combined in a fixed tree.
+__device__ __forceinline__ double column_partial(const double* __restrict__ P, int nb) {
+    double v[16] = {};
+    int b = threadIdx.x;
+    for (; b + 15 * 256 < nb; b += 16 * 256)
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] += P[b + u * 256];
+    for (; b + 3 * 256 < nb; b += 4 * 256)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] += P[b + u * 256];
+    for (; b < nb; b += 256) v[0] += P[b];
+#pragma unroll
+    for (int w = 8; w > 0; w >>= 1)
+#pragma unroll
+        for (int u = 0; u < w; ++u) v[u] += v[u + w];
+    return v[0];
+}
+
 // Column sums of the quantity-major partial tables: block (q, slot) adds the nb[slot]
-// block partials of quantity q in a fixed order (four strided accumulators per thread,
-// then a fixed tree).
+// block partials of quantity q in a fixed order (column_partial per thread, then a
+// fixed tree).
 __global__ void __launch_bounds__(256)
 k_colsum(const double* __restrict__ part, long stride, int nb0, int nb1, int nb2, int nb3,
          double* __restrict__ colsum) {
@@ -18,16 +38,7 @@ k_colsum(const double* __restrict__ part, long stride, int nb0, int nb1, int nb2
     const int q = blockIdx.x, slot = blockIdx.y;
     const int nb = slot == 0 ? nb0 : (slot == 1 ? nb1 : (slot == 2 ? nb2 : nb3));
     const double* P = part + ((long)slot * kPartialWidth + q) * stride;
-    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
-    int b = threadIdx.x;
-    for (; b + 768 < nb; b += 1024) {
-        v0 += P[b];
-        v1 += P[b + 256];
-        v2 += P[b + 512];
-        v3 += P[b + 768];
-    }
-    for (; b < nb; b += 256) v0 += P[b];
-    sm[threadIdx.x] = (v0 + v1) + (v2 + v3);
+    sm[threadIdx.x] = column_partial(P, nb);
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
@@ -44,16 +55,7 @@ __global__ void __launch_bounds__(256) k_colsum_batch(const ColsumArgs* __restri
     const int q = blockIdx.x, slot = blockIdx.y;
     const int nb = c.nb[slot];
     const double* P = c.part + ((long)slot * kPartialWidth + q) * c.stride;
-    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
-    int b = threadIdx.x;
-    for (; b + 768 < nb; b += 1024) {
-        v0 += P[b];
-        v1 += P[b + 256];
-        v2 += P[b + 512];
-        v3 += P[b + 768];
-    }
-    for (; b < nb; b += 256) v0 += P[b];
-    sm[threadIdx.x] = (v0 + v1) + (v2 + v3);
+    sm[threadIdx.x] = column_partial(P, nb);
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
