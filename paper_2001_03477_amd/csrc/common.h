@@ -70,15 +70,19 @@ __device__ __forceinline__ double wave_sum_lane63(double v) {
 }
 
 // Sum of 8 per-thread values over a block of NWAVES wavefronts; thread q < 8 writes
-// the total of quantity q to out[q * stride]. Fixed shapes, so deterministic.
+// the total of quantity q to out[q * stride]. Fixed shapes, so deterministic. Bit q of
+// skip (uniform over the wavefront) says that quantity q is +0 in every lane: its
+// wavefront sum, +0, is then not computed.
 template <int NWAVES>
-__device__ __forceinline__ void block_sum8(const double (&v)[8], double* out, long stride) {
+__device__ __forceinline__ void block_sum8(const double (&v)[8], double* out, long stride, unsigned skip = 0) {
     __shared__ double red[8][NWAVES];
     const int tid = threadIdx.y * blockDim.x + threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
+    skip = __builtin_amdgcn_readfirstlane(skip);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-        const double s = wave_sum_lane63(v[q]);
+        double s = 0.0;
+        if (!(skip >> q & 1u)) s = wave_sum_lane63(v[q]);
         if (lane == 63) red[q][wave] = s;
     }
     __syncthreads();

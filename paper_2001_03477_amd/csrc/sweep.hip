@@ -855,7 +855,8 @@ k_phase_apply(Dom d, const double* __restrict__ c, const double* __restrict__ e,
     const unsigned long long bits = __ballot(mx);
     if (threadIdx.x == 0 && y < d.n[1]) mask_out[((long)z * d.n[1] + y) * d.wpr + blockIdx.x] = bits;
     const long blk = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    block_sum8<4>(acc, part + blk, part_stride);
+    // acc[2..5] are never set here; a quiet wavefront changes no cell (dc = de = +0)
+    block_sum8<4>(acc, part + blk, part_stride, 0x3Cu | (quiet ? 0x3u : 0u));
 }
 
 }  // namespace
