@@ -27,11 +27,12 @@ namespace {
 
 constexpr int kNeighbours = 6;
 
-// Cell coordinates of the linear cell index id.
+// Cell coordinates of the linear cell index id, in 32-bit unsigned arithmetic (the
+// extension takes at most 2^31 - 1 cells).
 __device__ __forceinline__ void cell_xyz(const Dom& d, long id, int& x, int& y, int& z) {
-    const long nx = d.n[0], ny = d.n[1];
-    x = (int)(id % nx);
-    const long r = id / nx;
+    const unsigned ui = (unsigned)id, nx = (unsigned)d.n[0], ny = (unsigned)d.n[1];
+    x = (int)(ui % nx);
+    const unsigned r = ui / nx;
     y = (int)(r % ny);
     z = (int)(r / ny);
 }
@@ -374,22 +375,25 @@ __device__ __forceinline__ double face_update(const Dom& d, int axis, long i, co
                                               const double* __restrict__ phi, T* __restrict__ vel,
                                               double* __restrict__ du) {
     const long nx = d.n[0], ny = d.n[1];
+    // the face's coordinates in 32-bit unsigned arithmetic (far cheaper than 64-bit
+    // division): the extension takes at most 2^31 - 1 cells, so fewer than 2^32 faces
+    const unsigned ui = (unsigned)i, ux = (unsigned)nx, uy = (unsigned)ny;
     int q[3], f;
     if (axis == 0) {
-        f = (int)(i % (nx + 1));
-        const long r = i / (nx + 1);
-        q[1] = (int)(r % ny);
-        q[2] = (int)(r / ny);
+        f = (int)(ui % (ux + 1u));
+        const unsigned r = ui / (ux + 1u);
+        q[1] = (int)(r % uy);
+        q[2] = (int)(r / uy);
     } else if (axis == 1) {
-        q[0] = (int)(i % nx);
-        const long r = i / nx;
-        f = (int)(r % (ny + 1));
-        q[2] = (int)(r / (ny + 1));
+        q[0] = (int)(ui % ux);
+        const unsigned r = ui / ux;
+        f = (int)(r % (uy + 1u));
+        q[2] = (int)(r / (uy + 1u));
     } else {
-        q[0] = (int)(i % nx);
-        const long r = i / nx;
-        q[1] = (int)(r % ny);
-        f = (int)(r / ny);
+        q[0] = (int)(ui % ux);
+        const unsigned r = ui / ux;
+        q[1] = (int)(r % uy);
+        f = (int)(r / uy);
     }
     const int n = d.n[axis];
     const bool per = d.bc[axis] == 0;
