@@ -1,13 +1,23 @@
 """Pins of the oracle's stencils: the interface normal (Youngs and the mixed
 Youngs-centred selection named in section 3.2) on exact planar blocks, and the
 WENO5 face temperature of section 3.4.1 (Jiang-Shu) by exactness, convergence
-order and non-oscillation."""
+order and non-oscillation.
+
+The mixed Youngs-centred selection (method 1) is pinned by what the exact geometry
+fixes: on shallow planes the centred columns bracket the interface and are exact, so
+method 1 must return them; on a 45 degree line through the block off its centre
+Youngs' gradient is exact by the x-y symmetry while the columns do not bracket the
+line, so method 1 must return Youngs; over random exact planes it must return the
+more accurate of the two candidates nearly always. A copy of the oracle with the
+selection inverted fails each of these pins."""
 import math
+from fractions import Fraction as Fr
 
 import numpy as np
 import pytest
 
 import exact
+import oracle_mutants
 
 
 def _unit1(n):
@@ -54,10 +64,187 @@ def test_centred_columns_exact_on_shallow_planes(orc, nd):
         x0 = [0.5, 0.5, 0.5]
         x0[d] = rng.uniform(0.3, 0.7)
         blk = exact.plane_block(n, x0, nd=nd)
-        m = orc.normal(blk, 2)
-        assert np.allclose(m, _unit1(n), atol=2e-15, rtol=0), (n, m)
-        if nd == 2:
-            assert m[2] == 0.0
+        for method in (2, 1):
+            m = orc.normal(blk, method)
+            assert np.allclose(m, _unit1(n), atol=2e-15, rtol=0), (method, n, m)
+            if nd == 2:
+                assert m[2] == 0.0
+
+
+def _angle(a, b):
+    a = np.asarray(a, dtype=float)
+    b = np.asarray(b, dtype=float)
+    cs = float(a @ b) / (np.linalg.norm(a) * np.linalg.norm(b))
+    return math.acos(max(-1.0, min(1.0, cs)))
+
+
+def _shallow_blocks(nd, count, seed):
+    """Exact blocks of planes whose transverse slopes (relative to the dominant axis)
+    are below 1/2, so that every 3-cell column along that axis brackets the plane."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        d = int(rng.integers(0, 3)) if nd == 3 else int(rng.integers(0, 2))
+        n = np.zeros(3)
+        n[d] = rng.choice([-1.0, 1.0])
+        for t in range(3):
+            if t != d and (nd == 3 or t != 2):
+                n[t] = rng.uniform(-0.45, 0.45)
+        x0 = [0.5, 0.5, 0.5]
+        x0[d] = rng.uniform(0.3, 0.7)
+        n = [float(v) for v in n]
+        out.append((exact.plane_block(n, x0, nd=nd), n))
+    return out
+
+
+def _diagonal_blocks():
+    """Exact blocks of 45 degree planes (two components of the normal of equal
+    magnitude, the third zero) through points off the block's centre along the first
+    of the two axes; (block, exact normal with |n|_1 = 1)."""
+    out = []
+    for a, b in ((0, 1), (1, 2), (0, 2)):
+        for sa, sb in ((1, 1), (1, -1), (-1, -1)):
+            for k in (1, 3, 5, 11, 13, 15):
+                n = [0, 0, 0]
+                n[a], n[b] = sa, sb
+                x0 = [Fr(1, 2)] * 3
+                x0[a] = Fr(k, 16)
+                nd = 2 if 2 not in (a, b) else 3
+                out.append((exact.plane_block(n, x0, nd=nd), _unit1(n)))
+    return out
+
+
+def _random_blocks(count, seed):
+    """Exact blocks of random planes (normal and point on a 1/64 lattice) whose
+    central cell is mixed; (block, exact normal)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        n = np.round(rng.normal(size=3) * 64) / 64
+        if not np.any(n):
+            continue
+        x0 = np.round(rng.uniform(0.2, 0.8, size=3) * 64) / 64
+        blk = exact.plane_block([float(v) for v in n], [float(v) for v in x0])
+        if 1e-12 < blk[1, 1, 1] < 1 - 1e-12:
+            out.append((blk, n))
+    return out
+
+
+def _check_myc_shallow(normal):
+    for nd in (2, 3):
+        for blk, n in _shallow_blocks(nd, 40, 40 + nd):
+            m = normal(blk, 1)
+            assert np.allclose(m, _unit1(n), atol=2e-15, rtol=0), ("shallow", n, m)
+
+
+def _check_myc_diagonal(normal):
+    for blk, n in _diagonal_blocks():
+        m0, m1, m2 = normal(blk, 0), normal(blk, 1), normal(blk, 2)
+        # Youngs is exact here (x-y symmetry of the block), the columns are not
+        assert np.array_equal(m0, n), ("youngs", n, m0)
+        assert np.max(np.abs(m2 - n)) > 1e-4, ("columns", n, m2)
+        assert np.array_equal(m1, m0), ("diagonal", n, m1)
+
+
+def _myc_pick_rate(normal, blocks):
+    """Fraction of the blocks (those where Youngs' and the centred-columns normal differ
+    in accuracy by more than 1e-9 rad) on which method 1 returns the more accurate of
+    the two; also checks that method 1 always returns one of them."""
+    better = decided = 0
+    for blk, n in blocks:
+        m0, m1, m2 = normal(blk, 0), normal(blk, 1), normal(blk, 2)
+        assert np.array_equal(m1, m0) or np.array_equal(m1, m2)
+        e0, e2 = _angle(m0, n), _angle(m2, n)
+        if abs(e0 - e2) <= 1e-9:
+            continue
+        decided += 1
+        better += np.array_equal(m1, m0 if e0 < e2 else m2)
+    return better / decided, decided
+
+
+@pytest.fixture(scope="module")
+def random_plane_blocks():
+    return _random_blocks(600, 61)
+
+
+def test_myc_falls_back_to_youngs_on_diagonal_planes(orc):
+    """On 45 degree planes through the block off its centre the 3-cell columns do not
+    bracket the plane (their heights are clipped), which flattens the centred-columns
+    candidate: its own component exceeds every component of Youngs' normal, and the
+    mixed selection must return Youngs, which the block's symmetry makes exact."""
+    _check_myc_diagonal(orc.normal)
+
+
+def test_myc_picks_the_more_accurate_candidate(orc, random_plane_blocks):
+    rate, decided = _myc_pick_rate(orc.normal, random_plane_blocks)
+    assert decided >= 500
+    assert rate >= 0.95, rate
+
+
+def _check_myc_tie_band(normal):
+    """Along the family of planes n = (1, s, 0) through (1/16, 1/2, 1/2) the selection
+    switches from the centred columns to Youngs where the columns' own component
+    overtakes Youngs' largest one. Just inside the band (0 < own - max|m_Youngs| <=
+    1e-12) the columns are kept, just outside it Youngs is taken."""
+    x0 = [Fr(1, 16), Fr(1, 2), Fr(1, 2)]
+
+    def gap(s):
+        blk = exact.plane_block([1.0, s, 0.0], x0, nd=2)
+        m0, m2 = normal(blk, 0), normal(blk, 2)
+        return np.max(np.abs(m2)) - np.max(np.abs(m0)), blk, m0, m2
+
+    lo, hi = 13 / 16, 14 / 16
+    assert gap(lo)[0] < 0 and gap(hi)[0] > 1e-6
+
+    def find(target):
+        a, b = lo, hi
+        for _ in range(200):
+            mid = 0.5 * (a + b)
+            g = gap(mid)[0]
+            if abs(g - target) <= 0.4 * target:
+                return mid
+            if g < target:
+                a = mid
+            else:
+                b = mid
+        raise RuntimeError("no plane with the requested gap")
+
+    g, blk, m0, m2 = gap(find(5e-13))
+    assert 0 < g <= 1e-12 and not np.array_equal(m0, m2)
+    assert np.array_equal(normal(blk, 1), m2), "inside the tie band"
+    g, blk, m0, m2 = gap(find(1e-10))
+    assert g > 1e-12
+    assert np.array_equal(normal(blk, 1), m0), "outside the tie band"
+
+
+def test_myc_exact_on_shallow_planes(orc):
+    _check_myc_shallow(orc.normal)
+
+
+def test_myc_tie_band(orc):
+    """Candidates within 1e-12 of each other count as equal (the reading that keeps
+    1e-16 input differences from switching formulas)."""
+    _check_myc_tie_band(orc.normal)
+
+
+def test_myc_tie_band_pin_catches_a_missing_band(tmp_path):
+    lib = oracle_mutants.build(tmp_path, [("if (best_own > ymax + NORMAL_TIE) {", "if (best_own > ymax) {")])
+    with pytest.raises(AssertionError, match="inside the tie band"):
+        _check_myc_tie_band(oracle_mutants.normal_fn(lib))
+
+
+def test_myc_pins_catch_an_inverted_selection(tmp_path, random_plane_blocks):
+    """The same pins on a copy of the oracle whose selection test is inverted (Youngs
+    taken exactly where the centred columns should be): each pin fails."""
+    lib = oracle_mutants.build(tmp_path, [("if (best_own > ymax + NORMAL_TIE) {",
+                                           "if (!(best_own > ymax + NORMAL_TIE)) {")])
+    normal = oracle_mutants.normal_fn(lib)
+    with pytest.raises(AssertionError):
+        _check_myc_shallow(normal)
+    with pytest.raises(AssertionError):
+        _check_myc_diagonal(normal)
+    rate, _ = _myc_pick_rate(normal, random_plane_blocks)
+    assert rate < 0.5, rate
 
 
 def test_normal_orientation_and_symmetry(orc):
