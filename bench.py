@@ -1,17 +1,20 @@
 """Benchmark of the advection step on one MI355X.
 
-Workload (default): the 3D 128^3 LeVeque deformation of a sphere R = 0.15 at
-(0.35, 0.35, 0.35), CFL 0.3, per-phase random temperatures, rho c_p 1000 : 1,
-m'' = 0, FP64. A step is the whole hot path: prologue, three direction sweeps
-(geometric VOF fluxes + conservative WENO5 energy fluxes), checksums.
+Workload (default): the 3D 512^3 periodic box with 2000 seeded droplets (radii 4-16
+cells), a divergence-free random Fourier velocity at CFL 0.3, per-phase random
+temperatures, the water heat-capacity ratio, m'' = 0, FP64. A step is the whole hot
+path: prologue, three direction sweeps (geometric VOF fluxes + conservative WENO5
+energy fluxes), checksums.
 
 Prints one JSON line: whole-job cell-updates/s of the FP64 path over the timed steps
 (inputs already resident in HBM), the roofline of the dominant kernel (the sweep;
 algorithmic bytes per launch over its average duration, measured with HIP events on
 the library's stream over as many steps again, right after the timed ones), the same
-run in the mixed-precision mode (rate, speedup,
-roofline, volume drift and difference from the FP64 fractions), and the oracle timed
-on the host on a bounded sample.
+run in the mixed-precision mode (rate, speedup, roofline, volume drift and difference
+from the FP64 fractions), the 128^3 LeVeque and 256^3 bubble workloads (with phase
+change, the liquid-velocity extension and the energy diffusion) as extra keys with the
+energy-flux and split ablations, and the oracle timed on the host's cores on a bounded
+sample.
 """
 import argparse
 import json
@@ -68,10 +71,10 @@ def sweep_bytes(wl, axis, mixed=False):
     return SWEEP_BYTES_PER_CELL * wl.ncells + SWEEP_BYTES_PER_FACE * faces
 
 
-def recorded_traffic(wl, sweep_n):
+def recorded_traffic(wl, sweep_n, mixed=False):
     """HBM bytes per sweep launch (average over the axes, weighted like the timing) from
-    the committed counter summary of this workload, or None when there is none or the
-    sweep kernels changed since it was taken."""
+    the committed counter summary of this workload, or None when there is none, it does
+    not cover the precision, or the sweep kernels changed since it was taken."""
     path = os.path.join(ROOT, "profiles", f"sweep_{wl.name}_hbm_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -83,7 +86,9 @@ def recorded_traffic(wl, sweep_n):
     from paper_2001_03477_amd.profsum import sweep_source_hash
     if rec is None or rec.get("source_hash") != sweep_source_hash():
         return None
-    per_axis = rec["bytes_per_launch"]
+    per_axis = rec.get("bytes_per_launch_mixed" if mixed else "bytes_per_launch")
+    if per_axis is None or any(per_axis[a] is None for a in range(wl.ndim)):
+        return None
     tot = sum(per_axis[a] * sweep_n[a] for a in range(wl.ndim))
     return float(tot / sweep_n.sum())
 
@@ -427,34 +432,83 @@ def diffusion_timing(pcvof, torch, wl, k_l, k_g, calls=5):
     return {"ms": float(np.median(times)), "k_l": k_l, "k_g": k_g, "dt": wl.dt, **info, "rel_tol": 1e-13}
 
 
-def cpu_baseline(wl, budget_s=15.0, max_side=128):
-    """The oracle on the host: whole steps of the workload until the budget is used (at
-    least one step). Domains larger than max_side per axis are sampled: the oracle
-    steps the leading max_side^3 sub-box of the same inputs (outflow at its sides)."""
+def _subbox(wl, z0, y0, x0, side):
+    """The inputs of the side^3 sub-box of the workload with corner (z0, y0, x0), as
+    contiguous arrays (fractions, energies, face velocities, mass flux)."""
+    sz, sy, sx = (min(side, n) for n in wl.shape)
+    zs, ys, xs = slice(z0, z0 + sz), slice(y0, y0 + sy), slice(x0, x0 + sx)
+    c = np.ascontiguousarray(wl.c[zs, ys, xs])
+    e = np.ascontiguousarray(wl.e[zs, ys, xs])
+    u = np.ascontiguousarray(wl.u[zs, ys, x0:x0 + sx + 1])
+    v = np.ascontiguousarray(wl.v[zs, y0:y0 + sy + 1, xs])
+    w = None if wl.w is None else np.ascontiguousarray(wl.w[z0:z0 + sz + 1, ys, xs])
+    md = None if wl.mdot is None else np.ascontiguousarray(wl.mdot[zs, ys, xs])
+    return c, e, u, v, w, md
+
+
+def _oracle_steps(job):
+    """Whole oracle steps of one sub-box until the budget is used (at least one step):
+    (cells, steps, seconds). Runs in a worker process of its own."""
     import oracle
-    nz, ny, nx = wl.shape
-    sz, sy, sx = min(nz, max_side), min(ny, max_side), min(nx, max_side)
-    sub = (sz, sy, sx) != (nz, ny, nx)
-    c, e = wl.c[:sz, :sy, :sx].copy(), wl.e[:sz, :sy, :sx].copy()
-    u = np.ascontiguousarray(wl.u[:sz, :sy, :sx + 1])
-    v = np.ascontiguousarray(wl.v[:sz, :sy + 1, :sx])
-    w = None if wl.w is None else np.ascontiguousarray(wl.w[:sz + 1, :sy, :sx])
-    md = None if wl.mdot is None else np.ascontiguousarray(wl.mdot[:sz, :sy, :sx])
-    bc = (1, 1, 1) if sub else wl.bc
-    cfg = oracle.Config(shape=(sz, sy, sx), h=wl.h, ndim=wl.ndim, bc=bc, cp_l=wl.cp_l,
-                        cp_g=wl.cp_g, rho_l=wl.rho_l, T_gamma=wl.T_gamma, normal=wl.normal)
+    c, e, u, v, w, md, cfg_kw, dt, scales, budget_s = job
+    cfg = oracle.Config(**cfg_kw)
     t0 = time.perf_counter()
     n = 0
     while True:
-        c, e, _ = oracle.step(cfg, c, e, u, v, w, md, wl.dt, wl.u_scale(n), n)
+        c, e, _ = oracle.step(cfg, c, e, u, v, w, md, dt, scales[n % len(scales)], n)
         n += 1
         el = time.perf_counter() - t0
         if el >= budget_s:
             break
-    what = (f"the leading {sx}x{sy}x{sz} sub-box of the {wl.name} workload" if sub
-            else f"the {wl.name} workload")
-    return {"value": sx * sy * sz * n / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} full step(s) of {what}, single-threaded, {el:.1f} s"}
+    return int(c.size), n, el
+
+
+def _host_cpu():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(wl, budget_s=10.0, side=128, max_workers=16):
+    """The oracle on the host, two runs on the same inputs: one thread on the leading
+    side^3 sub-box of the workload (the whole workload if it is smaller), and one
+    process per available core (at most max_workers, the host share of one GPU), each
+    stepping its own side^3 sub-box. Sub-boxes of a larger domain have outflow sides;
+    they are independent, so the all-core rate is the sum of the workers' rates."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    model, avail = _host_cpu()
+    nz, ny, nx = wl.shape
+    sub = max(wl.shape) > side
+    cfg_kw = dict(shape=tuple(min(side, n) for n in wl.shape), h=wl.h, ndim=wl.ndim,
+                  bc=(1, 1, 1) if sub else tuple(wl.bc), cp_l=wl.cp_l, cp_g=wl.cp_g, rho_l=wl.rho_l,
+                  T_gamma=wl.T_gamma, normal=wl.normal)
+    scales = [wl.u_scale(k) for k in range(64)]
+    corners = [(z, y, x) for z in range(0, nz, side) for y in range(0, ny, side) for x in range(0, nx, side)
+               if z + side <= max(nz, side) and y + side <= max(ny, side) and x + side <= max(nx, side)]
+    one = _oracle_steps((*_subbox(wl, *corners[0], side), cfg_kw, wl.dt, scales, budget_s))
+    nw = max(1, min(avail, max_workers, len(corners)))
+    jobs = [(*_subbox(wl, *corners[k % len(corners)], side), cfg_kw, wl.dt, scales, budget_s) for k in range(nw)]
+    with cf.ProcessPoolExecutor(max_workers=nw, mp_context=mp.get_context("spawn")) as ex:
+        res = list(ex.map(_oracle_steps, jobs))
+    rate1 = one[0] * one[1] / one[2]
+    rate_n = sum(cells * n / el for cells, n, el in res)
+    shape = "x".join(str(v) for v in cfg_kw["shape"][::-1])
+    what = f"{shape} sub-box(es) of the {wl.name} workload (outflow sides)" if sub else f"the {wl.name} workload"
+    return {"value": rate_n, "unit": "cell-updates/s", "cores": nw, "kind": "oracle",
+            "sample": (f"{sum(n for _, n, _ in res)} full steps over {nw} independent {what}, one process per "
+                       f"core, about {budget_s:.0f} s each"),
+            "cpu_model": model, "cores_available": avail,
+            "single_thread": {"value": rate1, "cores": 1, "steps": one[1], "seconds": round(one[2], 2),
+                              "sample": (f"{one[1]} full steps of the leading {shape} sub-box" if sub
+                                         else f"{one[1]} full steps of the {wl.name} workload")}}
 
 
 def sweep_duration(wl, r, steps, mixed=False):
@@ -471,67 +525,26 @@ def sweep_duration(wl, r, steps, mixed=False):
             "event_pairs_ms": pairs, "timed_region_ms": region, "bytes_per_launch": per_launch}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="leveque128")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--fp64-only", action="store_true", help="skip the mixed-precision run")
-    ap.add_argument("--no-ablation", action="store_true",
-                    help="skip the energy-flux and split-scheme ablations")
-    ap.add_argument("--calibration-copy-mib", type=int, default=0,
-                    help="first copy this many MiB device to device, a kernel of known traffic "
-                         "for scaling the HBM byte counters of a profiler run")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: the advection step of one domain is measured on "
-              "one MI355X; sharding over several GPUs is designed but not implemented",
-              file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    from paper_2001_03477_amd import pcvof
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    if args.calibration_copy_mib > 0:
-        n = args.calibration_copy_mib * (1 << 20) // 8
-        src = torch.ones(n, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    copy_gbs = None if args.calibration_copy_mib > 0 else copy_bandwidth(torch)
-    if args.workload == "batch64":
-        bench_batch(args, pcvof, torch)
-        return
-    wl = workload(args.workload)
+def bench_workload(args, pcvof, torch, wl, copy_gbs, mixed=True):
+    """FP64 (and mixed-precision) runs of one single-domain workload: the fields of the
+    JSON line for it."""
     scales = np.array([wl.u_scale(k) for k in range(args.warmup + 2 * args.steps)])
     r64 = run(pcvof, torch, wl, "fp64", args.steps, args.warmup, scales)
     c64 = r64.pop("c_final")
     torch.cuda.synchronize()
-    rmx = run(pcvof, torch, wl, "mixed", args.steps, args.warmup, scales) if not args.fp64_only else None
+    rmx = run(pcvof, torch, wl, "mixed", args.steps, args.warmup, scales) if mixed else None
     total_ms, sweep_ms, sweep_n, prof = r64["total_ms"], r64["sweep_ms"], r64["sweep_n"], r64["prof"]
     dur = sweep_duration(wl, r64, args.steps)
     avg_sweep_ms = dur["avg_launch_ms"]
     achieved = dur["bytes_per_launch"] / (avg_sweep_ms * 1e-3) / 1e9
     value = wl.ncells * args.steps / (total_ms * 1e-3)
     out = {
-        "metric": METRIC,
         "value": value,
         "unit": "cell-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
         "ms_per_step": total_ms / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
         "config": {"workload": wl.name, "grid": list(wl.shape[::-1]), "ndim": wl.ndim,
-                   "bc": "outflow" if wl.bc[0] else "periodic", "cfl": round(W_max_face(wl) * wl.dt / wl.h, 4), "normal": "MYC",
-                   "mdot": "on" if wl.mdot is not None else "off", "precision": "fp64",
+                   "bc": "outflow" if wl.bc[0] else "periodic", "cfl": round(W_max_face(wl) * wl.dt / wl.h, 4),
+                   "normal": "MYC", "mdot": "on" if wl.mdot is not None else "off", "precision": "fp64",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(wl, sweep_n),
@@ -558,20 +571,95 @@ def main():
             "per_axis_ms": [float(t / n) for t, n in zip(rmx["sweep_ms"], rmx["sweep_n"])],
             "roofline": {"bound": "hbm", "achieved": mx_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": mx_achieved / HBM_PEAK_GBS, "duration_from": mdur["source"],
+                         "traffic": recorded_traffic(wl, rmx["sweep_n"], mixed=True),
                          "bytes_per_cell": SWEEP_BYTES_PER_CELL_MIXED + SWEEP_BYTES_PER_FACE_MIXED},
             "volume_drift": rmx["volume_drift"],
             "drift_net_of_reported_terms": rmx["unexplained"],
             "c_vs_fp64": {"max_abs": float(dc.max()), "l1_rel": float(dc.sum() / np.abs(c64).sum())},
         }
-    if not args.no_ablation and args.workload == "leveque128":
+    return out
+
+
+# extra single-domain workloads of the default line (name for workload(), key)
+EXTRA_WORKLOADS = (("leveque128", "leveque3d_128"), ("bubble256", "bubble3d_256"))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="droplets512")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp64-only", action="store_true", help="skip the mixed-precision run")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the energy-flux and split-scheme ablations")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the extra workloads (128^3 LeVeque, 256^3 bubble) of the default line")
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="first copy this many MiB device to device, a kernel of known traffic "
+                         "for scaling the HBM byte counters of a profiler run")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the advection step of one domain is measured on "
+              "one MI355X; sharding over several GPUs is designed but not implemented",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2001_03477_amd import pcvof
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibration_copy_mib > 0:
+        n = args.calibration_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    copy_gbs = None if args.calibration_copy_mib > 0 else copy_bandwidth(torch)
+    if args.workload == "batch64":
+        bench_batch(args, pcvof, torch)
+        return
+    wl = workload(args.workload)
+    print(f"bench: {wl.name}, {args.warmup} + {args.steps} steps", file=sys.stderr, flush=True)
+    res = bench_workload(args, pcvof, torch, wl, copy_gbs, mixed=not args.fp64_only)
+    out = {"metric": METRIC, "value": res.pop("value"), "unit": res.pop("unit"), "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": res.pop("ms_per_step"),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic", **res}
+    default_line = args.workload == "droplets512"
+    if default_line and not args.no_extra:
+        extra = {}
+        for name, key in EXTRA_WORKLOADS:
+            xw = workload(name)
+            print(f"bench: extra workload {xw.name}", file=sys.stderr, flush=True)
+            r = bench_workload(args, pcvof, torch, xw, copy_gbs, mixed=not args.fp64_only)
+            keep = {k: r[k] for k in ("value", "unit", "ms_per_step", "config", "kernel_ms_per_step",
+                                      "volume_drift", "drift_net_of_reported_terms")}
+            keep["roofline"] = {k: r["roofline"][k] for k in ("achieved", "frac", "traffic", "avg_launch_ms",
+                                                              "per_axis_ms")}
+            if "mixed" in r:
+                keep["mixed"] = {k: r["mixed"][k] for k in ("value", "ms_per_step", "speedup_vs_fp64",
+                                                            "volume_drift", "c_vs_fp64")}
+            if name == "bubble256":
+                # vapour density and conductivities of the paper's superheated-bubble case
+                keep["extension"] = extension_timing(pcvof, torch, xw, 0.25)
+                keep["diffusion"] = diffusion_timing(pcvof, torch, xw, 0.07, 0.007)
+            extra[key] = keep
+            if name == "leveque128" and not args.no_ablation:
+                print("bench: ablations", file=sys.stderr, flush=True)
+                out["energy_flux_ablation"] = energy_flux_ablation(pcvof, torch)
+                out["split_ablation"] = split_ablation(pcvof, torch, xw)
+            del xw
+        out["other_workloads"] = extra
+    elif args.workload == "leveque128" and not args.no_ablation:
         out["energy_flux_ablation"] = energy_flux_ablation(pcvof, torch)
         out["split_ablation"] = split_ablation(pcvof, torch, wl)
     if args.workload == "bubble256":
-        # vapour density of the paper's superheated-bubble case (its liquid one is rho_l)
         out["extension"] = extension_timing(pcvof, torch, wl, 0.25)
-        # conductivities of the same case
         out["diffusion"] = diffusion_timing(pcvof, torch, wl, 0.07, 0.007)
     if not args.no_cpu_baseline:
+        print("bench: oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)
 

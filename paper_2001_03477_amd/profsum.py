@@ -30,6 +30,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SWEEP_SOURCES = ("sweep.hip", "common.h", "geom.h", "geom32.h", "kernels.h")
 SWEEP_KERNELS = ("k_sweep_x", "k_sweep_t<1>", "k_sweep_t<2>")  # axis order
+SWEEP_KERNELS_MIXED = ("k_sweep_x_mixed", "k_sweep_t_mixed<1>", "k_sweep_t_mixed<2>")
 
 
 def sweep_source_hash():
@@ -46,9 +47,9 @@ def short_name(name):
     return n.split("(")[0]
 
 
-def sweep_axis(name):
+def sweep_axis(name, kernels=SWEEP_KERNELS):
     n = short_name(name)
-    for a, k in enumerate(SWEEP_KERNELS):
+    for a, k in enumerate(kernels):
         if n == k:
             return a
     return None
@@ -94,39 +95,56 @@ def calib_value(rows, counter):
     raise SystemExit(f"no copy kernel with {counter} in the run")
 
 
+def _sweep_traffic(frows, wrows, kernels, f_fetch, f_write):
+    """Per axis: (launches, mean FETCH KiB, mean WRITE KiB, read bytes, write bytes) of
+    the sweep kernels named in kernels, or None for an axis without dispatches."""
+    per = {a: {"fetch": [], "write": []} for a in range(3)}
+    for n, c in frows:
+        a = sweep_axis(n, kernels)
+        if a is not None and "FETCH_SIZE" in c:
+            per[a]["fetch"].append(c["FETCH_SIZE"])
+    for n, c in wrows:
+        a = sweep_axis(n, kernels)
+        if a is not None and "WRITE_SIZE" in c:
+            per[a]["write"].append(c["WRITE_SIZE"])
+    out = []
+    for a in range(3):
+        fe, wr = per[a]["fetch"], per[a]["write"]
+        if not fe or not wr:
+            out.append(None)
+            continue
+        fk, wk = sum(fe) / len(fe), sum(wr) / len(wr)
+        out.append((len(fe), fk, wk, fk * 1024 * f_fetch, wk * 1024 * f_write))
+    return out
+
+
 def traffic_summary(fetch_db, write_db, calib_mib, workload, cmd_fetch, cmd_write):
     frows, wrows = counter_rows(fetch_db), counter_rows(write_db)
     true_bytes = calib_mib * (1 << 20)
     f_fetch = true_bytes / (calib_value(frows, "FETCH_SIZE") * 1024.0)
     f_write = true_bytes / (calib_value(wrows, "WRITE_SIZE") * 1024.0)
-    per = {a: {"fetch": [], "write": []} for a in range(3)}
-    for n, c in frows:
-        a = sweep_axis(n)
-        if a is not None and "FETCH_SIZE" in c:
-            per[a]["fetch"].append(c["FETCH_SIZE"])
-    for n, c in wrows:
-        a = sweep_axis(n)
-        if a is not None and "WRITE_SIZE" in c:
-            per[a]["write"].append(c["WRITE_SIZE"])
     lines = [f"fetch run: {cmd_fetch}", f"write run: {cmd_write}", "",
              f"calibration copy: {calib_mib} MiB read + {calib_mib} MiB written",
              f"scale factors (true bytes / counter bytes): FETCH_SIZE {f_fetch:.4f}, "
              f"WRITE_SIZE {f_write:.4f}", "",
-             f"{'kernel':16s} {'n':>3s} {'FETCH_KiB':>12s} {'WRITE_KiB':>12s} {'read_MB':>10s} "
+             f"{'kernel':20s} {'n':>3s} {'FETCH_KiB':>12s} {'WRITE_KiB':>12s} {'read_MB':>10s} "
              f"{'write_MB':>10s} {'total_MB':>10s}"]
-    bytes_per_launch = []
-    for a in range(3):
-        fe, wr = per[a]["fetch"], per[a]["write"]
-        if not fe or not wr:
-            bytes_per_launch.append(None)
+    rec = {"workload": workload}
+    for key, kernels in (("bytes_per_launch", SWEEP_KERNELS), ("bytes_per_launch_mixed", SWEEP_KERNELS_MIXED)):
+        rows = _sweep_traffic(frows, wrows, kernels, f_fetch, f_write)
+        if all(r is None for r in rows):
             continue
-        fk, wk = sum(fe) / len(fe), sum(wr) / len(wr)
-        rb, wb = fk * 1024 * f_fetch, wk * 1024 * f_write
-        bytes_per_launch.append(rb + wb)
-        lines.append(f"{SWEEP_KERNELS[a]:16s} {len(fe):3d} {fk:12.0f} {wk:12.0f} {rb / 1e6:10.2f} "
-                     f"{wb / 1e6:10.2f} {(rb + wb) / 1e6:10.2f}")
-    rec = {"workload": workload, "bytes_per_launch": bytes_per_launch,
-           "fetch_scale": f_fetch, "write_scale": f_write, "source_hash": sweep_source_hash()}
+        bpl = []
+        for a, r in enumerate(rows):
+            if r is None:
+                bpl.append(None)
+                continue
+            n, fk, wk, rb, wb = r
+            bpl.append(rb + wb)
+            lines.append(f"{kernels[a]:20s} {n:3d} {fk:12.0f} {wk:12.0f} {rb / 1e6:10.2f} "
+                         f"{wb / 1e6:10.2f} {(rb + wb) / 1e6:10.2f}")
+        rec[key] = bpl
+    rec.update({"fetch_scale": f_fetch, "write_scale": f_write, "source_hash": sweep_source_hash()})
     lines += ["", "traffic_json: " + json.dumps(rec)]
     return "\n".join(lines)
 
