@@ -127,23 +127,37 @@ double or_area(const double m_in[3], double alpha) {
     return cut / sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
 }
 
-/* Plane constant for a given volume fraction (section 3.2: "alpha is obtained by
-   geometrical volume calculations"): bisection on the monotone volume function
-   over the admissible range of alpha until the bracket cannot shrink further. */
-double or_alpha(const double m_in[3], double c) {
-    double m[3];
-    double shift = reflect(m_in, 0.0, m); /* alpha_reflected = alpha + shift */
+/* Reflected plane constant a in [0, S] with V(a) = v (reflected frame, m >= 0):
+   bisection on the monotone volume function until the bracket cannot shrink
+   further. */
+static double bisect_alpha(const double m[3], double v) {
     double lo = 0.0, hi = m[0] + m[1] + m[2];
-    if (c <= 0.0) return lo - shift;
-    if (c >= 1.0) return hi - shift;
     double mid = 0.5 * (lo + hi);
     for (int it = 0; it < 200; ++it) {
         mid = 0.5 * (lo + hi);
         if (mid <= lo || mid >= hi) break;
-        if (or_volume(m, mid) < c) lo = mid;
+        if (or_volume(m, mid) < v) lo = mid;
         else hi = mid;
     }
-    return mid - shift;
+    return mid;
+}
+
+/* Plane constant for a given volume fraction (section 3.2: "alpha is obtained by
+   geometrical volume calculations"; the inverse of c = f(alpha, m) of section 3.3.2).
+   The cube is centrally symmetric, so V(a) + V(S - a) = 1 in the reflected frame:
+   above one half the complementary volume 1 - c (exact in floating point) is
+   inverted instead, where the volume function is small and evaluated to full
+   relative precision, and the plane is reflected, a = S - a(1 - c). Inverting V = c
+   directly near c = 1 would resolve a only to the absolute rounding of V (about
+   1e-16) divided by its slope, the vanishing area of a corner plane. */
+double or_alpha(const double m_in[3], double c) {
+    double m[3];
+    double shift = reflect(m_in, 0.0, m); /* alpha_reflected = alpha + shift */
+    double S = m[0] + m[1] + m[2];
+    if (c <= 0.0) return 0.0 - shift;
+    if (c >= 1.0) return S - shift;
+    if (c > 0.5) return (S - bisect_alpha(m, 1.0 - c)) - shift;
+    return bisect_alpha(m, c) - shift;
 }
 
 /* ------------------------------------------------------------------------- */

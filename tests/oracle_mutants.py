@@ -45,3 +45,19 @@ def normal_fn(lib):
         return out
 
     return normal
+
+
+def alpha_n_fn(lib):
+    """or_alpha of a (mutant) oracle library over arrays: alpha_n(m (n, 3), c (n,))."""
+    lib.or_alpha.restype = C.c_double
+    lib.or_alpha.argtypes = [_dp, C.c_double]
+
+    def alpha_n(m, c):
+        m = np.ascontiguousarray(np.asarray(m, dtype=np.float64))
+        out = np.empty(len(c))
+        for i in range(len(c)):
+            row = np.ascontiguousarray(m[i])
+            out[i] = lib.or_alpha(row.ctypes.data_as(_dp), float(c[i]))
+        return out
+
+    return alpha_n

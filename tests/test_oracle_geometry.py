@@ -131,6 +131,50 @@ def test_alpha_round_trip(orc):
     assert np.all(np.abs(a1 - a0) <= 1e-15 / np.maximum(slope, 1e-3) + 1e-15)
 
 
+def _corner_alpha_exact(m, v):
+    """Plane constant of an interface cutting off the corner of volume v (tetrahedral
+    regime of the reflected frame), to 50 digits: a^3 / (6 m1 m2 m3) = v."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 50
+    mr = [abs(Decimal(float(x))) for x in m]
+    a = (Decimal(6) * mr[0] * mr[1] * mr[2] * Decimal(float(v))) ** (Decimal(1) / Decimal(3))
+    return a, sum(mr), sum(-Decimal(float(x)) for x in m if x < 0)
+
+
+def _check_alpha_near_empty_and_full(alpha_n):
+    """alpha to rounding of alpha itself (not of the volume) when the interface cuts off
+    a small corner: c = v (liquid corner) and c = 1 - v (gas corner), v in [1e-14, 1e-6]."""
+    rng = np.random.default_rng(31)
+    m = rng.uniform(0.15, 1.0, size=(300, 3)) * rng.choice([-1.0, 1.0], size=(300, 3))
+    m /= np.abs(m).sum(axis=1, keepdims=True)
+    v = 10.0 ** rng.uniform(-14, -6, 300)
+    for full in (False, True):
+        c = 1.0 - v if full else v
+        got = alpha_n(m, c)
+        for i in range(len(v)):
+            # 1 - c is exact for c in [1/2, 1]: the gas corner has exactly the volume 1 - c
+            vv = (1.0 - c[i]) if full else c[i]
+            a, S, shift = _corner_alpha_exact(m[i], vv)
+            want = (S - a if full else a) - shift
+            assert abs(got[i] - float(want)) <= 4.5e-16, (full, m[i], v[i], got[i], float(want))
+
+
+def test_alpha_near_empty_and_full_cells(orc):
+    """The plane constant of a nearly empty or nearly full cell is fixed exactly by the
+    corner volume; step 2 moves such planes by a sizeable fraction of a cell, so an error
+    in alpha there is carried into the new fraction at full weight."""
+    _check_alpha_near_empty_and_full(orc.alpha_n)
+
+
+def test_alpha_pin_catches_direct_inversion_near_full(tmp_path):
+    """A copy of the oracle that inverts V = c directly also above one half (no
+    complement) misses the corner's plane by about 1e-16 over the corner's area."""
+    import oracle_mutants
+    lib = oracle_mutants.build(tmp_path, [("    if (c > 0.5) return (S - bisect_alpha(m, 1.0 - c)) - shift;\n", "")])
+    with pytest.raises(AssertionError):
+        _check_alpha_near_empty_and_full(oracle_mutants.alpha_n_fn(lib))
+
+
 def test_slab_bounds_additivity_and_planes(orc):
     rng = np.random.default_rng(21)
     for _ in range(400):
