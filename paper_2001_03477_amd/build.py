@@ -15,18 +15,23 @@ ARCH = os.environ.get("PCVOF_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=fast", "-Wall",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["sweep.hip", "kernels.hip", "massflux.hip", "ext.hip", "diffusion.hip", "capi.cpp"]
+SOURCES = ["sweep.hip", "phase.hip", "kernels.hip", "massflux.hip", "ext.hip", "diffusion.hip", "capi.cpp"]
 
 
-def build(verbose: bool = False) -> str:
-    objs = []
-    for src in SOURCES:
+def build(verbose: bool = False, jobs: int = 8) -> str:
+    """Compiles every source (up to `jobs` at a time), then links libpcvof.so."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def compile_one(src):
         obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
         cmd = [HIPCC, f"--offload-arch={ARCH}", *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        objs.append(obj)
+        return obj
+
+    with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

@@ -155,7 +155,9 @@ struct pcvof_handle {
     Layout L;
     char* ws;
     hipStream_t stream;
-    int cur;                 // index of the current state buffer (fractions, energies, mask)
+    int cur;                 // index of the current fraction and energy buffers
+    int mcur;                // index of the current mixed-cell mask (step 2 updates the
+                             // fractions in place but writes a new mask)
     int mask_cpw;            // cells per word of the current mask
     bool has_vof, has_energy, has_vel, has_mdot;
     double umax[3];          // max |u_f| per axis, from set_velocity
@@ -165,6 +167,7 @@ struct pcvof_handle {
     int sweeps_done;
     int nb[pcv::kSlots];  // partial rows written per slot (0: stage did not run)
     int last_slot;
+    int last_sweep;          // slot of the step's last sweep (-1: none yet)
     double step_cfl;
     // kernel timing
     int prof_mask;           // kernel classes timed (bit k = class k)
@@ -254,8 +257,15 @@ void fill_stats(const pcvof_handle* h, const double* cs, pcvof_stats* stats) {
     for (int sl = 0; sl < 3; ++sl)
         if (h->nb[sl])
             for (int k = 0; k < 6; ++k) q[k] += cs[sl * W + k];
-    stats->vol = cs[h->last_slot * W + 6] * hv;
-    stats->energy = cs[h->last_slot * W + 7] * hv;
+    // totals after the last sweep, plus the changes of step 2 when it ran (step 2
+    // changes only the interface cells, so it sums those changes, not the fields)
+    double tv = cs[h->last_sweep * W + 6], te = cs[h->last_sweep * W + 7];
+    if (h->nb[3]) {
+        tv += cs[3 * W + 0];
+        te += cs[3 * W + 1];
+    }
+    stats->vol = tv * hv;
+    stats->energy = te * hv;
     stats->vol_clip = q[0] * hv;
     stats->energy_clip = q[1] * hv;
     stats->vol_bnd_out = q[2] * hv;
@@ -327,6 +337,7 @@ int pcvof_create(const pcvof_grid* grid, const pcvof_params* params, void* d_wor
     h->ws = (char*)d_workspace;
     h->stream = (hipStream_t)hip_stream;
     h->cur = 0;
+    h->mcur = 0;
     h->mask_cpw = pcv::kMaskCpw;
     h->batch_view = false;
     h->has_vof = h->has_energy = h->has_vel = h->has_mdot = false;
@@ -365,7 +376,7 @@ int pcvof_set_vof(pcvof_handle* h, const double* c, int mem) {
     if (int r = check_field(h, h->c(h->cur), h->d.ncell, 1, &f)) return r;
     if (f & 1u) return fail(PCVOF_ERR_NONFINITE, "volume fraction has NaN or Inf");
     if (f & 2u) return fail(PCVOF_ERR_BOUNDS, "volume fraction outside [0,1]");
-    HIP_TRY(pcv::launch_classify(h->d, h->c(h->cur), h->mask(h->cur), h->stream));
+    HIP_TRY(pcv::launch_classify(h->d, h->c(h->cur), h->mask(h->mcur), h->stream));
     h->mask_cpw = pcv::kMaskCpw;
     h->has_vof = true;
     return PCVOF_OK;
@@ -452,6 +463,7 @@ int pcvof_begin_step(pcvof_handle* h) {
     h->sweeps_done = 0;
     for (int k = 0; k < pcv::kSlots; ++k) h->nb[k] = 0;
     h->last_slot = -1;
+    h->last_sweep = -1;
     h->step_cfl = 0.0;
     return PCVOF_OK;
 }
@@ -473,9 +485,9 @@ int pcvof_sweep(pcvof_handle* h, int axis, double dt, double u_scale) {
     pcv::SweepIO io;
     io.c = h->c(h->cur);
     io.e = h->e(h->cur);
-    io.mask = h->mask(h->cur);
+    io.mask = h->mask(h->mcur);
     io.mask_cpw = h->mask_cpw;
-    io.mask_out = h->mask(nxt);
+    io.mask_out = h->mask(1 - h->mcur);
     io.cc = h->cc();
     io.ec = h->ec();
     io.first = h->first_pending ? 1 : 0;
@@ -494,9 +506,11 @@ int pcvof_sweep(pcvof_handle* h, int axis, double dt, double u_scale) {
     HIP_TRY(pcv::launch_sweep(h->d, axis, io, h->stream));
     h->first_pending = false;
     h->cur = nxt;
+    h->mcur = 1 - h->mcur;
     h->mask_cpw = axis == 0 ? pcv::kMaskCpwX : pcv::kMaskCpw;
     h->sweeps_done++;
     h->last_slot = slot;
+    h->last_sweep = slot;
     return PCVOF_OK;
 }
 
@@ -507,27 +521,24 @@ int pcvof_phase_change(pcvof_handle* h, double dt) {
     if (!isfinite(dt) || !(dt >= 0.0)) return fail(PCVOF_ERR_ARG, "bad dt");
     const int slot = 3;
     if (h->nb[slot]) return fail(PCVOF_ERR_STATE, "phase_change called twice in one step");
-    const int nxt = 1 - h->cur;
+    if (h->sweeps_done == 0) return fail(PCVOF_ERR_STATE, "phase_change before the sweeps of the step");
     pcv::PhaseIO io;
     io.c = h->c(h->cur);
     io.e = h->e(h->cur);
-    io.mask = h->mask(h->cur);
+    io.mask = h->mask(h->mcur);
     io.mask_cpw = h->mask_cpw;
-    io.mask_out = h->mask(nxt);
+    io.mask_out = h->mask(1 - h->mcur);
     io.mdot = h->mdot();
     io.dt = dt;
     io.h = h->g.h;
     io.rec = h->rec();
-    io.c_out = h->c(nxt);
-    io.e_out = h->e(nxt);
     io.part = h->part(slot);
     io.part_stride = h->L.maxb;
     io.nblocks = &h->nb[slot];
     const int ps = prof_begin(h, PCVOF_PROF_PHASE);
     HIP_TRY(pcv::launch_phase(h->d, io, h->stream));
     prof_end(h, PCVOF_PROF_PHASE, ps);
-    h->cur = nxt;
-    h->mask_cpw = pcv::kMaskCpw;
+    h->mcur = 1 - h->mcur;  // fractions and energies stay in their buffers
     h->last_slot = slot;
     return PCVOF_OK;
 }
@@ -662,7 +673,7 @@ int pcvof_compute_mass_flux(pcvof_handle* h, double k_l, double k_g, double h_fg
     pcv::MassFluxIO io;
     io.c = h->c(h->cur);
     io.e = h->e(h->cur);
-    io.mask = h->mask(h->cur);
+    io.mask = h->mask(h->mcur);
     io.mask_cpw = h->mask_cpw;
     io.plane = h->rec();
     io.q = h->fgeo();
@@ -966,15 +977,16 @@ int batch_build_tiles(pcvof_batch* b) {
     return PCVOF_OK;
 }
 
-// The sweep arguments of domain i for sweep s of a step starting in state (cur, cpw).
-pcv::SweepIO batch_sweep_io(pcvof_batch* b, int i, int s, int axis, int cur, int cpw, double dt) {
+// The sweep arguments of domain i for sweep s of a step starting in state (cur, mcur,
+// cpw): fraction and energy buffers, mask buffer and its cells per word.
+pcv::SweepIO batch_sweep_io(pcvof_batch* b, int i, int s, int axis, int cur, int mcur, int cpw, double dt) {
     pcvof_handle* h = b->dom[i];
     pcv::SweepIO io;
     io.c = h->c(cur);
     io.e = h->e(cur);
-    io.mask = h->mask(cur);
+    io.mask = h->mask(mcur);
     io.mask_cpw = cpw;
-    io.mask_out = h->mask(1 - cur);
+    io.mask_out = h->mask(1 - mcur);
     io.cc = h->cc();
     io.ec = h->ec();
     io.first = s == 0 ? 1 : 0;
@@ -996,6 +1008,7 @@ int batch_slot_for_step(pcvof_batch* b, const double* dt, int* out) {
     key.push_back(b->step % b->ndim);
     for (auto* h : b->dom) {
         key.push_back(h->cur);
+        key.push_back(h->mcur);
         key.push_back(h->mask_cpw);
         key.push_back(h->has_mdot ? 1 : 0);
     }
@@ -1018,17 +1031,18 @@ int batch_slot_for_step(pcvof_batch* b, const double* dt, int* out) {
     std::vector<pcv::ColsumArgs> cs(b->nd);
     for (int i = 0; i < b->nd; ++i) {
         pcvof_handle* h = b->dom[i];
-        int cur = h->cur, cpw = h->mask_cpw;
+        int cur = h->cur, mcur = h->mcur, cpw = h->mask_cpw;
         pcv::ColsumArgs c{h->part(0), h->L.maxb, {0, 0, 0, 0}, h->colsum()};
         for (int s = 0; s < b->ndim; ++s) {
             const int axis = (int)((b->step + s) % b->ndim);
-            const pcv::SweepIO io = batch_sweep_io(b, i, s, axis, cur, cpw, dt[i]);
+            const pcv::SweepIO io = batch_sweep_io(b, i, s, axis, cur, mcur, cpw, dt[i]);
             pcv::sweep_args_pack(io, args.data() + ((size_t)s * b->nd + i) * ab);
             c.nb[s] = b->dom_tiles[axis][i];
             cur = 1 - cur;
+            mcur = 1 - mcur;
             cpw = axis == 0 ? pcv::kMaskCpwX : pcv::kMaskCpw;
         }
-        if (h->has_mdot) c.nb[3] = pcv::cell_launch(h->d).nblocks;
+        if (h->has_mdot) c.nb[3] = pcv::phase_launch(h->d).nblocks;
         cs[i] = c;
     }
     HIP_TRY(hipMemcpy(b->args(k, 0), args.data(), args.size(), hipMemcpyHostToDevice));
@@ -1050,20 +1064,20 @@ int batch_enqueue(pcvof_batch* b, int k, const double* dt, hipStream_t s_) {
     for (int i = 0; i < b->nd; ++i) {
         pcvof_handle* h = b->dom[i];
         if (!h->has_mdot) continue;
-        const int cur = b->ndim % 2 ? 1 - h->cur : h->cur;  // state after the sweeps
+        // state after the sweeps
+        const int cur = b->ndim % 2 ? 1 - h->cur : h->cur;
+        const int mcur = b->ndim % 2 ? 1 - h->mcur : h->mcur;
         const int last_axis = (int)((b->step + b->ndim - 1) % b->ndim);
         pcv::PhaseIO io;
         io.c = h->c(cur);
         io.e = h->e(cur);
-        io.mask = h->mask(cur);
+        io.mask = h->mask(mcur);
         io.mask_cpw = last_axis == 0 ? pcv::kMaskCpwX : pcv::kMaskCpw;
-        io.mask_out = h->mask(1 - cur);
+        io.mask_out = h->mask(1 - mcur);
         io.mdot = h->mdot();
         io.dt = dt[i];
         io.h = h->g.h;
         io.rec = h->rec();
-        io.c_out = h->c(1 - cur);
-        io.e_out = h->e(1 - cur);
         io.part = h->part(3);
         io.part_stride = h->L.maxb;
         int nb = 0;
@@ -1207,6 +1221,7 @@ int pcvof_batch_advect_step(pcvof_batch* b, const double* dt, int use_graph, pcv
             const int axis = (int)((b->step + s) % b->ndim);
             h->nb[s] = b->dom_tiles[axis][i];
             h->cur = 1 - h->cur;
+            h->mcur = 1 - h->mcur;
             h->mask_cpw = axis == 0 ? pcv::kMaskCpwX : pcv::kMaskCpw;
             const double cfl = h->umax[axis] * dt[i] / h->g.h;
             if (cfl > h->step_cfl) h->step_cfl = cfl;
@@ -1214,10 +1229,10 @@ int pcvof_batch_advect_step(pcvof_batch* b, const double* dt, int use_graph, pcv
         for (int s = b->ndim; s < 3; ++s) h->nb[s] = 0;
         h->nb[3] = 0;
         h->last_slot = b->ndim - 1;
+        h->last_sweep = b->ndim - 1;
         if (h->has_mdot) {
-            h->nb[3] = pcv::cell_launch(h->d).nblocks;
-            h->cur = 1 - h->cur;
-            h->mask_cpw = pcv::kMaskCpw;
+            h->nb[3] = pcv::phase_launch(h->d).nblocks;
+            h->mcur = 1 - h->mcur;  // step 2: fractions in place, new mask
             h->last_slot = 3;
         }
         h->step++;
@@ -1287,7 +1302,7 @@ int pcvof_batch_autotune(pcvof_batch* b, const double* dt, int reps, int* chosen
             // a sweep of the current state into the other buffers (state not committed)
             for (int i = 0; i < b->nd; ++i) {
                 pcvof_handle* h = b->dom[i];
-                pcv::SweepIO io = batch_sweep_io(b, i, 0, axis, h->cur, h->mask_cpw, dt[i]);
+                pcv::SweepIO io = batch_sweep_io(b, i, 0, axis, h->cur, h->mcur, h->mask_cpw, dt[i]);
                 io.first = 1;
                 pcv::sweep_args_pack(io, args.data() + (size_t)i * ab);
             }

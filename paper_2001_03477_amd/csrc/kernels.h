@@ -27,7 +27,8 @@ constexpr int kMaskCpw = 64;
 
 // Per-block partial sums written by every stage kernel: 8 doubles per block.
 // Sweeps: clip_v, clip_e, bnd_v, bnd_e, src_v, src_e, tot_v, tot_e.
-// Phase change: phase_v, phase_e, 0, 0, 0, 0, tot_v, tot_e.
+// Phase change: phase_v, phase_e, 0, 0, 0, 0, 0, 0 (the step's totals are the last
+// sweep's plus these changes).
 constexpr int kPartialWidth = 8;
 constexpr int kSlots = 4;  // 3 sweeps + phase change
 
@@ -89,21 +90,21 @@ int max_chunk();
 int min_chunk();
 
 struct PhaseIO {
-    const double* c;
-    const double* e;
+    double* c;                 // updated in place
+    double* e;                 // updated in place
     const uint64_t* mask;      // mixed cells of c, cells per word mask_cpw
     int mask_cpw;
-    uint64_t* mask_out;        // mixed cells of c_out (cpw kMaskCpw)
+    uint64_t* mask_out;        // mixed cells after the step (same layout as mask)
     const double* mdot;
     double dt, h;
     double* rec;
-    double* c_out;
-    double* e_out;
-    double* part;
+    double* part;              // quantity 0: sum of Delta c, 1: sum of Delta e (per block)
     long part_stride;
-    int* nblocks;
+    int* nblocks;              // out: blocks (partial rows); may be null
 };
-// Step 2: reconstruction of the moving cells, then the shift of every cell.
+// Step 2: reconstruction of the moving cells, then the shift of the interface cells,
+// in place, one lane per mask word.
+Launch phase_launch(const Dom& d);
 hipError_t launch_phase(const Dom& d, const PhaseIO& io, hipStream_t s);
 
 // colsum[slot * 8 + q] = sum over the nb[slot] blocks of quantity q of slot.

@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <string.h>
 
+#include <algorithm>
+
 #include <type_traits>
 
 #include "common.h"
@@ -715,150 +717,6 @@ k_sweep_t_batch_mixed(const Dom* doms, const SweepArgs* args, const BatchTile* t
     sweep_t_tiles<AX, true>(doms, args, tiles, ntiles);
 }
 
-// Step 2, first pass (section 3.3.2), over every mixed cell of c~ with a non-zero mass
-// flux: the reconstruction and the moved plane constant, rec = (m, alpha~, alpha*)
-// with alpha* = alpha~ + |m|_2 Delta d and Delta d = -(m''/rho_l) dt / h.
-__global__ void __launch_bounds__(256)
-k_phase_recon(Dom d, const double* __restrict__ c, const uint64_t* __restrict__ mask, int cpw,
-              const double* __restrict__ mdot, double dt_h, double* __restrict__ rec) {
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y * 4 + threadIdx.y;
-    const int z = blockIdx.z;
-    if (x >= d.n[0] || y >= d.n[1]) return;
-    const long row = (long)z * d.n[1] + y;
-    if (!mask_bit(mask, row * d.wpr, x, cpw)) return;  // the mixed cells of c
-    const long id = row * d.n[0] + x;
-    const double md = mdot[id];
-    const double cv = c[id];
-    if (md == 0.0) return;
-    double c27[27];
-    gather27(d, c, x, y, z, c27);
-    const Normal nm = normal27(c27, d.normal);
-    const double alpha = alpha_of(nm.m[0], nm.m[1], nm.m[2], cv);
-    const double dd = -(md / d.rho_l) * dt_h;
-    const double norm2 = sqrt(nm.m[0] * nm.m[0] + nm.m[1] * nm.m[1] + nm.m[2] * nm.m[2]);
-    double* r = rec + 5 * id;
-    r[0] = nm.m[0];
-    r[1] = nm.m[1];
-    r[2] = nm.m[2];
-    r[3] = alpha;
-    r[4] = alpha + norm2 * dd;
-}
-
-// Step 2, second pass: a moving cell takes V(m, alpha*) (the motion capped at the cell
-// bounds); a pure cell that a neighbour's plane advances into (liquid for evaporation,
-// gas for condensation) takes the volume the extended plane sweeps in it, averaged over
-// those neighbours; then the latent correction Delta e = Delta c (C_pl - C_pg) T_Gamma
-// (section 3.4.1).
-__global__ void __launch_bounds__(256)
-k_phase_apply(Dom d, const double* __restrict__ c, const double* __restrict__ e,
-              const uint64_t* __restrict__ mask, int cpw, const double* __restrict__ mdot, double dt_h,
-              const double* __restrict__ rec,
-              double* __restrict__ c_out, double* __restrict__ e_out, uint64_t* __restrict__ mask_out,
-              double* __restrict__ part, long part_stride) {
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y * 4 + threadIdx.y;
-    const int z = blockIdx.z;
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    bool mx = false;
-    // Wavefront shortcut: when the mask words around the wavefront's 64 cells (its row and
-    // the face-neighbour rows, over cells x0-1 .. x0+64) hold no mixed cell, no cell of
-    // the wavefront is mixed or has a mixed face neighbour, so none changes. Taken only
-    // away from the x ends of the domain; the words are read with wavefront-uniform
-    // (scalar) addresses.
-    bool quiet = false;
-    {
-        const int x0 = blockIdx.x * 64;
-        const int yu = __builtin_amdgcn_readfirstlane(y);
-        if (yu < d.n[1] && x0 > 0 && x0 + 64 < d.n[0]) {
-            const int klo = (x0 - 1) / cpw, khi = (x0 + 64) / cpw;  // at most 3 words
-            uint64_t any = 0;
-            auto row_or = [&](int yy, int zz) {
-                const long rw = ((long)zz * d.n[1] + yy) * d.wpr;
-                for (int k = klo; k <= khi; ++k) any |= mask[rw + k];
-            };
-            row_or(yu, z);
-            for (int sg = -1; sg <= 1; sg += 2) {
-                const int yy = yu + sg;
-                if (yy >= 0 && yy < d.n[1]) row_or(yy, z);
-                else if (d.bc[1] == 0) row_or(yy < 0 ? yy + d.n[1] : yy - d.n[1], z);
-                if (d.ndim == 3) {
-                    const int zz = z + sg;
-                    if (zz >= 0 && zz < d.n[2]) row_or(yu, zz);
-                    else if (d.bc[2] == 0) row_or(yu, zz < 0 ? zz + d.n[2] : zz - d.n[2]);
-                }
-            }
-            quiet = any == 0ull;
-        }
-    }
-    if (x < d.n[0] && y < d.n[1]) {
-        const long row = (long)z * d.n[1] + y;
-        const long id = row * d.n[0] + x;
-        const double cj = c[id];
-        double cnew = cj;
-        // mixedness of c from its mask (the same test, without reading the neighbours'
-        // fractions and mass fluxes unless they are mixed)
-        if (quiet) {
-        } else if (mask_bit(mask, row * d.wpr, x, cpw)) {
-            if (mdot[id] != 0.0) {
-                const double* r = rec + 5 * id;
-                cnew = volume(r[0], r[1], r[2], r[4]);
-            }
-        } else {
-            const double want = cj >= 1.0 - d.eps ? -1.0 : 1.0;
-            // the six face neighbours (x-, x+, y-, y+, z-, z+): their mask bits are loaded
-            // together, then the mixed ones are visited in that fixed order
-            const int pos[3] = {x, y, z};
-            long nid[6];
-            bool nmix[6];
-#pragma unroll
-            for (int j = 0; j < 6; ++j) {
-                const int k = j >> 1, sg = (j & 1) ? 1 : -1;
-                int q[3] = {pos[0], pos[1], pos[2]};
-                q[k] += sg;
-                const bool inside = k < d.ndim && !(d.bc[k] == 1 && (q[k] < 0 || q[k] >= d.n[k]));
-                const long nrow = (long)wrap(q[2], d.ndim == 2 ? 1 : d.n[2], d.bc[2]) * d.n[1] +
-                                  wrap(q[1], d.n[1], d.bc[1]);
-                const int nx_ = wrap(q[0], d.n[0], d.bc[0]);
-                nid[j] = nrow * d.n[0] + nx_;
-                nmix[j] = inside && mask_bit(mask, nrow * d.wpr, nx_, cpw);
-            }
-            double sum = 0.0;
-            int cnt = 0;
-#pragma unroll
-            for (int j = 0; j < 6; ++j) {
-                if (!nmix[j]) continue;
-                const int k = j >> 1, sg = (j & 1) ? 1 : -1;
-                const double mdn = mdot[nid[j]];
-                if (mdn == 0.0) continue;
-                const double dd = -(mdn / d.rho_l) * dt_h;
-                const double motion = dd > 0.0 ? 1.0 : -1.0;
-                if (motion != want) continue;
-                const double* r = rec + 5 * nid[j];
-                const double mo = -sg * r[k];
-                sum += volume(r[0], r[1], r[2], r[3] - mo) - volume(r[0], r[1], r[2], r[4] - mo);
-                ++cnt;
-            }
-            if (cnt) cnew = cj - sum / cnt;
-        }
-        const double dc = cnew - cj;
-        const double de = (dc * (d.cp_l - d.cp_g)) * d.T_gamma;
-        const double enew = e[id] + de;
-        c_out[id] = cnew;
-        e_out[id] = enew;
-        acc[0] = dc;
-        acc[1] = de;
-        acc[6] = cnew;
-        acc[7] = enew;
-        mx = mixed(d, cnew);
-    }
-    const unsigned long long bits = __ballot(mx);
-    if (threadIdx.x == 0 && y < d.n[1]) mask_out[((long)z * d.n[1] + y) * d.wpr + blockIdx.x] = bits;
-    const long blk = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    // acc[2..5] are never set here; a quiet wavefront changes no cell (dc = de = +0)
-    block_sum8<4>(acc, part + blk, part_stride, 0x3Cu | (quiet ? 0x3u : 0u));
-}
-
 }  // namespace
 
 Launch cell_launch(const Dom& d) {
@@ -896,7 +754,7 @@ Launch sweep_launch(const Dom& d, int axis, int* chunk) {
 
 int max_partial_blocks(const Dom& d) {
     // y / z sweeps are counted with the shortest chunk a batch may choose (kMinChunk)
-    int m = cell_launch(d).nblocks;
+    int m = std::max(cell_launch(d).nblocks, phase_launch(d).nblocks);
     for (int a = 0; a < d.ndim; ++a) {
         const int nb = sweep_tiles(d, a, a == 0 ? 0 : kMinChunk, 0, nullptr);
         if (nb > m) m = nb;
@@ -986,16 +844,5 @@ hipError_t launch_sweep(const Dom& d, int axis, const SweepIO& io, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_phase(const Dom& d, const PhaseIO& io, hipStream_t s) {
-    const double dt_h = io.dt / io.h;
-    const Launch L = cell_launch(d);
-    hipLaunchKernelGGL(k_phase_recon, L.grid, L.block, 0, s, d, io.c, io.mask, io.mask_cpw, io.mdot, dt_h, io.rec);
-    hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k_phase_apply, L.grid, L.block, 0, s, d, io.c, io.e, io.mask, io.mask_cpw, io.mdot, dt_h,
-                       io.rec, io.c_out, io.e_out, io.mask_out, io.part, io.part_stride);
-    *io.nblocks = L.nblocks;
-    return hipGetLastError();
-}
 
 }  // namespace pcv
