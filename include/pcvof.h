@@ -252,6 +252,19 @@ size_t pcvof_diffusion_workspace_bytes(pcvof_handle* h);
 int pcvof_diffuse(pcvof_handle* h, double dt, double k_l, double k_g, double rel_tol, int max_iter, void* d_workspace,
                   size_t workspace_bytes, double* T_out, int mem, pcvof_ext_info* info);
 
+/* pcvof_diffuse for callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid allocation): the same operation,
+   arguments and results as pcvof_diffuse, without the workspace arguments. It allocates
+   nothing: its scratch is one device array of 256 MiB per GPU, part of the library and
+   held until the process ends, enough for domains of about 1.9 million cells
+   (pcvof_diffusion_workspace_bytes(h) <= 256 MiB); larger domains get
+   PCVOF_ERR_WORKSPACE without anything launched. Every call on a GPU shares that GPU's
+   array: calls that overlap on one GPU (several host threads, or streams that run at
+   the same time) race and give undefined results. The array keeps the last call's
+   contents; the call writes every location it reads. */
+int pcvof_diffuse_static(pcvof_handle* h, double dt, double k_l, double k_g, double rel_tol, int max_iter,
+                         double* T_out, int mem, pcvof_ext_info* info);
+
 /* One time step with face CFL numbers lambda_f = u_f * (u_scale * dt) / h:
    prologue, ndim sweeps in the axis order rotated by the step counter (x,y,z /
    y,z,x / z,x,y), step 2 when a mass flux is set, checksums. Increments the step

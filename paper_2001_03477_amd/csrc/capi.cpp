@@ -782,6 +782,24 @@ int pcvof_extend_velocity(pcvof_handle* h, double rho_g, double rel_tol, int max
     return PCVOF_OK;
 }
 
+int pcvof_diffuse_static(pcvof_handle* h, double dt, double k_l, double k_g, double rel_tol, int max_iter,
+                         double* T_out, int mem, pcvof_ext_info* info) {
+    if (int r = check_handle(h)) return r;
+    // the GPU that holds the domain (its workspace), whose scratch array is used
+    hipPointerAttribute_t attr;
+    HIP_TRY(hipPointerGetAttributes(&attr, h->ws));
+    void* ws = nullptr;
+    size_t cap = 0;
+    HIP_TRY(pcv::diff_static_scratch(attr.device, &ws, &cap));
+    const size_t need = pcv::diff_layout(h->d).bytes;
+    if (need > cap)
+        return fail(PCVOF_ERR_WORKSPACE,
+                    "the diffusion of %ld cells needs %zu bytes of scratch; the static scratch holds %zu "
+                    "(about %zu cells): use pcvof_diffuse with a workspace",
+                    h->d.ncell, need, cap, cap / 137);
+    return pcvof_diffuse(h, dt, k_l, k_g, rel_tol, max_iter, ws, cap, T_out, mem, info);
+}
+
 size_t pcvof_diffusion_workspace_bytes(pcvof_handle* h) {
     if (!h || !h->ws) return 0;
     return pcv::diff_layout(h->d).bytes;

@@ -52,6 +52,12 @@ hipError_t launch_diff_start(const Dom& d, const double* c, const double* e, dou
                              double k_g, DiffIO& io, hipStream_t s);
 // One BiCGSTAB iteration (scal[kBiRr] updated).
 hipError_t launch_diff_iteration(const Dom& d, const DiffIO& io, hipStream_t s);
+// The diffusion's scratch for callers that cannot allocate: a file-scope device array
+// of kDiffStaticBytes on every GPU the library runs on (held until the process ends).
+// Its address on `device`, looked up once per device with that device current.
+constexpr size_t kDiffStaticBytes = size_t(256) << 20;
+hipError_t diff_static_scratch(int device, void** ptr, size_t* bytes);
+
 // e = C_p(c) T^{n+1}; T_out (may be null) = T^{n+1}.
 hipError_t launch_diff_finish(const Dom& d, const double* c, double* e, double* T_out, const DiffIO& io,
                               hipStream_t s);

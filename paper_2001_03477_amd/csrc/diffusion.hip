@@ -22,6 +22,8 @@
 #include "common.h"
 #include "diffusion.h"
 
+#include <mutex>
+
 namespace pcv {
 
 namespace {
@@ -415,6 +417,41 @@ int grid_for(long n) {
 }
 
 }  // namespace
+
+// Scratch of pcvof_diffuse_static. In host code `scratch` names a host-side stand-in,
+// not device memory: only the address from hipGetSymbolAddress is ever used.
+static __device__ __align__(256) unsigned char scratch[kDiffStaticBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+hipError_t diff_static_scratch(int device, void** ptr, size_t* bytes) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) {
+            const hipError_t e2 = hipSetDevice(cur);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    *bytes = kDiffStaticBytes;
+    return hipSuccess;
+}
 
 DiffLayout diff_layout(const Dom& d) {
     DiffLayout L;

@@ -33,7 +33,7 @@ EXPORTS = (
     "pcvof_batch_domain", "pcvof_batch_advect_step", "pcvof_batch_get_step", "pcvof_batch_set_tiles",
     "pcvof_batch_get_tiles", "pcvof_batch_autotune", "pcvof_compute_mass_flux",
     "pcvof_extension_workspace_bytes", "pcvof_extend_velocity", "pcvof_diffusion_workspace_bytes",
-    "pcvof_diffuse",
+    "pcvof_diffuse", "pcvof_diffuse_static",
 )
 
 PROF_NAMES = ("sweep_x", "sweep_y", "sweep_z", "phase", "checksum")
@@ -142,6 +142,8 @@ def lib():
         L.pcvof_diffusion_workspace_bytes.argtypes = [_vp]
         L.pcvof_diffuse.argtypes = [_vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, _vp, C.c_size_t,
                                     _vp, C.c_int, C.POINTER(ExtInfo)]
+        L.pcvof_diffuse_static.argtypes = [_vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, _vp,
+                                           C.c_int, C.POINTER(ExtInfo)]
         for nm in EXPORTS:
             f = getattr(L, nm)
             if nm not in ("pcvof_workspace_bytes", "pcvof_last_error", "pcvof_batch_workspace_bytes",
@@ -308,6 +310,18 @@ class Domain:
         check(lib().pcvof_diffuse(self._h, float(dt), float(k_l), float(k_g), float(rel_tol), int(max_iter),
                                   ws.data_ptr(), int(nbytes), T.data_ptr() if T is not None else None,
                                   PCVOF_MEM_DEVICE, C.byref(info)))
+        return info.as_dict(), T
+
+    def diffuse_static(self, dt: float, k_l: float, k_g: float, rel_tol: float = 1e-13, max_iter: int = 5000,
+                       temperature: bool = False):
+        """pcvof_diffuse_static: the same diffusion step as diffuse(), with the library's
+        static device scratch instead of a workspace (nothing is allocated for it)."""
+        import torch
+        T = torch.empty(self.spec.shape, dtype=torch.float64, device=self.device) if temperature else None
+        info = ExtInfo()
+        check(lib().pcvof_diffuse_static(self._h, float(dt), float(k_l), float(k_g), float(rel_tol), int(max_iter),
+                                         T.data_ptr() if T is not None else None, PCVOF_MEM_DEVICE,
+                                         C.byref(info)))
         return info.as_dict(), T
 
     def compute_mass_flux(self, k_l: float, k_g: float, h_fg: float, distances: bool = False):
