@@ -11,7 +11,9 @@ Reads the SQLite database that rocprofv3 writes (``-d DIR -o run`` gives
   M MiB read and M MiB written. The result ends with a ``traffic_json:`` line that
   bench.py reads back, tagged with a hash of the sweep kernel sources;
 * ``kernels``: the same scaled HBM bytes per dispatch for every kernel whose name starts
-  with one of the given prefixes, also per cell of the grid.
+  with one of the given prefixes, also per cell of the grid;
+* ``counters``: the mean per dispatch of every counter of one or more ``--pmc`` runs, for
+  the kernels whose names start with the given prefixes.
 
 Usage::
 
@@ -179,6 +181,35 @@ def kernels_summary(fetch_db, write_db, calib_mib, cells, prefixes, cmd_fetch, c
     return "\n".join(lines)
 
 
+def counters_summary(dbs, prefixes, command):
+    """Mean of every collected counter per dispatch, for the kernels whose short name
+    starts with one of the prefixes (several --pmc runs may be given; their counters are
+    merged by kernel name)."""
+    per = collections.OrderedDict()
+    for db in dbs:
+        for n, c in counter_rows(db):
+            k = short_name(n)
+            if not any(k.startswith(p) for p in prefixes):
+                continue
+            slot = per.setdefault(k, collections.OrderedDict())
+            for cn, v in c.items():
+                slot.setdefault(cn, []).append(v)
+    names = []
+    for slot in per.values():
+        for cn in slot:
+            if cn not in names:
+                names.append(cn)
+    lines = [f"command: {command}", "", "mean per dispatch", ""]
+    lines.append(f"{'counter':28s} " + " ".join(f"{k[:18]:>18s}" for k in per))
+    for cn in names:
+        vals = []
+        for slot in per.values():
+            v = slot.get(cn)
+            vals.append(f"{sum(v) / len(v):18.4g}" if v else f"{'-':>18s}")
+        lines.append(f"{cn[:28]:28s} " + " ".join(vals))
+    return "\n".join(lines)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -200,8 +231,14 @@ def main(argv=None):
     k.add_argument("--prefixes", required=True, help="comma-separated kernel name prefixes")
     k.add_argument("--command-fetch", required=True)
     k.add_argument("--command-write", required=True)
+    cn = sub.add_parser("counters")
+    cn.add_argument("dbs", nargs="+")
+    cn.add_argument("--prefixes", required=True, help="comma-separated kernel name prefixes")
+    cn.add_argument("--command", required=True)
     args = ap.parse_args(argv)
-    if args.what == "kernels":
+    if args.what == "counters":
+        print(counters_summary(args.dbs, args.prefixes.split(","), args.command))
+    elif args.what == "kernels":
         print(kernels_summary(args.fetch, args.write, args.calib_mib, args.cells, args.prefixes.split(","),
                               args.command_fetch, args.command_write))
     elif args.what == "trace":
