@@ -10,9 +10,10 @@ from paper_2001_03477_amd import workloads as W
 
 pytestmark = [
     pytest.mark.gpu,
-    pytest.mark.skip(reason="the mass-flux kernels are switched off: their first GPU run ended in a "
-                            "memory fault whose cause is not found yet (a CPU emulation of the kernel "
-                            "bodies stays within every buffer)"),
+    pytest.mark.skip(reason="the mass-flux kernels are switched off: their first GPU run, in an earlier "
+                            "state of the sources, ended in a memory fault whose cause is not found (the "
+                            "kept kernel bodies stay inside every buffer and match the oracle on the host: "
+                            "tests/test_host_mass_flux.py)"),
 ]
 
 
