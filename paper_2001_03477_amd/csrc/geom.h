@@ -78,8 +78,11 @@ PCV_HD double volume(double mx, double my, double mz, double alpha) {
     const double S = s.m1 + s.m2 + s.m3;
     if (a <= 0.0) return 0.0;
     if (a >= S) return 1.0;
-    if (a <= 0.5 * S) return vol_lower(s, a);
-    return 1.0 - vol_lower(s, S - a);
+    // one evaluation of the lower half for both halves (a single inlined copy, so that
+    // lanes on either side of S / 2 run the same instructions)
+    const bool up = !(a <= 0.5 * S);
+    const double v = vol_lower(s, up ? S - a : a);
+    return up ? 1.0 - v : v;
 }
 
 // Cube root of x > 0: a single-precision estimate refined by one Halley step in double
@@ -167,9 +170,10 @@ PCV_HD double alpha_of(double mx, double my, double mz, double c) {
     if (mz < 0.0) shift += mz;
     const Sorted3 s = sort_abs(mx, my, mz);
     const double S = s.m1 + s.m2 + s.m3;
-    double a;
-    if (c <= 0.5) a = alpha_lower(s, c);
-    else a = S - alpha_lower(s, 1.0 - c);
+    // one inversion of the lower half for both halves (a single inlined copy)
+    const bool up = !(c <= 0.5);
+    const double la = alpha_lower(s, up ? 1.0 - c : c);
+    const double a = up ? S - la : la;
     return a + shift;
 }
 

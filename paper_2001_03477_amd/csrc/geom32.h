@@ -52,8 +52,9 @@ PCV_HD float volume_f(float mx, float my, float mz, float alpha) {
     const float S = s.m1 + s.m2 + s.m3;
     if (a <= 0.0f) return 0.0f;
     if (a >= S) return 1.0f;
-    if (a <= 0.5f * S) return vol_lower_f(s, a);
-    return 1.0f - vol_lower_f(s, S - a);
+    const bool up = !(a <= 0.5f * S);  // one inlined copy for both halves
+    const float v = vol_lower_f(s, up ? S - a : a);
+    return up ? 1.0f - v : v;
 }
 
 // Inverse of vol_lower_f for 0 < v <= 1/2: closed forms, and Halley iterations on the
@@ -121,7 +122,9 @@ PCV_HD float alpha_of_f(float mx, float my, float mz, float c, float cbar) {
     if (mz < 0.0f) shift += mz;
     const Sorted3f s = sort_abs_f(mx, my, mz);
     const float S = s.m1 + s.m2 + s.m3;
-    const float a = c <= 0.5f ? alpha_lower_f(s, c) : S - alpha_lower_f(s, cbar);
+    const bool up = !(c <= 0.5f);  // one inlined copy for both halves
+    const float la = alpha_lower_f(s, up ? cbar : c);
+    const float a = up ? S - la : la;
     return a + shift;
 }
 
