@@ -108,35 +108,42 @@ PCV_HD double alpha_lower(const Sorted3& s, double v) {
         const double v1 = m1 * m1 / d6;
         if (v < v1) return cbrt_pos(6.0 * m1 * m2 * m3 * v);
     }
-    if (m2 > 0.0) {
-        const double v2 = (3.0 * m2 * m2 - 3.0 * m2 * m1 + m1 * m1) / d6;
-        if (v < v2) return 0.5 * m1 + sqrt(fmax(2.0 * m2 * m3 * v - m1 * m1 / 12.0, 0.0));
-    } else {
-        return m3 * v;  // m1 = m2 = 0: a slab
-    }
-    double lo, hi;
+    if (!(m2 > 0.0)) return m3 * v;  // m1 = m2 = 0: a slab
+    const double v2 = (3.0 * m2 * m2 - 3.0 * m2 * m1 + m1 * m1) / d6;  // V(m2)
+    if (v < v2) return 0.5 * m1 + sqrt(fmax(2.0 * m2 * m3 * v - m1 * m1 / 12.0, 0.0));
+    // the cubic regimes (m1 > 0 here: with m1 = 0 the truncated and four-edge regimes
+    // meet at V = m2 / (2 m3)); the volumes at the bracket ends are the regime bounds
+    // already known: V(m2) = v2, V(m12) or V(m3) = v3, V(S/2) = 1/2
+    double lo, hi, vlo, vhi;
     int three;  // number of corners cut off in the cubic regime
     if (m12 <= m3) {
         const double v3 = 0.5 * m12 / m3;
         if (v >= v3) return m3 * v + 0.5 * m12;
         lo = m2;
         hi = m12;
+        vlo = v2;
+        vhi = v3;
         three = 0;
     } else {
-        const double v3 = vol_lower(s, m3);
+        // V(m3): two corners cut off, (q(m3) - (m3 - m2)^3 / m1) / (6 m2 m3)
+        const double t = m3 - m2;
+        const double v3 = ((3.0 * m3 * m3 - 3.0 * m3 * m1 + m1 * m1) - t * t * t / m1) / d6;
         if (v < v3) {
             lo = m2;
             hi = m3;
+            vlo = v2;
+            vhi = v3;
             three = 0;
         } else {
             lo = m3;
             hi = 0.5 * (m1 + m2 + m3);
+            vlo = v3;
+            vhi = 0.5;
             three = 1;
         }
     }
     const double inv_m1 = 1.0 / m1;
     const double inv_d2 = 1.0 / (2.0 * m2 * m3);
-    const double vlo = vol_lower(s, lo), vhi = vol_lower(s, hi);
     double a = (vhi > vlo) ? lo + (hi - lo) * ((v - vlo) / (vhi - vlo)) : lo;
     const double tol = 1e-8 * (hi - lo);
     for (int it = 0; it < 6; ++it) {

@@ -64,31 +64,39 @@ PCV_HD float alpha_lower_f(const Sorted3f& s, float v) {
     const float m12 = m1 + m2;
     const float d6 = 6.0f * m2 * m3;
     if (m1 > 0.0f && v < m1 * m1 / d6) return cbrtf(6.0f * m1 * m2 * m3 * v);
-    if (m2 > 0.0f) {
-        if (v < (3.0f * m2 * m2 - 3.0f * m2 * m1 + m1 * m1) / d6)
-            return 0.5f * m1 + sqrtf(fmaxf(2.0f * m2 * m3 * v - m1 * m1 / 12.0f, 0.0f));
-    } else {
-        return m3 * v;
-    }
-    float lo, hi;
+    if (!(m2 > 0.0f)) return m3 * v;
+    const float v2 = (3.0f * m2 * m2 - 3.0f * m2 * m1 + m1 * m1) / d6;  // V(m2)
+    if (v < v2) return 0.5f * m1 + sqrtf(fmaxf(2.0f * m2 * m3 * v - m1 * m1 / 12.0f, 0.0f));
+    // cubic regimes: the bracket ends' volumes are the regime bounds (see alpha_lower)
+    float lo, hi, vlo, vhi;
     int three;
     if (m12 <= m3) {
-        if (v >= 0.5f * m12 / m3) return m3 * v + 0.5f * m12;
+        const float v3 = 0.5f * m12 / m3;
+        if (v >= v3) return m3 * v + 0.5f * m12;
         lo = m2;
         hi = m12;
-        three = 0;
-    } else if (v < vol_lower_f(s, m3)) {
-        lo = m2;
-        hi = m3;
+        vlo = v2;
+        vhi = v3;
         three = 0;
     } else {
-        lo = m3;
-        hi = 0.5f * (m1 + m2 + m3);
-        three = 1;
+        const float t = m3 - m2;
+        const float v3 = ((3.0f * m3 * m3 - 3.0f * m3 * m1 + m1 * m1) - t * t * t / m1) / d6;  // V(m3)
+        if (v < v3) {
+            lo = m2;
+            hi = m3;
+            vlo = v2;
+            vhi = v3;
+            three = 0;
+        } else {
+            lo = m3;
+            hi = 0.5f * (m1 + m2 + m3);
+            vlo = v3;
+            vhi = 0.5f;
+            three = 1;
+        }
     }
     const float inv_m1 = 1.0f / m1;
     const float inv_d2 = 1.0f / (2.0f * m2 * m3);
-    const float vlo = vol_lower_f(s, lo), vhi = vol_lower_f(s, hi);
     float a = (vhi > vlo) ? lo + (hi - lo) * ((v - vlo) / (vhi - vlo)) : lo;
     const float tol = 1e-4f * (hi - lo);
     for (int it = 0; it < 4; ++it) {
