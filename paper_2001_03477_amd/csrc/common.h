@@ -11,10 +11,16 @@
 namespace pcv {
 
 // Ghost rule per axis: periodic wrap, or outflow = copy of the nearest interior cell.
+// Positions within one period of the domain (all that the stencils reach on grids of
+// at least three cells) wrap with one correction; the loops only run on smaller grids.
 __device__ __forceinline__ int wrap(int i, int n, int bc) {
     if (bc == 0) {
-        while (i < 0) i += n;
-        while (i >= n) i -= n;
+        if (i < 0) i += n;
+        else if (i >= n) i -= n;
+        if (i < 0 || i >= n) {
+            while (i < 0) i += n;
+            while (i >= n) i -= n;
+        }
         return i;
     }
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
