@@ -14,15 +14,15 @@ struct Dom {
     long ncell;
     double cp_l, cp_g, rho_l, T_gamma, eps, weno_eps;
     int normal;
-    int wpr;       // words per row of the mixed-cell masks: ceil(n[0] / 63)
+    int wpr;       // words per row of the mixed-cell masks: ceil(n[0] / 64)
     int ncons;     // 1: non-conservative energy flux (cells scale lambda T_f by their C_p)
     int split;     // 1: Lagrangian-explicit sweeps (donor stretched by 1 + lam_R - lam_L)
 };
 
 // Mixed-cell mask of a state: one bit per cell, rows of wpr 64-bit words, word k of a
-// row holding cells k*cpw .. k*cpw + cpw - 1 (bit = offset). The x sweep writes masks
-// with cpw = 63 (one word per 63-cell row segment), every other kernel with cpw = 64.
-constexpr int kMaskCpwX = 63;
+// row holding cells k*cpw .. k*cpw + cpw - 1 (bit = offset). Every kernel writes masks
+// with cpw = 64; the x sweep reads only such masks.
+constexpr int kMaskCpwX = 64;
 constexpr int kMaskCpw = 64;
 
 // Per-block partial sums written by every stage kernel: 8 doubles per block.

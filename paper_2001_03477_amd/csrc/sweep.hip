@@ -228,24 +228,6 @@ __device__ __forceinline__ void cell_energy_flux(const Dom& d, double cv, double
     }
 }
 
-// x sweep: each wavefront walks XRPW rows of one segment of XC = 63 cells (block
-// (bx, by, z): segment bx of rows (4 by + wave) XRPW .. + XRPW - 1 of plane z). A segment is
-// staged in the wavefront's own LDS row with a 3-cell halo on both sides (no block
-// barrier: a wavefront's LDS accesses complete in order); lane l computes the flux of
-// face x0 + l (64 faces for 63 cells) and cell l takes its right face from lane l + 1.
-// The next row's loads are issued before the current row is computed, and the
-// checksums are reduced once per wavefront. Indices that depend on the lane's position
-// are recomputed per row rather than kept, which lets the kernel fit five wavefronts
-// per SIMD without spilling.
-constexpr int XW = 64;
-constexpr int XC = XW - 1;
-constexpr int XWAVES = 4;
-constexpr int XRPW = 8;
-constexpr int XH = 3;
-// staged positions x0-3 .. x0+65 (LDS index 0 .. 68): the face of lane 63 (x0 + 63)
-// reads temperatures up to x0+65 and donors up to x0+63
-constexpr int XS = XW + 5;
-
 // Longest column chunk of the y and z sweeps, and the number of donor fluxes a y / z
 // wavefront keeps in LDS (fluxes beyond it go to a face array in global memory,
 // written and read back by the same wavefront).
@@ -253,6 +235,86 @@ constexpr int TCH = 32;
 constexpr int kMinChunk = 8;
 constexpr int TFCAP = 192;
 static_assert(TCH < 64 && (TCH + 1) * 64 <= 65536, "work items and positions fit 16 bits");
+
+// x sweep: a wavefront walks XR rows (XR = 1, 2, 4 or 8, chosen per domain) of one
+// sub-row range [x0, x1) (x0 a multiple of 64, at most XKMAX chunks of 64 cells) chunk
+// by chunk, one cell per lane. Lane l computes the right face of its cell and takes the
+// left face from lane l - 1; lane 0 takes it from lane 63 of the previous chunk, or, at
+// the start of a row, from the row's first face, which the wavefront computes for all
+// of its rows at once. Fractions, energies and temperatures are staged in a ring of two
+// 64-position LDS slots (chunk j holds positions x0 - 2 + 64 j .. + 63), so that each
+// position is loaded and divided once per row; the chunk after the current one is
+// staged before its faces are computed (the WENO5 stencil of the last lane reaches 3
+// cells ahead) and loaded one chunk earlier. The output mask words are the chunks
+// (cpw = 64). Before the walk the wavefront lists the faces of all its rows with a mixed
+// cell on either side (in walk order: first faces, then row by row, chunk by chunk) and
+// reconstructs their mixed donors 64 at a time; the walk recomputes each face's list
+// position from the same mask words, so no per-face index is stored.
+constexpr int XW = 64;
+constexpr int XWAVES = 4;
+constexpr int XRMAX = 8;     // rows per wavefront
+constexpr int XKMAX = 16;    // chunks per sub-row (1024 cells; face offsets fit 11 bits)
+constexpr int XFCAP = 256;   // donor fluxes per wavefront kept in LDS (more go to fgeo)
+constexpr int XRING = 128;   // staged positions per wavefront (two chunks)
+constexpr long kMinXWaves = 16384;  // wavefronts a launch should have (about three rounds)
+
+// Rows per wavefront and chunks per sub-row of the x sweep of a domain: as many rows and
+// chunks as keep at least kMinXWaves wavefronts (rows halved first, then chunks).
+struct XPlan {
+    int rows, chunks, splits;
+};
+__host__ __device__ inline XPlan x_plan(int nx, int ny, int nz) {
+    const int kt = (nx + XW - 1) / XW;
+    XPlan p{XRMAX, kt < XKMAX ? kt : XKMAX, 0};
+    for (;;) {
+        p.splits = (kt + p.chunks - 1) / p.chunks;
+        const long waves = (long)p.splits * ((ny + p.rows - 1) / p.rows) * nz;
+        if (waves >= kMinXWaves) break;
+        if (p.rows > 1)
+            p.rows >>= 1;
+        else if (p.chunks > 1)
+            p.chunks = (p.chunks + 1) >> 1;
+        else
+            break;
+    }
+    return p;
+}
+
+// Mixed bit of cell x (ghost positions mapped) in row R of the input mask (cpw = 64).
+__device__ __forceinline__ bool mask64(const Dom& d, const uint64_t* __restrict__ mask, int R, int x) {
+    const int xm = wrap(x, d.n[0], d.bc[0]);
+    return (mask[(long)R * d.wpr + (xm >> 6)] >> (xm & 63)) & 1ull;
+}
+
+// Whether the right face of this lane's cell x0 + 64 k + lane (own: x < x1) has a mixed
+// cell on either side: w0 is the mask word of the chunk, w1 the next word of the row (0
+// past the row's end), gbit the bit of the ghost cell right of the last cell (cell 0 on
+// periodic axes, the last cell on outflow ones).
+__device__ __forceinline__ bool x_face_need(int nx, uint64_t w0, uint64_t w1, int x, int lane, bool own,
+                                            bool gbit) {
+    bool right;
+    if (x + 1 == nx)
+        right = gbit;
+    else if (lane < 63)
+        right = (w0 >> (lane + 1)) & 1ull;
+    else
+        right = w1 & 1ull;
+    return own && (((w0 >> lane) & 1ull) || right);
+}
+
+// A wavefront-uniform 64-bit value moved into scalar registers (each half zero-extended).
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Orders a wavefront's LDS accesses: the compiler keeps them on their side of it, and
+// the LDS executes a wavefront's accesses in order.
+__device__ __forceinline__ void wave_lds_order() {
+    __builtin_amdgcn_wave_barrier();
+    __asm__ volatile("" ::: "memory");
+}
 
 // A tile of a sweep: block coordinates in the domain's own launch grid and the row
 // of the partial tables it writes.
@@ -263,157 +325,220 @@ struct TileAt {
 
 template <bool MP>
 __device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a, const TileAt& tl) {
-    __shared__ double s_c[XWAVES][XS];
-    __shared__ double s_T[XWAVES][XS];
-    __shared__ double s_F[XWAVES][XRPW][XW];                 // liquid flux of mixed donors
-    __shared__ unsigned short s_work[XWAVES][XRPW * XW];    // candidate faces (row:lane)
+    __shared__ double s_c[XWAVES][XRING];
+    __shared__ double s_e[XWAVES][XRING];
+    __shared__ double s_T[XWAVES][XRING];
+    __shared__ double s_F[XWAVES][XFCAP];           // liquid flux of listed faces, by position
+    __shared__ double s_first[XWAVES][3][XRMAX];    // Phi, E, lambda of each row's carried face
+    __shared__ unsigned short s_work[XWAVES][128];  // listed faces not yet reconstructed (ring)
+    __shared__ uint64_t s_mw[XWAVES][XRMAX * (XKMAX + 1)];  // input mask words of the rows
+    __shared__ uint64_t s_bal[XWAVES][XRMAX * XKMAX];       // listed faces of each chunk (ballot)
+    using T = typename Prec<MP>::T;
     const int lane = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
     const int nx = d.n[0];
-    const int sx = tl.bx;  // the wavefront's segment
-    const int y0 = (tl.by * XWAVES + wave) * XRPW;
-    const int nrows = max(0, min(XRPW, d.n[1] - y0));  // uniform over the wavefront
-    const int R0 = tl.bz * d.n[1] + y0;                 // row index (z ny + y) of row 0
+    const XPlan pl = x_plan(nx, d.n[1], d.ndim == 2 ? 1 : d.n[2]);
+    const int x0 = tl.bx * pl.chunks * XW;
+    const int x1 = min(nx, x0 + pl.chunks * XW);
+    const int K = (x1 - x0 + XW - 1) / XW;
+    const int y0 = (tl.by * XWAVES + wave) * pl.rows;
+    const int nrows = max(0, min(pl.rows, d.n[1] - y0));  // uniform over the wavefront
+    const int R0 = tl.bz * d.n[1] + y0;                    // row index (z ny + y) of row 0
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 
-    // Geometry, first pass: the faces x0 .. x0+63 of the wavefront's rows with a mixed
-    // cell on either side (lane = face offset, item = row:lane), read from the mask of
-    // the input (cell x-1 in this lane, cell x from the next lane); the mask words of
-    // all rows are loaded first, so that the loads overlap.
-    unsigned nwork = 0;
-    {
-        const int cpw = a.mask_cpw;
-        const int x0 = sx * XC;
-        const int xl = wrap(x0 + lane - 1, nx, d.bc[0]);
-        const int xr = wrap(x0 + XW - 1, nx, d.bc[0]);  // lane 63's right cell
-        const int kl = xl / cpw, bl = xl - kl * cpw;
-        const int kr = xr / cpw, br = xr - kr * cpw;
-        uint64_t g_wl[XRPW], g_wr[XRPW];
-#pragma unroll
-        for (int r = 0; r < XRPW; ++r) {
-            g_wl[r] = 0ull;
-            g_wr[r] = 0ull;
-            if (r < nrows) {
-                const long rw = (long)(R0 + r) * d.wpr;
-                g_wl[r] = a.mask[rw + kl];
-                if (lane == XW - 1) g_wr[r] = a.mask[rw + kr];
+    // Geometry: list the faces (item = row << 11 | face offset from x0) and reconstruct
+    // the mixed donors of the listed faces 64 at a time (position q of the list: flux in
+    // s_F[q], or in fgeo at the face beyond XFCAP).
+    unsigned nwork = 0, ndone = 0;
+    auto append = [&](bool need, unsigned item) {
+        const unsigned long long bal = __ballot(need);
+        if (need) s_work[wave][(nwork + (unsigned)__popcll(bal & __lanemask_lt())) & 127] = (unsigned short)item;
+        nwork += (unsigned)__popcll(bal);
+    };
+    auto reconstruct = [&]() {  // items ndone .. min(nwork, ndone + 64) - 1
+        wave_lds_order();
+        const unsigned q = ndone + lane;
+        if (q < nwork) {
+            const unsigned it = s_work[wave][q & 127];
+            const int r = it >> 11, f = x0 + (int)(it & 2047);
+            const int R = R0 + r;
+            const double lam = vel_at<MP>(a, (long)R * (nx + 1) + f) * a.kfac;
+            const int xd = lam > 0.0 ? f - 1 : f;
+            const double cd = a.c[(long)R * nx + wrap(xd, nx, d.bc[0])];
+            if (lam != 0.0 && mixed(d, cd)) {
+                double s = 1.0;
+                if (d.split) {
+                    const int fo = face_wrap(lam > 0.0 ? f - 1 : f + 1, nx, d.bc[0]);
+                    s = donor_stretch(lam, vel_at<MP>(a, (long)R * (nx + 1) + fo) * a.kfac);
+                }
+                const double F = donor_flux<0, MP>(d, a.c, xd, y0 + r, tl.bz, cd, lam, s);
+                if (q < XFCAP)
+                    s_F[wave][q] = F;
+                else
+                    a.fgeo[(long)R * (nx + 1) + f] = F;
             }
         }
+        ndone = min(nwork, ndone + XW);
+        wave_lds_order();
+    };
+    const bool need0 = lane < nrows && (mask64(d, a.mask, R0 + lane, x0 - 1) || mask64(d, a.mask, R0 + lane, x0));
+    const unsigned pos0 = (unsigned)__popcll(__ballot(need0) & __lanemask_lt());  // list position
+    append(need0, (unsigned)lane << 11);
+    const unsigned nfirst = nwork;
+    // the mask words x0 / 64 .. x0 / 64 + K of each row (0 past the row's end), and the
+    // bits of the rows' ghost cells right of their last cells
+    for (int i = lane; i < nrows * (XKMAX + 1); i += XW) {
+        const int r = i / (XKMAX + 1), w = (x0 >> 6) + (i - r * (XKMAX + 1));
+        s_mw[wave][i] = w < d.wpr ? a.mask[(long)(R0 + r) * d.wpr + w] : 0ull;
+    }
+    const uint64_t gbits = __ballot(lane < nrows && mask64(d, a.mask, R0 + lane, nx));
+    wave_lds_order();
+    for (int r = 0; r < nrows; ++r) {
+        const bool gbit = (gbits >> r) & 1ull;
+        for (int k = 0; k < K; ++k) {
+            const int x = x0 + 64 * k + lane;
+            const uint64_t w0 = s_mw[wave][r * (XKMAX + 1) + k], w1 = s_mw[wave][r * (XKMAX + 1) + k + 1];
+            const bool need = x_face_need(nx, w0, w1, x, lane, x < x1, gbit);
+            const uint64_t bal = __ballot(need);
+            if (lane == 0) s_bal[wave][r * XKMAX + k] = bal;
+            append(need, ((unsigned)r << 11) | (unsigned)(64 * k + lane + 1));
+            while (nwork - ndone >= (unsigned)XW) reconstruct();
+        }
+    }
+    if (nwork > ndone) reconstruct();
+    if (nwork > XFCAP) __threadfence_block();  // fgeo entries are read back by other lanes
+
+    // The first face (x0) of each row: lane r computes it for row r.
+    if (lane < nrows) {
+        const int R = R0 + lane;
+        const long rb = (long)R * nx;
+        const double lam = vel_at<MP>(a, (long)R * (nx + 1) + x0) * a.kfac;
+        double Phi = 0.0, E = 0.0;
+        if (lam != 0.0) {
+            const int b = lam > 0.0 ? x0 - 3 : x0 + 2, st = lam > 0.0 ? 1 : -1;
+            double Ts[5];
 #pragma unroll
-        for (int r = 0; r < XRPW; ++r) {
-            const int ml = (int)((g_wl[r] >> bl) & 1ull);
-            const int right = __shfl_down(ml, 1, 64);  // cell x of lane l is cell x-1 of lane l+1
-            const int mr = lane == XW - 1 ? (int)((g_wr[r] >> br) & 1ull) : right;
-            const bool need = r < nrows && x0 + lane <= nx && (ml | mr);
-            work_append(need, (unsigned short)((r << 6) | lane), s_work[wave], nwork);
+            for (int i = 0; i < 5; ++i) {
+                const long id = rb + wrap(b + i * st, nx, d.bc[0]);
+                Ts[i] = a.e[id] / cp_of(d, a.c[id]);
+            }
+            const double Tf = weno5(Ts[0], Ts[1], Ts[2], Ts[3], Ts[4], d.weno_eps);
+            const double cd = a.c[rb + wrap(lam > 0.0 ? x0 - 1 : x0, nx, d.bc[0])];
+            double F = fabs(lam) * cd;
+            if (mixed(d, cd)) F = s_F[wave][pos0];
+            face_energy(d, lam, F, Tf, Phi, E);
         }
+        s_first[wave][0][lane] = Phi;
+        s_first[wave][1][lane] = E;
+        s_first[wave][2][lane] = lam;
     }
-    __builtin_amdgcn_wave_barrier();
-    // Second pass: the lanes take the listed faces whose donor is mixed.
-    for (unsigned i = lane; i < nwork; i += XW) {
-        const unsigned it = s_work[wave][i];
-        const int r = it >> 6, l = it & (XW - 1);
-        const int R = R0 + r;
-        const int xf = sx * XC + l;
-        const double lam = vel_at<MP>(a, (long)R * (nx + 1) + xf) * a.kfac;
-        if (lam == 0.0) continue;
-        const int xd = lam > 0.0 ? xf - 1 : xf;
-        const double cd = a.c[(long)R * nx + wrap(xd, nx, d.bc[0])];
-        if (!mixed(d, cd)) continue;
-        double s = 1.0;
-        if (d.split) {
-            const int fo = face_wrap(lam > 0.0 ? xf - 1 : xf + 1, nx, d.bc[0]);
-            s = donor_stretch(lam, vel_at<MP>(a, (long)R * (nx + 1) + fo) * a.kfac);
-        }
-        s_F[wave][r][l] = donor_flux<0, MP>(d, a.c, xd, y0 + r, tl.bz, cd, lam, s);
-    }
-    __builtin_amdgcn_wave_barrier();
-    using T = typename Prec<MP>::T;
-    double pc0 = 0, pe0 = 0, pc1 = 0, pe1 = 0, pev = 0;
+
+    // The walk. Prefetched registers: the next chunk to stage (c, e) and the next step's
+    // face velocity and frozen fields (in their storage type).
+    double pc = 0.0, pe = 0.0;
     T pu = 0, pec = 0;
     uint8_t pcc = 0;
-    const bool two = lane + XW < XS;  // lanes 0..4 stage a second position (LDS 64 .. 68)
-    auto prefetch = [&](int R) {
-        const int x0 = sx * XC, x = x0 + lane;
-        const long rb = (long)R * nx;
-        const long fr = (long)R * (nx + 1);
-        const int xi0 = wrap(x0 - XH + lane, nx, d.bc[0]);
-        pc0 = a.c[rb + xi0];
-        pe0 = a.e[rb + xi0];
-        if (two) {
-            const int xi1 = wrap(x0 - XH + lane + XW, nx, d.bc[0]);
-            pc1 = a.c[rb + xi1];
-            pe1 = a.e[rb + xi1];
-        }
-        if (lane < XC && x < nx) {
-            pev = a.e[rb + x];
+    auto load_chunk = [&](int R, int j) {  // positions x0 - 2 + 64 j + lane of row R
+        const long id = (long)R * nx + wrap(x0 - 2 + 64 * j + lane, nx, d.bc[0]);
+        pc = a.c[id];
+        pe = a.e[id];
+    };
+    auto load_step = [&](int R, int k) {  // right face and frozen fields of cell x0 + 64 k + lane
+        const int x = x0 + 64 * k + lane;
+        if (x < x1) {
+            pu = vel_at<MP>(a, (long)R * (nx + 1) + x + 1);
             if (!a.first) {
-                pcc = a.cc[rb + x];
-                pec = ec_at<MP>(a, rb + x);
+                pcc = a.cc[(long)R * nx + x];
+                pec = ec_at<MP>(a, (long)R * nx + x);
             }
         }
-        if (x <= nx) pu = vel_at<MP>(a, fr + x);
     };
-    if (nrows > 0) prefetch(R0);
+    unsigned pos_base = nfirst;  // list position of the next step's first listed face
+    if (nrows > 0) load_chunk(R0, 0);
     for (int r = 0; r < nrows; ++r) {
         const int R = R0 + r;
-        const int x = sx * XC + lane;
-        const bool own = lane < XC && x < nx;
-        const bool face = x <= nx;
-        const long rowbase = (long)R * nx;
-        const double c0 = pc0, e0 = pe0, c1 = pc1, e1 = pe1, ev_own = pev;
-        const double u = (double)pu, ec_own = (double)pec;
-        const uint8_t cc_own = pcc;
-        if (r + 1 < nrows) prefetch(R + 1);
-        s_c[wave][lane] = c0;
-        s_T[wave][lane] = e0 / cp_of(d, c0);
-        if (two) {
-            s_c[wave][lane + XW] = c1;
-            s_T[wave][lane + XW] = e1 / cp_of(d, c1);
-        }
-        __builtin_amdgcn_wave_barrier();
-        double Phi = 0.0, E = 0.0, lam = 0.0;
-        if (face) {
-            lam = u * a.kfac;
-            if (lam != 0.0) {
-                const int q = lane;
-                const double cd = lam > 0.0 ? s_c[wave][q + XH - 1] : s_c[wave][q + XH];
-                // upwind stencil selected first (cells q .. q+4, or q+5 .. q+1 mirrored), so
-                // that one WENO5 evaluation serves both signs
-                const int b = lam > 0.0 ? q : q + 5, st = lam > 0.0 ? 1 : -1;
-                const double Tf = weno5(s_T[wave][b], s_T[wave][b + st], s_T[wave][b + 2 * st],
-                                        s_T[wave][b + 3 * st], s_T[wave][b + 4 * st], d.weno_eps);
-                const double F = mixed(d, cd) ? s_F[wave][r][lane] : fabs(lam) * cd;
-                face_energy(d, lam, F, Tf, Phi, E);
+        const long rb = (long)R * nx;
+        for (int j = 0; j <= K; ++j) {
+            {  // stage chunk j
+                const int q = (64 * j + lane) & (XRING - 1);
+                const double cj = pc, ej = pe;
+                s_c[wave][q] = cj;
+                s_e[wave][q] = ej;
+                s_T[wave][q] = ej / cp_of(d, cj);
             }
-        }
-        // the right face of cell l is the face of lane l + 1
-        const double PhiR = __shfl_down(Phi, 1, 64);
-        const double ER = __shfl_down(E, 1, 64);
-        const double lamR = __shfl_down(lam, 1, 64);
-        bool mx = false;
-        if (own) {
-            const double cv = s_c[wave][lane + XH];
-            double EL = E, ERc = ER;
-            cell_energy_flux(d, cv, EL, ERc);
-            const double cn = update_cell<MP>(d, a, rowbase + x, cv, ev_own, s_T[wave][lane + XH], lam, lamR, Phi,
-                                              PhiR, EL, ERc, cc_own, ec_own, acc);
-            mx = mixed(d, cn);
-            if (d.bc[0] == 1) {
-                if (x == 0) {
-                    acc[2] -= Phi;
-                    acc[3] -= EL;
-                }
-                if (x == nx - 1) {
-                    acc[2] += PhiR;
-                    acc[3] += ERc;
+            if (j < K)
+                load_chunk(R, j + 1);
+            else if (r + 1 < nrows)
+                load_chunk(R + 1, 0);
+            const double u = (double)pu, ec_own = (double)pec;
+            const uint8_t cc_own = pcc;
+            if (j < K) load_step(R, j);
+            wave_lds_order();
+            if (j == 0) continue;
+            // step k = j - 1: cell x = x0 + 64 k + lane (staged position p), right face x + 1
+            const int k = j - 1;
+            const int x = x0 + 64 * k + lane;
+            const bool own = x < x1;
+            const int p = 64 * k + lane + 2;
+            const uint64_t bal = uniform64(s_bal[wave][r * XKMAX + k]);
+            const unsigned pos = pos_base + (unsigned)__popcll(bal & __lanemask_lt());
+            pos_base += (unsigned)__popcll(bal);
+            double Phi = 0.0, E = 0.0, lam = 0.0;
+            if (own) {
+                lam = u * a.kfac;
+                if (lam != 0.0) {
+                    const double cd = lam > 0.0 ? s_c[wave][p & (XRING - 1)] : s_c[wave][(p + 1) & (XRING - 1)];
+                    // upwind stencil selected first (cells x-2 .. x+2, or x+3 .. x-1 mirrored),
+                    // so that one WENO5 evaluation serves both signs
+                    const int b = lam > 0.0 ? p - 2 : p + 3, st = lam > 0.0 ? 1 : -1;
+                    const double Tf = weno5(s_T[wave][b & (XRING - 1)], s_T[wave][(b + st) & (XRING - 1)],
+                                            s_T[wave][(b + 2 * st) & (XRING - 1)],
+                                            s_T[wave][(b + 3 * st) & (XRING - 1)],
+                                            s_T[wave][(b + 4 * st) & (XRING - 1)], d.weno_eps);
+                    double F = fabs(lam) * cd;
+                    if (mixed(d, cd)) F = pos < XFCAP ? s_F[wave][pos] : a.fgeo[(long)R * (nx + 1) + x + 1];
+                    face_energy(d, lam, F, Tf, Phi, E);
                 }
             }
+            // the left face of cell l is the face of lane l - 1; lane 0 reads the row's
+            // carried face (its first face, then lane 63's face of the previous chunk)
+            double PhiL = __shfl_up(Phi, 1, 64), EL = __shfl_up(E, 1, 64), lamL = __shfl_up(lam, 1, 64);
+            if (lane == 0) {
+                PhiL = s_first[wave][0][r];
+                EL = s_first[wave][1][r];
+                lamL = s_first[wave][2][r];
+            }
+            wave_lds_order();
+            if (lane == XW - 1) {
+                s_first[wave][0][r] = Phi;
+                s_first[wave][1][r] = E;
+                s_first[wave][2][r] = lam;
+            }
+            bool mx = false;
+            if (own) {
+                const int pq = p & (XRING - 1);
+                const double cv = s_c[wave][pq];
+                double ELc = EL, ERc = E;
+                cell_energy_flux(d, cv, ELc, ERc);
+                const double cn = update_cell<MP>(d, a, rb + x, cv, s_e[wave][pq], s_T[wave][pq], lamL, lam, PhiL,
+                                                  Phi, ELc, ERc, cc_own, ec_own, acc);
+                mx = mixed(d, cn);
+                if (d.bc[0] == 1) {
+                    if (x == 0) {
+                        acc[2] -= PhiL;
+                        acc[3] -= ELc;
+                    }
+                    if (x == nx - 1) {
+                        acc[2] += Phi;
+                        acc[3] += ERc;
+                    }
+                }
+            }
+            // mask of the output: the chunk is one word (cpw = 64)
+            const unsigned long long bits = __ballot(mx);
+            if (lane == 0) a.mask_out[(long)R * d.wpr + (x0 >> 6) + k] = bits;
+            wave_lds_order();
         }
-        // mask of the output: the segment's 63 cells are one word (cpw = 63)
-        const unsigned long long bits = __ballot(mx);
-        if (lane == 0) a.mask_out[(long)R * d.wpr + sx] = bits;
-        __builtin_amdgcn_wave_barrier();
     }
     block_sum8<XWAVES>(acc, a.part + tl.blk, a.part_stride);
 }
@@ -727,8 +852,8 @@ Launch cell_launch(const Dom& d) {
     return L;
 }
 
-// Launch shape of a sweep. x: XRPW rows of a 63-cell segment per wavefront, four
-// wavefronts per block. y, z: 64 x 4 columns per block marching over a chunk of the
+// Launch shape of a sweep. x: x_plan's rows of one sub-row range per wavefront, four
+// wavefronts per block (grid: sub-row ranges, row groups, planes). y, z: 64 x 4 columns per block marching over a chunk of the
 // sweep axis; the chunk is the longest of TCH, TCH / 2, ... 8 cells that still gives
 // >= 4096 blocks (four rounds of blocks at four wavefronts per SIMD on 256 CUs; fewer,
 // longer columns leave the last round partly idle).
@@ -737,7 +862,8 @@ Launch sweep_launch(const Dom& d, int axis, int* chunk) {
     L.block = dim3(64, 4, 1);
     const int nz = d.ndim == 2 ? 1 : d.n[2];
     if (axis == 0) {
-        L.grid = dim3(d.wpr, (d.n[1] + XWAVES * XRPW - 1) / (XWAVES * XRPW), nz);
+        const XPlan p = x_plan(d.n[0], d.n[1], nz);
+        L.grid = dim3(p.splits, (d.n[1] + XWAVES * p.rows - 1) / (XWAVES * p.rows), nz);
         *chunk = 0;
     } else {
         const int nt = axis == 1 ? nz : d.n[1];

@@ -37,7 +37,7 @@ int main(int argc, char** argv) {
     d.normal = hdr[7];
     d.ncell = (long)d.n[0] * d.n[1] * d.n[2];
     d.cp_l = par[0]; d.cp_g = par[1]; d.rho_l = 1.0; d.T_gamma = par[2]; d.eps = 1e-12; d.weno_eps = 1e-6;
-    d.wpr = (d.n[0] + 62) / 63;
+    d.wpr = (d.n[0] + 63) / 64;
     d.ncons = 0; d.split = 0;
     const double h = par[3], k_l = par[4], k_g = par[5], h_fg = par[6];
     const size_t N = (size_t)d.ncell;
