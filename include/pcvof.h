@@ -338,7 +338,7 @@ const char* pcvof_last_error(void);
    launches of a step are captured once per cached state into a HIP graph and replayed
    afterwards. stats (nullable) receives nd checksum records and synchronises.
    pcvof_batch_set_tiles sets the column chunk of the y / z sweeps (chunk[1], chunk[2]:
-   0 = each domain's single-domain rule, else a power of two in [8, 32]);
+   0 = each domain's single-domain rule, else a power of two in [8, 64]);
    pcvof_batch_autotune times the choices on the current state (reps timed launches per
    choice; the state is not advanced) and keeps the fastest per axis. */
 typedef struct pcvof_batch pcvof_batch;

@@ -912,7 +912,7 @@ bool batch_layout(int nd, const pcvof_grid* g, const pcvof_params* p, BatchLayou
         off = align_up(off + L->dom_bytes[i]);
         const pcv::Dom d = make_dom(g[i], p[i]);
         for (int a = 0; a < g[i].ndim; ++a)
-            L->max_tiles[a] += pcv::sweep_tiles(d, a, a == 0 ? 0 : pcv::min_chunk(), 0, nullptr);
+            L->max_tiles[a] += pcv::sweep_tiles(d, a, false, a == 0 ? 0 : pcv::min_chunk(), 0, nullptr);
     }
     L->doms = off;
     off = align_up(off + (size_t)nd * sizeof(pcv::Dom));
@@ -982,10 +982,11 @@ int batch_build_tiles(pcvof_batch* b) {
         b->dom_tiles[a].assign(b->nd, 0);
         for (int i = 0; i < b->nd; ++i) {
             const int ch = a == 0 ? 0 : b->chunk[a];
-            const int n = pcv::sweep_tiles(b->dom[i]->d, a, ch, i, nullptr);
+            const bool mixed = b->mixed != 0;
+            const int n = pcv::sweep_tiles(b->dom[i]->d, a, mixed, ch, i, nullptr);
             const size_t at = t.size();
             t.resize(at + n);
-            pcv::sweep_tiles(b->dom[i]->d, a, ch, i, t.data() + at);
+            pcv::sweep_tiles(b->dom[i]->d, a, mixed, ch, i, t.data() + at);
             b->dom_tiles[a][i] = n;
         }
         if ((int)t.size() > b->L.max_tiles[a]) return fail(PCVOF_ERR_WORKSPACE, "tile table overflow");
@@ -1306,14 +1307,14 @@ int pcvof_batch_autotune(pcvof_batch* b, const double* dt, int reps, int* chosen
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    const int chunks[] = {0, 8, 16, 32};
+    const int chunks[] = {0, 8, 16, 32, 64};
     int best_chunk[3] = {0, 0, 0};
     int rc = PCVOF_OK;
     const size_t ab = pcv::sweep_args_bytes();
     std::vector<char> args((size_t)b->nd * ab);
     for (int axis = 0; axis < b->ndim && !rc; ++axis) {
         float best = 1e30f;
-        for (int ci = 0; ci < (axis ? 4 : 1) && !rc; ++ci) {
+        for (int ci = 0; ci < (axis ? 5 : 1) && !rc; ++ci) {
             int ch[3] = {b->chunk[0], b->chunk[1], b->chunk[2]};
             ch[axis] = axis ? chunks[ci] : 0;
             if ((rc = pcvof_batch_set_tiles(b, ch))) break;

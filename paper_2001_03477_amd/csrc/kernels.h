@@ -77,7 +77,7 @@ struct BatchTile {
 // Tiles of a domain's sweep along axis (chunk <= 0: the single-domain rule; else the
 // given chunk, at most the longest supported); writes them to out (if not null) and
 // returns their number. The tiles' blk rows stay below max_partial_blocks.
-int sweep_tiles(const Dom& d, int axis, int chunk, int dom, BatchTile* out);
+int sweep_tiles(const Dom& d, int axis, bool mixed, int chunk, int dom, BatchTile* out);
 // The device form of a sweep's arguments (the batched kernels read one per domain).
 size_t sweep_args_bytes();
 void sweep_args_pack(const SweepIO& io, void* out);

@@ -140,16 +140,6 @@ __device__ double donor_flux(const Dom& d, const double* __restrict__ c, int x, 
     return d.split ? s * F : F;
 }
 
-// Appends item to a wavefront's work list in LDS where take is true; n is the
-// wavefront-uniform length of the list. Returns the item's position.
-__device__ __forceinline__ unsigned work_append(bool take, unsigned short item, unsigned short* work, unsigned& n) {
-    const unsigned long long ballot = __ballot(take);
-    const unsigned pos = n + (unsigned)__popcll(ballot & __lanemask_lt());
-    if (take) work[pos] = item;
-    n += (unsigned)__popcll(ballot);
-    return pos;
-}
-
 // Linear index of the block (row of the partial tables).
 __device__ __forceinline__ int block_linear() {
     return (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
@@ -231,10 +221,11 @@ __device__ __forceinline__ void cell_energy_flux(const Dom& d, double cv, double
 // Longest column chunk of the y and z sweeps, and the number of donor fluxes a y / z
 // wavefront keeps in LDS (fluxes beyond it go to a face array in global memory,
 // written and read back by the same wavefront).
-constexpr int TCH = 32;
+constexpr int TCH = 64;
 constexpr int kMinChunk = 8;
-constexpr int TFCAP = 192;
-static_assert(TCH < 64 && (TCH + 1) * 64 <= 65536, "work items and positions fit 16 bits");
+constexpr int TFCAP = 255;
+static_assert(TCH <= 64 && ((TCH + 1) << 6) <= 65536, "work items fit 16 bits");
+static_assert(TFCAP <= 255, "saturated list positions fit 8 bits");
 
 // x sweep: a wavefront walks XR rows (XR = 1, 2, 4 or 8, chosen per domain) of one
 // sub-row range [x0, x1) (x0 a multiple of 64, at most XKMAX chunks of 64 cells) chunk
@@ -550,9 +541,10 @@ __device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a, c
 template <int AX, bool MP>
 __device__ __forceinline__ void sweep_t_body(const Dom& d, const SweepArgs& a, int chunk, const TileAt& tl) {
     constexpr int TA = AX == 1 ? 2 : 1;  // the transverse axis other than x
-    __shared__ unsigned short s_idx[4][TCH + 1][64];     // work position of each candidate face
-    __shared__ unsigned short s_work[4][(TCH + 1) * 64];  // candidate faces (face offset:lane)
-    __shared__ double s_F[4][TFCAP];                      // liquid flux of mixed donors, by position
+    __shared__ unsigned short s_work[4][128];  // listed faces not yet reconstructed (ring)
+    __shared__ uint64_t s_mw[4][TCH + 2];      // input mask words of cells s0 - 1 .. s1
+    __shared__ uint8_t s_idx[4][TCH + 1][64];  // list position of each listed face (at most TFCAP)
+    __shared__ double s_F[4][TFCAP];           // liquid flux of listed faces, by list position
     const int lane = threadIdx.x, tr = threadIdx.y;
     const int bx = tl.bx, by = tl.by, bz = tl.bz;
     const int x = bx * 64 + lane;
@@ -569,60 +561,70 @@ __device__ __forceinline__ void sweep_t_body(const Dom& d, const SweepArgs& a, i
     const long fstride = AX == 1 ? d.n[0] : plane;
     auto cell_id = [&](int cell) { return base + (long)wrap(cell, ns, d.bc[AX]) * stride; };
 
-    // Geometry, first pass: the faces s0 .. s1 of the wavefront's columns with a mixed
-    // cell on either side (item = face offset:lane), read from the mask of the input
-    // (cells s0-1 .. s1 of the column); the mask words are loaded first, so that the
-    // loads overlap.
-    unsigned nwork = 0;
-    {
-        const int cpw = a.mask_cpw;
-        const int kw = x / cpw, kb = x - kw * cpw;
-        uint64_t g_w[TCH + 2];
-#pragma unroll
-        for (int j = 0; j < TCH + 2; ++j) {
-            g_w[j] = 0ull;
-            if (ok && s0 - 1 + j <= s1) {
-                const int cell = wrap(s0 - 1 + j, ns, d.bc[AX]);
-                const long row = AX == 1 ? (long)t * d.n[1] + cell : (long)cell * d.n[1] + t;
-                g_w[j] = a.mask[row * d.wpr + kw];
+    // Geometry: the faces s0 .. s1 of the wavefront's columns with a mixed cell on either
+    // side, in face order and lane order (item = face offset:lane). The 64 columns of a
+    // wavefront are one mask word per cell of the sweep axis (cpw = 64), so the words of
+    // cells s0-1 .. s1 are staged in LDS and a face's list is the lanes of (w_j | w_j+1).
+    // The mixed donors of the listed faces are reconstructed 64 at a time (list position
+    // q: flux in s_F[q] below TFCAP, else in fgeo at the face); s_idx keeps each listed
+    // face's position, saturated at TFCAP.
+    const uint64_t okmask = __ballot(ok);
+    const int nface = s1 - s0 + 1;
+    for (int j = lane; j <= nface; j += 64) {
+        uint64_t w = 0ull;
+        if (t < nt) {
+            const int cell = wrap(s0 - 1 + j, ns, d.bc[AX]);
+            const long row = AX == 1 ? (long)t * d.n[1] + cell : (long)cell * d.n[1] + t;
+            w = a.mask[row * d.wpr + bx];
+        }
+        s_mw[tr][j] = w;
+    }
+    wave_lds_order();
+    auto listed = [&](int j) { return uniform64(s_mw[tr][j] | s_mw[tr][j + 1]) & okmask; };
+    unsigned nwork = 0, ndone = 0;
+    auto reconstruct = [&]() {  // items ndone .. min(nwork, ndone + 64) - 1
+        wave_lds_order();
+        const unsigned q = ndone + lane;
+        if (q < nwork) {
+            const unsigned it = s_work[tr][q & 127];
+            const int fl = it >> 6, l = it & 63;
+            const int xw = bx * 64 + l;
+            const long bw = AX == 1 ? (long)t * plane + xw : (long)t * d.n[0] + xw;
+            const long fw = AX == 1 ? (long)t * (d.n[1] + 1) * d.n[0] + xw : (long)t * d.n[0] + xw;
+            const int f = s0 + fl;
+            const double lam = vel_at<MP>(a, fw + (long)f * fstride) * a.kfac;
+            const int sd = lam > 0.0 ? f - 1 : f;
+            const double cd = a.c[bw + (long)wrap(sd, ns, d.bc[AX]) * stride];
+            if (lam != 0.0 && mixed(d, cd)) {
+                double sf = 1.0;
+                if (d.split) {
+                    const int fo = face_wrap(lam > 0.0 ? f - 1 : f + 1, ns, d.bc[AX]);
+                    sf = donor_stretch(lam, vel_at<MP>(a, fw + (long)fo * fstride) * a.kfac);
+                }
+                const double F = AX == 1 ? donor_flux<1, MP>(d, a.c, xw, sd, t, cd, lam, sf)
+                                         : donor_flux<2, MP>(d, a.c, xw, t, sd, cd, lam, sf);
+                if (q < TFCAP)
+                    s_F[tr][q] = F;
+                else
+                    a.fgeo[fw + (long)f * fstride] = F;
             }
         }
-#pragma unroll
-        for (int j = 0; j <= TCH; ++j) {
-            if (s0 + j <= s1) {  // uniform over the block
-                const bool need = ok && (((g_w[j] | g_w[j + 1]) >> kb) & 1ull);
-                const unsigned pos = work_append(need, (unsigned short)((j << 6) | lane), s_work[tr], nwork);
-                if (need) s_idx[tr][j][lane] = (unsigned short)pos;
-            }
+        ndone = min(nwork, ndone + 64u);
+        wave_lds_order();
+    };
+    for (int j = 0; j < nface; ++j) {
+        const uint64_t bal = listed(j);
+        if ((bal >> lane) & 1ull) {
+            const unsigned q = nwork + (unsigned)__popcll(bal & __lanemask_lt());
+            s_work[tr][q & 127] = (unsigned short)((j << 6) | lane);
+            s_idx[tr][j][lane] = (uint8_t)min(q, (unsigned)TFCAP);
         }
+        nwork += (unsigned)__popcll(bal);
+        while (nwork - ndone >= 64u) reconstruct();
     }
-    __builtin_amdgcn_wave_barrier();
-    // Second pass: the lanes take the listed faces whose donor is mixed.
-    for (unsigned i = lane; i < nwork; i += 64) {
-        const unsigned it = s_work[tr][i];
-        const int fl = it >> 6, l = it & 63;
-        const int xw = bx * 64 + l;
-        const long bw = AX == 1 ? (long)t * plane + xw : (long)t * d.n[0] + xw;
-        const long fw = AX == 1 ? (long)t * (d.n[1] + 1) * d.n[0] + xw : (long)t * d.n[0] + xw;
-        const int f = s0 + fl;
-        const double lam = vel_at<MP>(a, fw + (long)f * fstride) * a.kfac;
-        if (lam == 0.0) continue;
-        const int sd = lam > 0.0 ? f - 1 : f;
-        const double cd = a.c[bw + (long)wrap(sd, ns, d.bc[AX]) * stride];
-        if (!mixed(d, cd)) continue;
-        double s = 1.0;
-        if (d.split) {
-            const int fo = face_wrap(lam > 0.0 ? f - 1 : f + 1, ns, d.bc[AX]);
-            s = donor_stretch(lam, vel_at<MP>(a, fw + (long)fo * fstride) * a.kfac);
-        }
-        const double F = AX == 1 ? donor_flux<1, MP>(d, a.c, xw, sd, t, cd, lam, s)
-                                 : donor_flux<2, MP>(d, a.c, xw, t, sd, cd, lam, s);
-        if (i < TFCAP) s_F[tr][i] = F;
-        else a.fgeo[fw + (long)f * fstride] = F;
-    }
+    if (nwork > ndone) reconstruct();
     // the overflow fluxes are read back by other lanes of this wavefront
     if (nwork > TFCAP) __threadfence_block();
-    __builtin_amdgcn_wave_barrier();
     // Register ring of cells f-3 .. f+4 in slots (k + j) % 8, where k counts the faces
     // of the chunk and j = 0..7 the cells from f-3: cells f-3 .. f+2 are the WENO and
     // update window, cells f+3, f+4 are loads in flight; at each face the load of cell
@@ -771,7 +773,8 @@ k_sweep_x_mixed(Dom d, SweepArgs a) {
     sweep_x_body<true>(d, a, own_tile());
 }
 template <int AX>
-__global__ void __launch_bounds__(256) k_sweep_t(Dom d, SweepArgs a, int chunk) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_sweep_t(Dom d, SweepArgs a, int chunk) {
     sweep_t_body<AX, false>(d, a, chunk, own_tile());
 }
 template <int AX>
@@ -832,7 +835,7 @@ k_sweep_x_batch_mixed(const Dom* doms, const SweepArgs* args, const BatchTile* t
     sweep_x_tiles<true>(doms, args, tiles, ntiles);
 }
 template <int AX>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_sweep_t_batch(const Dom* doms, const SweepArgs* args, const BatchTile* tiles, int ntiles) {
     sweep_t_tiles<AX, false>(doms, args, tiles, ntiles);
 }
@@ -853,11 +856,14 @@ Launch cell_launch(const Dom& d) {
 }
 
 // Launch shape of a sweep. x: x_plan's rows of one sub-row range per wavefront, four
-// wavefronts per block (grid: sub-row ranges, row groups, planes). y, z: 64 x 4 columns per block marching over a chunk of the
-// sweep axis; the chunk is the longest of TCH, TCH / 2, ... 8 cells that still gives
-// >= 4096 blocks (four rounds of blocks at four wavefronts per SIMD on 256 CUs; fewer,
-// longer columns leave the last round partly idle).
-Launch sweep_launch(const Dom& d, int axis, int* chunk) {
+// wavefronts per block (grid: sub-row ranges, row groups, planes). y, z: 64 x 4 columns
+// per block marching over a chunk of the sweep axis; the chunk is the longest of C, C / 2,
+// ... 8 cells that still gives >= 4096 blocks (four rounds of blocks at four wavefronts
+// per SIMD on 256 CUs; fewer, longer columns leave the last round partly idle), where C
+// is TCH for mixed-precision y sweeps and TCH / 2 otherwise (the faster choice measured
+// at 512^3: longer columns halve the halo reads, but the double-precision sweeps and the
+// z sweeps, whose columns cross a plane per cell, gain nothing from them).
+Launch sweep_launch(const Dom& d, int axis, bool mixed, int* chunk) {
     Launch L;
     L.block = dim3(64, 4, 1);
     const int nz = d.ndim == 2 ? 1 : d.n[2];
@@ -869,7 +875,7 @@ Launch sweep_launch(const Dom& d, int axis, int* chunk) {
         const int nt = axis == 1 ? nz : d.n[1];
         const long bxy = (long)((d.n[0] + 63) / 64) * ((nt + 3) / 4);
         const int ns = d.n[axis];
-        int ch = TCH;
+        int ch = mixed && axis == 1 ? TCH : TCH / 2;
         while (ch > 8 && bxy * ((ns + ch - 1) / ch) < 4096) ch >>= 1;
         *chunk = ch;
         L.grid = dim3((d.n[0] + 63) / 64, (nt + 3) / 4, (ns + ch - 1) / ch);
@@ -882,7 +888,7 @@ int max_partial_blocks(const Dom& d) {
     // y / z sweeps are counted with the shortest chunk a batch may choose (kMinChunk)
     int m = std::max(cell_launch(d).nblocks, phase_launch(d).nblocks);
     for (int a = 0; a < d.ndim; ++a) {
-        const int nb = sweep_tiles(d, a, a == 0 ? 0 : kMinChunk, 0, nullptr);
+        const int nb = sweep_tiles(d, a, false, a == 0 ? 0 : kMinChunk, 0, nullptr);
         if (nb > m) m = nb;
     }
     return m;
@@ -942,9 +948,9 @@ hipError_t launch_sweep_batch(int axis, int mixed, const Dom* doms, const void* 
     return hipGetLastError();
 }
 
-int sweep_tiles(const Dom& d, int axis, int chunk, int dom, BatchTile* out) {
+int sweep_tiles(const Dom& d, int axis, bool mixed, int chunk, int dom, BatchTile* out) {
     int ch = 0;
-    Launch L = sweep_launch(d, axis, &ch);
+    Launch L = sweep_launch(d, axis, mixed, &ch);
     if (axis != 0) {
         ch = chunk > 0 ? chunk : ch;
         L.grid.z = (d.n[axis] + ch - 1) / ch;
@@ -959,7 +965,7 @@ int sweep_tiles(const Dom& d, int axis, int chunk, int dom, BatchTile* out) {
 
 hipError_t launch_sweep(const Dom& d, int axis, const SweepIO& io, hipStream_t s) {
     int chunk = 0;
-    const Launch L = sweep_launch(d, axis, &chunk);
+    const Launch L = sweep_launch(d, axis, io.mixed != 0, &chunk);
     SweepArgs a{io.c,   io.e,    io.mask, io.mask_cpw, io.mask_out, io.cc,   io.ec,          io.vel,
                 io.kfac, io.fgeo, io.c_out, io.e_out,   io.part,     io.part_stride, io.first};
     if (io.mixed)

@@ -461,7 +461,7 @@ class Batch:
         return v.value
 
     def set_tiles(self, chunk):
-        """Column chunk of the y / z sweeps: chunk[1], chunk[2] in (0, 8, 16, 32)."""
+        """Column chunk of the y / z sweeps: chunk[1], chunk[2] in (0, 8, 16, 32, 64)."""
         ch = (C.c_int * 3)(*chunk)
         check(lib().pcvof_batch_set_tiles(self._b, C.cast(ch, _vp)))
 

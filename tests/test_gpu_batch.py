@@ -101,7 +101,7 @@ def test_batch_first_domains_match_oracle(pc):
     b.close()
 
 
-@pytest.mark.parametrize("chunk", [8, 16, 32])
+@pytest.mark.parametrize("chunk", [8, 16, 32, 64])
 def test_batch_tile_choices_give_the_same_fields(pc, chunk):
     wls = _workloads()
     ref = _singles(pc, wls, 3)
@@ -121,7 +121,7 @@ def test_batch_autotune_keeps_the_state(pc):
     b = _batch(pc, wls)
     b.step([wl.dt for wl in wls])
     chosen = b.autotune([wl.dt for wl in wls], reps=2)
-    assert chosen["chunk"][0] == 0 and all(c in (0, 8, 16, 32) for c in chosen["chunk"][1:])
+    assert chosen["chunk"][0] == 0 and all(c in (0, 8, 16, 32, 64) for c in chosen["chunk"][1:])
     b.step([wl.dt for wl in wls], use_graph=True)
     for d, (c, e, _) in zip(b.domains, ref):
         assert np.array_equal(d.vof().cpu().numpy(), c)
