@@ -337,8 +337,10 @@ const char* pcvof_last_error(void);
    recurring step state. With use_graph != 0 (and no mass flux in any domain) the
    launches of a step are captured once per cached state into a HIP graph and replayed
    afterwards. stats (nullable) receives nd checksum records and synchronises.
-   pcvof_batch_set_tiles sets the column chunk of the y / z sweeps (chunk[1], chunk[2]:
-   0 = each domain's single-domain rule, else a power of two in [8, 64]);
+   pcvof_batch_set_tiles sets the rows per wavefront of the x sweep (chunk[0]: 0 = each
+   domain's single-domain rule, else 1, 2, 4 or 8) and the column chunk of the y / z sweeps
+   (chunk[1], chunk[2]: 0 = each domain's single-domain rule, else a power of two in
+   [8, 64]); the fields do not depend on these choices;
    pcvof_batch_autotune times the choices on the current state (reps timed launches per
    choice; the state is not advanced) and keeps the fastest per axis. */
 typedef struct pcvof_batch pcvof_batch;

@@ -912,7 +912,7 @@ bool batch_layout(int nd, const pcvof_grid* g, const pcvof_params* p, BatchLayou
         off = align_up(off + L->dom_bytes[i]);
         const pcv::Dom d = make_dom(g[i], p[i]);
         for (int a = 0; a < g[i].ndim; ++a)
-            L->max_tiles[a] += pcv::sweep_tiles(d, a, false, a == 0 ? 0 : pcv::min_chunk(), 0, nullptr);
+            L->max_tiles[a] += pcv::max_sweep_tiles(d, a);
     }
     L->doms = off;
     off = align_up(off + (size_t)nd * sizeof(pcv::Dom));
@@ -981,7 +981,7 @@ int batch_build_tiles(pcvof_batch* b) {
         std::vector<pcv::BatchTile> t;
         b->dom_tiles[a].assign(b->nd, 0);
         for (int i = 0; i < b->nd; ++i) {
-            const int ch = a == 0 ? 0 : b->chunk[a];
+            const int ch = b->chunk[a];
             const bool mixed = b->mixed != 0;
             const int n = pcv::sweep_tiles(b->dom[i]->d, a, mixed, ch, i, nullptr);
             const size_t at = t.size();
@@ -1277,14 +1277,14 @@ int pcvof_batch_get_step(pcvof_batch* b, long* step) {
 
 int pcvof_batch_set_tiles(pcvof_batch* b, const int* chunk) {
     if (int r = batch_check(b)) return r;
-    for (int a = 1; a < b->ndim && chunk; ++a) {
+    for (int a = 0; a < b->ndim && chunk; ++a) {
         const int c = chunk[a];
-        if (c != 0 && (c < pcv::min_chunk() || c > pcv::max_chunk() || (c & (c - 1))))
-            return fail(PCVOF_ERR_ARG, "axis %d: chunk %d is not 0 or a power of two in [%d, %d]", a, c,
-                        pcv::min_chunk(), pcv::max_chunk());
+        const int lo = a == 0 ? 1 : pcv::min_chunk(), hi = a == 0 ? 8 : pcv::max_chunk();
+        if (c != 0 && (c < lo || c > hi || (c & (c - 1))))
+            return fail(PCVOF_ERR_ARG, "axis %d: %d is not 0 or a power of two in [%d, %d]", a, c, lo, hi);
     }
     if (int r = batch_invalidate(b)) return r;
-    for (int a = 1; a < b->ndim; ++a)
+    for (int a = 0; a < b->ndim; ++a)
         if (chunk) b->chunk[a] = chunk[a];
     return batch_build_tiles(b);
 }
@@ -1307,16 +1307,16 @@ int pcvof_batch_autotune(pcvof_batch* b, const double* dt, int reps, int* chosen
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    const int chunks[] = {0, 8, 16, 32, 64};
+    const int chunks[2][5] = {{0, 1, 2, 4, 8}, {0, 8, 16, 32, 64}};  // x: rows per wavefront
     int best_chunk[3] = {0, 0, 0};
     int rc = PCVOF_OK;
     const size_t ab = pcv::sweep_args_bytes();
     std::vector<char> args((size_t)b->nd * ab);
     for (int axis = 0; axis < b->ndim && !rc; ++axis) {
         float best = 1e30f;
-        for (int ci = 0; ci < (axis ? 5 : 1) && !rc; ++ci) {
+        for (int ci = 0; ci < 5 && !rc; ++ci) {
             int ch[3] = {b->chunk[0], b->chunk[1], b->chunk[2]};
-            ch[axis] = axis ? chunks[ci] : 0;
+            ch[axis] = chunks[axis ? 1 : 0][ci];
             if ((rc = pcvof_batch_set_tiles(b, ch))) break;
             // a sweep of the current state into the other buffers (state not committed)
             for (int i = 0; i < b->nd; ++i) {

@@ -72,12 +72,15 @@ hipError_t launch_sweep(const Dom& d, int axis, const SweepIO& io, hipStream_t s
 // sweep launch: its coordinates in that launch grid, its row in the domain's partial
 // table (blk) and, for y / z sweeps, the column chunk.
 struct BatchTile {
-    int dom, bx, by, bz, blk, chunk;
+    int dom, bx, by, bz, blk, chunk;  // chunk: y / z column chunk; x: the packed plan
 };
-// Tiles of a domain's sweep along axis (chunk <= 0: the single-domain rule; else the
-// given chunk, at most the longest supported); writes them to out (if not null) and
-// returns their number. The tiles' blk rows stay below max_partial_blocks.
+// Tiles of a domain's sweep along axis (chunk <= 0: the single-domain rule; else, for
+// y / z, the given column chunk, at most the longest supported, and for x the given rows
+// per wavefront, 1, 2, 4 or 8); writes them to out (if not null) and returns their
+// number. The tiles' blk rows stay below max_partial_blocks.
 int sweep_tiles(const Dom& d, int axis, bool mixed, int chunk, int dom, BatchTile* out);
+// Most tiles of any choice of sweep_tiles along axis.
+int max_sweep_tiles(const Dom& d, int axis);
 // The device form of a sweep's arguments (the batched kernels read one per domain).
 size_t sweep_args_bytes();
 void sweep_args_pack(const SweepIO& io, void* out);

@@ -247,29 +247,40 @@ constexpr int XRMAX = 8;     // rows per wavefront
 constexpr int XKMAX = 16;    // chunks per sub-row (1024 cells; face offsets fit 11 bits)
 constexpr int XFCAP = 256;   // donor fluxes per wavefront kept in LDS (more go to fgeo)
 constexpr int XRING = 128;   // staged positions per wavefront (two chunks)
-constexpr long kMinXWaves = 16384;  // wavefronts a launch should have (about three rounds)
 
-// Rows per wavefront and chunks per sub-row of the x sweep of a domain: as many rows and
-// chunks as keep at least kMinXWaves wavefronts (rows halved first, then chunks).
+// Plan of an x sweep: rows per wavefront, chunks per sub-row range, ranges per row. The
+// kernels take rows and chunks packed into one int (rows | chunks << 8).
 struct XPlan {
     int rows, chunks, splits;
 };
-__host__ __device__ inline XPlan x_plan(int nx, int ny, int nz) {
+// The given rows per wavefront, ranges as long as allowed.
+inline XPlan x_plan_rows(int nx, int rows) {
     const int kt = (nx + XW - 1) / XW;
-    XPlan p{XRMAX, kt < XKMAX ? kt : XKMAX, 0};
-    for (;;) {
+    const int ch = kt < XKMAX ? kt : XKMAX;
+    return {rows, ch, (kt + ch - 1) / ch};
+}
+inline long x_waves(const XPlan& p, int ny, int nz) { return (long)p.splits * ((ny + p.rows - 1) / p.rows) * nz; }
+// Single-domain rule: 8 rows per wavefront if that leaves at least 16,384 wavefronts, else 4
+// rows if that leaves 4,096, else 2 if 2,048, else one row, with shorter ranges while fewer
+// than 2,048 wavefronts. (Measured: 8 rows at 512^3, 4 at 256^3 and 128^3 were the fastest;
+// one row per wavefront at 128^3 took 50 instead of 35 µs per x sweep: every wavefront then
+// pays the first-face pass, a staging-only chunk and the geometry latency for one short row.)
+inline XPlan x_plan_rule(int nx, int ny, int nz) {
+    const int rows[3] = {8, 4, 2};
+    const long need[3] = {16384, 4096, 2048};
+    for (int i = 0; i < 3; ++i) {
+        const XPlan p = x_plan_rows(nx, rows[i]);
+        if (x_waves(p, ny, nz) >= need[i]) return p;
+    }
+    XPlan p = x_plan_rows(nx, 1);
+    const int kt = (nx + XW - 1) / XW;
+    while (p.chunks > 1 && x_waves(p, ny, nz) < 2048) {
+        p.chunks = (p.chunks + 1) >> 1;
         p.splits = (kt + p.chunks - 1) / p.chunks;
-        const long waves = (long)p.splits * ((ny + p.rows - 1) / p.rows) * nz;
-        if (waves >= kMinXWaves) break;
-        if (p.rows > 1)
-            p.rows >>= 1;
-        else if (p.chunks > 1)
-            p.chunks = (p.chunks + 1) >> 1;
-        else
-            break;
     }
     return p;
 }
+inline int x_plan_pack(const XPlan& p) { return p.rows | (p.chunks << 8); }
 
 // Mixed bit of cell x (ghost positions mapped) in row R of the input mask (cpw = 64).
 __device__ __forceinline__ bool mask64(const Dom& d, const uint64_t* __restrict__ mask, int R, int x) {
@@ -315,7 +326,7 @@ struct TileAt {
 };
 
 template <bool MP>
-__device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a, const TileAt& tl) {
+__device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a, const TileAt& tl, int plan) {
     __shared__ double s_c[XWAVES][XRING];
     __shared__ double s_e[XWAVES][XRING];
     __shared__ double s_T[XWAVES][XRING];
@@ -328,12 +339,12 @@ __device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a, c
     const int lane = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
     const int nx = d.n[0];
-    const XPlan pl = x_plan(nx, d.n[1], d.ndim == 2 ? 1 : d.n[2]);
-    const int x0 = tl.bx * pl.chunks * XW;
-    const int x1 = min(nx, x0 + pl.chunks * XW);
+    const int prows = plan & 0xff, pchunks = plan >> 8;  // rows per wavefront, chunks per range
+    const int x0 = tl.bx * pchunks * XW;
+    const int x1 = min(nx, x0 + pchunks * XW);
     const int K = (x1 - x0 + XW - 1) / XW;
-    const int y0 = (tl.by * XWAVES + wave) * pl.rows;
-    const int nrows = max(0, min(pl.rows, d.n[1] - y0));  // uniform over the wavefront
+    const int y0 = (tl.by * XWAVES + wave) * prows;
+    const int nrows = max(0, min(prows, d.n[1] - y0));  // uniform over the wavefront
     const int R0 = tl.bz * d.n[1] + y0;                    // row index (z ny + y) of row 0
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 
@@ -765,12 +776,12 @@ __device__ __forceinline__ TileAt own_tile() {
     return {(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z, block_linear()};
 }
 __global__ void __launch_bounds__(XW* XWAVES) __attribute__((amdgpu_waves_per_eu(5, 8)))
-k_sweep_x(Dom d, SweepArgs a) {
-    sweep_x_body<false>(d, a, own_tile());
+k_sweep_x(Dom d, SweepArgs a, int plan) {
+    sweep_x_body<false>(d, a, own_tile(), plan);
 }
 __global__ void __launch_bounds__(XW* XWAVES) __attribute__((amdgpu_waves_per_eu(5, 8)))
-k_sweep_x_mixed(Dom d, SweepArgs a) {
-    sweep_x_body<true>(d, a, own_tile());
+k_sweep_x_mixed(Dom d, SweepArgs a, int plan) {
+    sweep_x_body<true>(d, a, own_tile(), plan);
 }
 template <int AX>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
@@ -814,7 +825,7 @@ __device__ __forceinline__ void sweep_x_tiles(const Dom* __restrict__ doms, cons
     const BatchTile bt = uniform_load(tiles + t);
     const Dom d = uniform_load(doms + bt.dom);
     const SweepArgs a = uniform_load(args + bt.dom);
-    sweep_x_body<MP>(d, a, TileAt{bt.bx, bt.by, bt.bz, bt.blk});
+    sweep_x_body<MP>(d, a, TileAt{bt.bx, bt.by, bt.bz, bt.blk}, bt.chunk);
 }
 template <int AX, bool MP>
 __device__ __forceinline__ void sweep_t_tiles(const Dom* __restrict__ doms, const SweepArgs* __restrict__ args,
@@ -855,8 +866,9 @@ Launch cell_launch(const Dom& d) {
     return L;
 }
 
-// Launch shape of a sweep. x: x_plan's rows of one sub-row range per wavefront, four
-// wavefronts per block (grid: sub-row ranges, row groups, planes). y, z: 64 x 4 columns
+// Launch shape of a sweep. x: the rule's rows of one sub-row range per wavefront, four
+// wavefronts per block (grid: sub-row ranges, row groups, planes; *chunk = the packed
+// plan). y, z: 64 x 4 columns
 // per block marching over a chunk of the sweep axis; the chunk is the longest of C, C / 2,
 // ... 8 cells that still gives >= 4096 blocks (four rounds of blocks at four wavefronts
 // per SIMD on 256 CUs; fewer, longer columns leave the last round partly idle), where C
@@ -868,9 +880,9 @@ Launch sweep_launch(const Dom& d, int axis, bool mixed, int* chunk) {
     L.block = dim3(64, 4, 1);
     const int nz = d.ndim == 2 ? 1 : d.n[2];
     if (axis == 0) {
-        const XPlan p = x_plan(d.n[0], d.n[1], nz);
+        const XPlan p = x_plan_rule(d.n[0], d.n[1], nz);
         L.grid = dim3(p.splits, (d.n[1] + XWAVES * p.rows - 1) / (XWAVES * p.rows), nz);
-        *chunk = 0;
+        *chunk = x_plan_pack(p);
     } else {
         const int nt = axis == 1 ? nz : d.n[1];
         const long bxy = (long)((d.n[0] + 63) / 64) * ((nt + 3) / 4);
@@ -884,13 +896,16 @@ Launch sweep_launch(const Dom& d, int axis, bool mixed, int* chunk) {
     return L;
 }
 
+int max_sweep_tiles(const Dom& d, int axis) {
+    // x: the rule's plan or one row per wavefront (the most blocks a batch may choose);
+    // y / z: the shortest chunk a batch may choose (kMinChunk)
+    if (axis == 0) return std::max(sweep_tiles(d, 0, false, 0, 0, nullptr), sweep_tiles(d, 0, false, 1, 0, nullptr));
+    return sweep_tiles(d, axis, false, kMinChunk, 0, nullptr);
+}
+
 int max_partial_blocks(const Dom& d) {
-    // y / z sweeps are counted with the shortest chunk a batch may choose (kMinChunk)
     int m = std::max(cell_launch(d).nblocks, phase_launch(d).nblocks);
-    for (int a = 0; a < d.ndim; ++a) {
-        const int nb = sweep_tiles(d, a, false, a == 0 ? 0 : kMinChunk, 0, nullptr);
-        if (nb > m) m = nb;
-    }
+    for (int a = 0; a < d.ndim; ++a) m = std::max(m, max_sweep_tiles(d, a));
     return m;
 }
 
@@ -907,7 +922,7 @@ void launch_sweep_kernel(const Dom& d, int axis, const Launch& L, int chunk, con
                          hipEvent_t e0, hipEvent_t e1) {
     if (e0 && e1) {
         if (axis == 0)
-            hipExtLaunchKernelGGL(MP ? k_sweep_x_mixed : k_sweep_x, L.grid, L.block, 0, s, e0, e1, 0, d, a);
+            hipExtLaunchKernelGGL(MP ? k_sweep_x_mixed : k_sweep_x, L.grid, L.block, 0, s, e0, e1, 0, d, a, chunk);
         else if (axis == 1)
             hipExtLaunchKernelGGL(MP ? k_sweep_t_mixed<1> : k_sweep_t<1>, L.grid, L.block, 0, s, e0, e1, 0, d, a,
                                   chunk);
@@ -917,7 +932,7 @@ void launch_sweep_kernel(const Dom& d, int axis, const Launch& L, int chunk, con
         return;
     }
     if (axis == 0)
-        hipLaunchKernelGGL(MP ? k_sweep_x_mixed : k_sweep_x, L.grid, L.block, 0, s, d, a);
+        hipLaunchKernelGGL(MP ? k_sweep_x_mixed : k_sweep_x, L.grid, L.block, 0, s, d, a, chunk);
     else if (axis == 1)
         hipLaunchKernelGGL(MP ? k_sweep_t_mixed<1> : k_sweep_t<1>, L.grid, L.block, 0, s, d, a, chunk);
     else
@@ -951,7 +966,11 @@ hipError_t launch_sweep_batch(int axis, int mixed, const Dom* doms, const void* 
 int sweep_tiles(const Dom& d, int axis, bool mixed, int chunk, int dom, BatchTile* out) {
     int ch = 0;
     Launch L = sweep_launch(d, axis, mixed, &ch);
-    if (axis != 0) {
+    if (axis == 0 && chunk > 0) {  // chunk: rows per wavefront
+        const XPlan p = x_plan_rows(d.n[0], chunk);
+        L.grid = dim3(p.splits, (d.n[1] + XWAVES * p.rows - 1) / (XWAVES * p.rows), L.grid.z);
+        ch = x_plan_pack(p);
+    } else if (axis != 0) {
         ch = chunk > 0 ? chunk : ch;
         L.grid.z = (d.n[axis] + ch - 1) / ch;
     }

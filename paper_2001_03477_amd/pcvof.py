@@ -461,7 +461,8 @@ class Batch:
         return v.value
 
     def set_tiles(self, chunk):
-        """Column chunk of the y / z sweeps: chunk[1], chunk[2] in (0, 8, 16, 32, 64)."""
+        """Rows per x wavefront chunk[0] in (0, 1, 2, 4, 8) and column chunk of the y / z sweeps
+        chunk[1], chunk[2] in (0, 8, 16, 32, 64); 0 keeps each domain's single-domain rule."""
         ch = (C.c_int * 3)(*chunk)
         check(lib().pcvof_batch_set_tiles(self._b, C.cast(ch, _vp)))
 

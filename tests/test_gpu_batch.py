@@ -101,12 +101,13 @@ def test_batch_first_domains_match_oracle(pc):
     b.close()
 
 
-@pytest.mark.parametrize("chunk", [8, 16, 32, 64])
+@pytest.mark.parametrize("chunk", [(0, 8), (1, 16), (2, 32), (4, 64), (8, 0)])
 def test_batch_tile_choices_give_the_same_fields(pc, chunk):
+    """Rows per x wavefront and y / z column chunks (0: the single-domain rules)."""
     wls = _workloads()
     ref = _singles(pc, wls, 3)
     b = _batch(pc, wls)
-    b.set_tiles(chunk=[0, chunk, chunk])
+    b.set_tiles(chunk=[chunk[0], chunk[1], chunk[1]])
     for _ in range(3):
         b.step([wl.dt for wl in wls], use_graph=True)
     for d, (c, e, _) in zip(b.domains, ref):
@@ -121,7 +122,7 @@ def test_batch_autotune_keeps_the_state(pc):
     b = _batch(pc, wls)
     b.step([wl.dt for wl in wls])
     chosen = b.autotune([wl.dt for wl in wls], reps=2)
-    assert chosen["chunk"][0] == 0 and all(c in (0, 8, 16, 32, 64) for c in chosen["chunk"][1:])
+    assert chosen["chunk"][0] in (0, 1, 2, 4, 8) and all(c in (0, 8, 16, 32, 64) for c in chosen["chunk"][1:])
     b.step([wl.dt for wl in wls], use_graph=True)
     for d, (c, e, _) in zip(b.domains, ref):
         assert np.array_equal(d.vof().cpu().numpy(), c)
@@ -155,6 +156,9 @@ def test_batch_errors(pc):
     assert ex.value.code == -7
     with pytest.raises(pc.PcvofError) as ex:
         b.set_tiles(chunk=[0, 12, 16])
+    assert ex.value.code == -1
+    with pytest.raises(pc.PcvofError) as ex:
+        b.set_tiles(chunk=[16, 0, 0])  # at most 8 rows per x wavefront
     assert ex.value.code == -1
     with pytest.raises(pc.PcvofError):
         pc.Batch([_spec(pc, wls[0]), _spec(pc, wls[1], "mixed")])  # mixed precisions
