@@ -456,21 +456,24 @@ __device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a, c
         }
     };
     unsigned pos_base = nfirst;  // list position of the next step's first listed face
+    // The stencils of a row's faces read staged positions up to (x1 - x0) + 4, so chunk K is
+    // staged only if that reaches it.
+    const int klast = (x1 - x0) + 4 >= XW * K ? K : K - 1;
     if (nrows > 0) load_chunk(R0, 0);
     for (int r = 0; r < nrows; ++r) {
         const int R = R0 + r;
         const long rb = (long)R * nx;
         for (int j = 0; j <= K; ++j) {
-            {  // stage chunk j
+            if (j <= klast) {  // stage chunk j
                 const int q = (64 * j + lane) & (XRING - 1);
                 const double cj = pc, ej = pe;
                 s_c[wave][q] = cj;
                 s_e[wave][q] = ej;
                 s_T[wave][q] = ej / cp_of(d, cj);
             }
-            if (j < K)
+            if (j < klast)
                 load_chunk(R, j + 1);
-            else if (r + 1 < nrows)
+            else if (j == klast && r + 1 < nrows)
                 load_chunk(R + 1, 0);
             const double u = (double)pu, ec_own = (double)pec;
             const uint8_t cc_own = pcc;
