@@ -11,10 +11,10 @@ Prints one JSON line: whole-job cell-updates/s of the FP64 path over the timed s
 algorithmic bytes per launch over its average duration, measured with HIP events on
 the library's stream over as many steps again, right after the timed ones), the same
 run in the mixed-precision mode (rate, speedup, roofline, volume drift and difference
-from the FP64 fractions), the 128^3 LeVeque and 256^3 bubble workloads (with phase
-change, the liquid-velocity extension and the energy diffusion) as extra keys with the
-energy-flux and split ablations, and the oracle timed on the host's cores on a bounded
-sample.
+from the FP64 fractions), the 128^3 LeVeque (with its shape error after one period of
+the deformation) and 256^3 bubble workloads (with phase change, the liquid-velocity
+extension and the energy diffusion) as extra keys with the energy-flux and split
+ablations, and the oracle timed on the host's cores on a bounded sample.
 """
 import argparse
 import json
@@ -382,6 +382,38 @@ def split_ablation(pcvof, torch, wl, steps=200, timed_steps=50):
     return out
 
 
+def period_shape_error(pcvof, torch, wl):
+    """One period T of the LeVeque deformation (its time scale cos(pi t / T) reverses the
+    flow at T / 2, so the exact field after T is the initial one): the L1 shape error
+    sum |c(T) - c(0)| h^3, also relative to the initial volume, the relative volume change
+    and the time of the wl.steps steps, for the FP64 and mixed-precision paths."""
+    hv = wl.h ** wl.ndim
+    v0 = math.fsum(wl.c.ravel().tolist()) * hv
+    scales = [wl.u_scale(k) for k in range(wl.steps)]
+    out = {"workload": wl.name, "steps": wl.steps, "period": round(wl.steps * wl.dt, 6)}
+    for prec in ("fp64", "mixed"):
+        spec = pcvof.DomainSpec(shape=wl.shape, h=wl.h, ndim=wl.ndim, bc=wl.bc, cp_l=wl.cp_l, cp_g=wl.cp_g,
+                                normal=wl.normal, precision=prec)
+        d = pcvof.Domain(spec)
+        d.set_vof(wl.c)
+        d.set_energy(wl.e)
+        d.set_velocity(wl.u, wl.v, wl.w)
+        stream = torch.cuda.current_stream()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        d.steps(wl.steps, wl.dt, u_scale=scales)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        c = d.vof().cpu().numpy()
+        l1 = math.fsum(np.abs(c - wl.c).ravel().tolist()) * hv
+        v1 = math.fsum(c.ravel().tolist()) * hv
+        out[prec] = {"l1": l1, "l1_rel": l1 / v0, "vol_change_rel": (v1 - v0) / v0,
+                     "ms": t0.elapsed_time(t1)}
+        del d
+        torch.cuda.empty_cache()
+    return out
+
+
 def extension_timing(pcvof, torch, wl, rho_g, calls=5):
     """The liquid-velocity extension (section 3.3.1) on the workload's fractions and
     mass flux: wall time per pcvof_extend_velocity call (labels, compaction, assembly,
@@ -641,6 +673,8 @@ def main():
             if "mixed" in r:
                 keep["mixed"] = {k: r["mixed"][k] for k in ("value", "ms_per_step", "speedup_vs_fp64",
                                                             "volume_drift", "c_vs_fp64")}
+            if name == "leveque128":
+                keep["period_shape_error"] = period_shape_error(pcvof, torch, xw)
             if name == "bubble256":
                 # vapour density and conductivities of the paper's superheated-bubble case
                 keep["extension"] = extension_timing(pcvof, torch, xw, 0.25)
@@ -655,6 +689,8 @@ def main():
     elif args.workload == "leveque128" and not args.no_ablation:
         out["energy_flux_ablation"] = energy_flux_ablation(pcvof, torch)
         out["split_ablation"] = split_ablation(pcvof, torch, wl)
+    if args.workload.startswith("leveque"):
+        out["period_shape_error"] = period_shape_error(pcvof, torch, wl)
     if args.workload == "bubble256":
         out["extension"] = extension_timing(pcvof, torch, wl, 0.25)
         out["diffusion"] = diffusion_timing(pcvof, torch, wl, 0.07, 0.007)
