@@ -103,7 +103,7 @@ pcv::Dom make_dom(const pcvof_grid& g, const pcvof_params& p) {
     d.eps = p.precision == PCVOF_PREC_MIXED ? fmax(p.eps_mixed, kMixedEps) : p.eps_mixed;
     d.weno_eps = p.weno_eps;
     d.normal = p.normal;
-    d.wpr = (g.nx + pcv::kMaskCpwX - 1) / pcv::kMaskCpwX;
+    d.wpr = (g.nx + 63) / 64;
     d.ncons = p.energy_flux == PCVOF_EFLUX_NONCONSERVATIVE ? 1 : 0;
     d.split = p.split == PCVOF_SPLIT_LE ? 1 : 0;
     return d;
@@ -158,7 +158,6 @@ struct pcvof_handle {
     int cur;                 // index of the current fraction and energy buffers
     int mcur;                // index of the current mixed-cell mask (step 2 updates the
                              // fractions in place but writes a new mask)
-    int mask_cpw;            // cells per word of the current mask
     bool has_vof, has_energy, has_vel, has_mdot;
     double umax[3];          // max |u_f| per axis, from set_velocity
     long step;
@@ -338,7 +337,6 @@ int pcvof_create(const pcvof_grid* grid, const pcvof_params* params, void* d_wor
     h->stream = (hipStream_t)hip_stream;
     h->cur = 0;
     h->mcur = 0;
-    h->mask_cpw = pcv::kMaskCpw;
     h->batch_view = false;
     h->has_vof = h->has_energy = h->has_vel = h->has_mdot = false;
     h->umax[0] = h->umax[1] = h->umax[2] = 0.0;
@@ -377,7 +375,6 @@ int pcvof_set_vof(pcvof_handle* h, const double* c, int mem) {
     if (f & 1u) return fail(PCVOF_ERR_NONFINITE, "volume fraction has NaN or Inf");
     if (f & 2u) return fail(PCVOF_ERR_BOUNDS, "volume fraction outside [0,1]");
     HIP_TRY(pcv::launch_classify(h->d, h->c(h->cur), h->mask(h->mcur), h->stream));
-    h->mask_cpw = pcv::kMaskCpw;
     h->has_vof = true;
     return PCVOF_OK;
 }
@@ -486,7 +483,6 @@ int pcvof_sweep(pcvof_handle* h, int axis, double dt, double u_scale) {
     io.c = h->c(h->cur);
     io.e = h->e(h->cur);
     io.mask = h->mask(h->mcur);
-    io.mask_cpw = h->mask_cpw;
     io.mask_out = h->mask(1 - h->mcur);
     io.cc = h->cc();
     io.ec = h->ec();
@@ -507,7 +503,6 @@ int pcvof_sweep(pcvof_handle* h, int axis, double dt, double u_scale) {
     h->first_pending = false;
     h->cur = nxt;
     h->mcur = 1 - h->mcur;
-    h->mask_cpw = axis == 0 ? pcv::kMaskCpwX : pcv::kMaskCpw;
     h->sweeps_done++;
     h->last_slot = slot;
     h->last_sweep = slot;
@@ -526,7 +521,6 @@ int pcvof_phase_change(pcvof_handle* h, double dt) {
     io.c = h->c(h->cur);
     io.e = h->e(h->cur);
     io.mask = h->mask(h->mcur);
-    io.mask_cpw = h->mask_cpw;
     io.mask_out = h->mask(1 - h->mcur);
     io.mdot = h->mdot();
     io.dt = dt;
@@ -674,7 +668,6 @@ int pcvof_compute_mass_flux(pcvof_handle* h, double k_l, double k_g, double h_fg
     io.c = h->c(h->cur);
     io.e = h->e(h->cur);
     io.mask = h->mask(h->mcur);
-    io.mask_cpw = h->mask_cpw;
     io.plane = h->rec();
     io.q = h->fgeo();
     io.dist = dist;
@@ -996,15 +989,14 @@ int batch_build_tiles(pcvof_batch* b) {
     return PCVOF_OK;
 }
 
-// The sweep arguments of domain i for sweep s of a step starting in state (cur, mcur,
-// cpw): fraction and energy buffers, mask buffer and its cells per word.
-pcv::SweepIO batch_sweep_io(pcvof_batch* b, int i, int s, int axis, int cur, int mcur, int cpw, double dt) {
+// The sweep arguments of domain i for sweep s of a step starting in state (cur, mcur):
+// fraction and energy buffers and mask buffer.
+pcv::SweepIO batch_sweep_io(pcvof_batch* b, int i, int s, int axis, int cur, int mcur, double dt) {
     pcvof_handle* h = b->dom[i];
     pcv::SweepIO io;
     io.c = h->c(cur);
     io.e = h->e(cur);
     io.mask = h->mask(mcur);
-    io.mask_cpw = cpw;
     io.mask_out = h->mask(1 - mcur);
     io.cc = h->cc();
     io.ec = h->ec();
@@ -1028,7 +1020,6 @@ int batch_slot_for_step(pcvof_batch* b, const double* dt, int* out) {
     for (auto* h : b->dom) {
         key.push_back(h->cur);
         key.push_back(h->mcur);
-        key.push_back(h->mask_cpw);
         key.push_back(h->has_mdot ? 1 : 0);
     }
     for (int k = 0; k < kArgSlots; ++k)
@@ -1050,16 +1041,15 @@ int batch_slot_for_step(pcvof_batch* b, const double* dt, int* out) {
     std::vector<pcv::ColsumArgs> cs(b->nd);
     for (int i = 0; i < b->nd; ++i) {
         pcvof_handle* h = b->dom[i];
-        int cur = h->cur, mcur = h->mcur, cpw = h->mask_cpw;
+        int cur = h->cur, mcur = h->mcur;
         pcv::ColsumArgs c{h->part(0), h->L.maxb, {0, 0, 0, 0}, h->colsum()};
         for (int s = 0; s < b->ndim; ++s) {
             const int axis = (int)((b->step + s) % b->ndim);
-            const pcv::SweepIO io = batch_sweep_io(b, i, s, axis, cur, mcur, cpw, dt[i]);
+            const pcv::SweepIO io = batch_sweep_io(b, i, s, axis, cur, mcur, dt[i]);
             pcv::sweep_args_pack(io, args.data() + ((size_t)s * b->nd + i) * ab);
             c.nb[s] = b->dom_tiles[axis][i];
             cur = 1 - cur;
             mcur = 1 - mcur;
-            cpw = axis == 0 ? pcv::kMaskCpwX : pcv::kMaskCpw;
         }
         if (h->has_mdot) c.nb[3] = pcv::phase_launch(h->d).nblocks;
         cs[i] = c;
@@ -1086,12 +1076,10 @@ int batch_enqueue(pcvof_batch* b, int k, const double* dt, hipStream_t s_) {
         // state after the sweeps
         const int cur = b->ndim % 2 ? 1 - h->cur : h->cur;
         const int mcur = b->ndim % 2 ? 1 - h->mcur : h->mcur;
-        const int last_axis = (int)((b->step + b->ndim - 1) % b->ndim);
         pcv::PhaseIO io;
         io.c = h->c(cur);
         io.e = h->e(cur);
         io.mask = h->mask(mcur);
-        io.mask_cpw = last_axis == 0 ? pcv::kMaskCpwX : pcv::kMaskCpw;
         io.mask_out = h->mask(1 - mcur);
         io.mdot = h->mdot();
         io.dt = dt[i];
@@ -1241,7 +1229,6 @@ int pcvof_batch_advect_step(pcvof_batch* b, const double* dt, int use_graph, pcv
             h->nb[s] = b->dom_tiles[axis][i];
             h->cur = 1 - h->cur;
             h->mcur = 1 - h->mcur;
-            h->mask_cpw = axis == 0 ? pcv::kMaskCpwX : pcv::kMaskCpw;
             const double cfl = h->umax[axis] * dt[i] / h->g.h;
             if (cfl > h->step_cfl) h->step_cfl = cfl;
         }
@@ -1321,7 +1308,7 @@ int pcvof_batch_autotune(pcvof_batch* b, const double* dt, int reps, int* chosen
             // a sweep of the current state into the other buffers (state not committed)
             for (int i = 0; i < b->nd; ++i) {
                 pcvof_handle* h = b->dom[i];
-                pcv::SweepIO io = batch_sweep_io(b, i, 0, axis, h->cur, h->mcur, h->mask_cpw, dt[i]);
+                pcv::SweepIO io = batch_sweep_io(b, i, 0, axis, h->cur, h->mcur, dt[i]);
                 io.first = 1;
                 pcv::sweep_args_pack(io, args.data() + (size_t)i * ab);
             }

@@ -100,19 +100,9 @@ __device__ __forceinline__ void block_sum8(const double (&v)[8], double* out, lo
     }
 }
 
-// Bit of the mixed-cell mask (cells per word cpw, 63 or 64) for cell x of the row
-// starting at word rowword. The word index uses constant divisors (cpw is uniform over
-// the launch, so only one branch runs), not a division by a run-time value.
-__device__ __forceinline__ bool mask_bit(const uint64_t* __restrict__ mask, long rowword, int x, int cpw) {
-    int k, b;
-    if (cpw == 64) {
-        k = x >> 6;
-        b = x & 63;
-    } else {
-        k = x / 63;
-        b = x - 63 * k;
-    }
-    return (mask[rowword + k] >> b) & 1ull;
+// Bit of the mixed-cell mask for cell x of the row starting at word rowword.
+__device__ __forceinline__ bool mask_bit(const uint64_t* __restrict__ mask, long rowword, int x) {
+    return (mask[rowword + (x >> 6)] >> (x & 63)) & 1ull;
 }
 
 // Index of face f along axis of the face row through transverse cell coordinates.

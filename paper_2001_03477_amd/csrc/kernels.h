@@ -19,11 +19,8 @@ struct Dom {
     int split;     // 1: Lagrangian-explicit sweeps (donor stretched by 1 + lam_R - lam_L)
 };
 
-// Mixed-cell mask of a state: one bit per cell, rows of wpr 64-bit words, word k of a
-// row holding cells k*cpw .. k*cpw + cpw - 1 (bit = offset). Every kernel writes masks
-// with cpw = 64; the x sweep reads only such masks.
-constexpr int kMaskCpwX = 64;
-constexpr int kMaskCpw = 64;
+// Mixed-cell mask of a state: one bit per cell, rows of wpr = ceil(nx / 64) 64-bit words,
+// word k of a row holding cells 64k .. 64k + 63 (bit = offset).
 
 // Per-block partial sums written by every stage kernel: 8 doubles per block.
 // Sweeps: clip_v, clip_e, bnd_v, bnd_e, src_v, src_e, tot_v, tot_e.
@@ -44,9 +41,8 @@ int max_partial_blocks(const Dom& d);
 struct SweepIO {
     const double* c;
     const double* e;
-    const uint64_t* mask;      // mixed cells of c, cells per word mask_cpw
-    int mask_cpw;
-    uint64_t* mask_out;        // mixed cells of c_out (cpw kMaskCpwX for axis 0, else kMaskCpw)
+    const uint64_t* mask;      // mixed cells of c
+    uint64_t* mask_out;        // mixed cells of c_out
     uint8_t* cc;
     void* ec;                  // double, or float when mixed
     int first;                 // also freeze c_c and e_c of the step (the prologue)
@@ -62,7 +58,7 @@ struct SweepIO {
     hipEvent_t ev_start = nullptr;  // if set: events recorded with the kernel's dispatch
     hipEvent_t ev_stop = nullptr;
 };
-// Mask of the mixed cells of c (cpw kMaskCpw), after the fractions were set.
+// Mask of the mixed cells of c, after the fractions were set.
 hipError_t launch_classify(const Dom& d, const double* c, uint64_t* mask, hipStream_t s);
 
 // A direction sweep is one launch (geometry of the mixed donors inside each tile).
@@ -95,9 +91,8 @@ int min_chunk();
 struct PhaseIO {
     double* c;                 // updated in place
     double* e;                 // updated in place
-    const uint64_t* mask;      // mixed cells of c, cells per word mask_cpw
-    int mask_cpw;
-    uint64_t* mask_out;        // mixed cells after the step (same layout as mask)
+    const uint64_t* mask;      // mixed cells of c
+    uint64_t* mask_out;        // mixed cells after the step
     const double* mdot;
     double dt, h;
     double* rec;
@@ -147,7 +142,6 @@ struct MassFluxIO {
     const double* c;
     const double* e;
     const uint64_t* mask;
-    int mask_cpw;
     double* plane;
     double* q;
     double* dist;   // may be null

@@ -60,13 +60,13 @@ __device__ __forceinline__ double mf_dot(const double* n, double dx0, double dx1
 }
 
 __global__ void __launch_bounds__(256) k_mf_plane(Dom d, const double* __restrict__ c, const uint64_t* __restrict__ mask,
-                                                  int cpw, double* __restrict__ plane) {
+                                                  double* __restrict__ plane) {
     const int x = blockIdx.x * 64 + threadIdx.x;
     const int y = blockIdx.y * 4 + threadIdx.y;
     const int z = blockIdx.z;
     if (x >= d.n[0] || y >= d.n[1]) return;
     const long row = (long)z * d.n[1] + y;
-    if (!mask_bit(mask, row * d.wpr, x, cpw)) return;
+    if (!mask_bit(mask, row * d.wpr, x)) return;
     const long id = row * d.n[0] + x;
     double c27[27];
     gather27(d, c, x, y, z, c27);
@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(256) k_mf_plane(Dom d, const double* __restric
 }
 
 __global__ void __launch_bounds__(256) k_mf_pure(Dom d, const double* __restrict__ c, const double* __restrict__ e,
-                                                 const uint64_t* __restrict__ mask, int cpw,
+                                                 const uint64_t* __restrict__ mask,
                                                  const double* __restrict__ plane, double h, double* __restrict__ q,
                                                  double* __restrict__ dist) {
     const int x = blockIdx.x * 64 + threadIdx.x;
@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(256) k_mf_pure(Dom d, const double* __restrict
     const long row = (long)z * d.n[1] + y;
     const long id = row * d.n[0] + x;
     double qv = __builtin_nan(""), dv = __builtin_nan("");
-    if (!mask_bit(mask, row * d.wpr, x, cpw)) {
+    if (!mask_bit(mask, row * d.wpr, x)) {
         const int rz = d.ndim == 2 ? 0 : kMfR;
         bool found = false;
         double best = 0.0, dbest = 0.0;
@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(256) k_mf_pure(Dom d, const double* __restrict
                 for (int ox = -kMfR; ox <= kMfR; ++ox) {
                     long mrow;
                     int mx;
-                    if (!mf_pos(d, x, y, z, ox, oy, oz, mrow, mx) || !mask_bit(mask, mrow * d.wpr, mx, cpw)) continue;
+                    if (!mf_pos(d, x, y, z, ox, oy, oz, mrow, mx) || !mask_bit(mask, mrow * d.wpr, mx)) continue;
                     const long mid = mrow * d.n[0] + mx;
                     // from the mixed cell's origin to this cell's centre
                     const double dx0 = -ox + 0.5, dx1 = -oy + 0.5, dx2 = d.ndim == 2 ? 0.0 : -oz + 0.5;
@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(256) k_mf_pure(Dom d, const double* __restrict
 }
 
 __global__ void __launch_bounds__(256) k_mf_mdot(Dom d, const double* __restrict__ c, const uint64_t* __restrict__ mask,
-                                                 int cpw, const double* __restrict__ plane,
+                                                 const double* __restrict__ plane,
                                                  const double* __restrict__ q, double k_l, double k_g, double h_fg,
                                                  double* __restrict__ mdot) {
     const int x = blockIdx.x * 64 + threadIdx.x;
@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(256) k_mf_mdot(Dom d, const double* __restrict
     const long row = (long)z * d.n[1] + y;
     const long id = row * d.n[0] + x;
     double out = 0.0;
-    if (mask_bit(mask, row * d.wpr, x, cpw)) {
+    if (mask_bit(mask, row * d.wpr, x)) {
         const int rz = d.ndim == 2 ? 0 : kMfR;
         const double nv[3] = {plane[4 * id + 0], plane[4 * id + 1], plane[4 * id + 2]};
         double wg = 0.0, wl = 0.0, gg = 0.0, gl = 0.0;
@@ -182,14 +182,14 @@ __global__ void __launch_bounds__(256) k_mf_mdot(Dom d, const double* __restrict
 
 hipError_t launch_mass_flux(const Dom& d, const MassFluxIO& io, hipStream_t s) {
     const Launch L = cell_launch(d);
-    hipLaunchKernelGGL(k_mf_plane, L.grid, L.block, 0, s, d, io.c, io.mask, io.mask_cpw, io.plane);
+    hipLaunchKernelGGL(k_mf_plane, L.grid, L.block, 0, s, d, io.c, io.mask, io.plane);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k_mf_pure, L.grid, L.block, 0, s, d, io.c, io.e, io.mask, io.mask_cpw, io.plane, io.h, io.q,
+    hipLaunchKernelGGL(k_mf_pure, L.grid, L.block, 0, s, d, io.c, io.e, io.mask, io.plane, io.h, io.q,
                        io.dist);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k_mf_mdot, L.grid, L.block, 0, s, d, io.c, io.mask, io.mask_cpw, io.plane, io.q, io.k_l,
+    hipLaunchKernelGGL(k_mf_mdot, L.grid, L.block, 0, s, d, io.c, io.mask, io.plane, io.q, io.k_l,
                        io.k_g, io.h_fg, io.mdot);
     return hipGetLastError();
 }

@@ -32,7 +32,7 @@ namespace {
 constexpr int kPhaseBlock = 256;
 
 // Word k of the mask row (z, y), located from the flat word index gw (rows of wpr
-// words; only the first ceil(nx / cpw) words of a row are used).
+// words).
 struct Seg {
     long row;   // z * ny + y
     int y, z;
@@ -41,33 +41,24 @@ struct Seg {
     int n;      // cells in the segment (0: no segment)
 };
 
-__device__ __forceinline__ Seg seg_of(const Dom& d, long gw, int cpw) {
+__device__ __forceinline__ Seg seg_of(const Dom& d, long gw) {
     Seg s;
     const long nrows = (long)(d.ndim == 2 ? 1 : d.n[2]) * d.n[1];
     s.row = gw / d.wpr;
     s.k = (int)(gw - s.row * d.wpr);
     s.z = (int)(s.row / d.n[1]);
     s.y = (int)(s.row - (long)s.z * d.n[1]);
-    s.x0 = s.k * cpw;
-    s.n = (s.row < nrows && s.x0 < d.n[0]) ? min(cpw, d.n[0] - s.x0) : 0;
+    s.x0 = s.k * 64;
+    s.n = (s.row < nrows && s.x0 < d.n[0]) ? min(64, d.n[0] - s.x0) : 0;
     return s;
 }
 
 // The bits of a segment of n cells (1 <= n <= 64).
 __device__ __forceinline__ uint64_t seg_bits(int n) { return n == 64 ? ~0ull : (1ull << n) - 1ull; }
 
-// Bit of cell x in the mask row starting at word rowword (cpw is uniform over the
-// launch: one branch runs).
-__device__ __forceinline__ uint64_t bit_at(const uint64_t* __restrict__ mask, long rowword, int x, int cpw) {
-    int k, b;
-    if (cpw == 64) {
-        k = x >> 6;
-        b = x & 63;
-    } else {
-        k = x / 63;
-        b = x - 63 * k;
-    }
-    return (mask[rowword + k] >> b) & 1ull;
+// Bit of cell x in the mask row starting at word rowword.
+__device__ __forceinline__ uint64_t bit_at(const uint64_t* __restrict__ mask, long rowword, int x) {
+    return (mask[rowword + (x >> 6)] >> (x & 63)) & 1ull;
 }
 
 // Mask word k of the row (z, y) shifted by one cell along axis (1 or 2) in direction
@@ -91,13 +82,13 @@ __device__ __forceinline__ uint64_t row_word(const Dom& d, const uint64_t* __res
 // cell: in the neighbouring word of the row, wrapped on a periodic x axis, 0 beyond an
 // outflow boundary.
 __device__ __forceinline__ uint64_t edge_bit(const Dom& d, const uint64_t* __restrict__ mask, const Seg& s,
-                                             int cpw, int sg) {
+                                             int sg) {
     int x = sg < 0 ? s.x0 - 1 : s.x0 + s.n;
     if (x < 0 || x >= d.n[0]) {
         if (d.bc[0] == 1) return 0ull;
         x = x < 0 ? x + d.n[0] : x - d.n[0];
     }
-    return bit_at(mask, s.row * d.wpr, x, cpw);
+    return bit_at(mask, s.row * d.wpr, x);
 }
 
 // The set bits of the 64 lanes' words, numbered lane by lane and, within a word, in bit
@@ -155,11 +146,11 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t v, int j) {
 }
 
 __global__ void __launch_bounds__(kPhaseBlock)
-k_phase_recon(Dom d, const double* __restrict__ c, const uint64_t* __restrict__ mask, int cpw,
+k_phase_recon(Dom d, const double* __restrict__ c, const uint64_t* __restrict__ mask,
               const double* __restrict__ mdot, double dt_h, double* __restrict__ rec) {
     const int lane = threadIdx.x & 63;
     const long gw = (long)blockIdx.x * kPhaseBlock + threadIdx.x;
-    const Seg s = seg_of(d, gw, cpw);
+    const Seg s = seg_of(d, gw);
     // only the segment's own cells (bits beyond them are not cells of this word)
     const uint64_t w = s.n ? mask[gw] & seg_bits(s.n) : 0ull;
     const WaveList L = wave_list(w);
@@ -169,7 +160,7 @@ k_phase_recon(Dom d, const double* __restrict__ c, const uint64_t* __restrict__ 
         const int j = wave_list_at(L, t, &rank);
         const uint64_t wj = shfl64(w, j);
         if (t >= L.total) continue;
-        const Seg sj = seg_of(d, gw - lane + j, cpw);
+        const Seg sj = seg_of(d, gw - lane + j);
         const int x = sj.x0 + nth_bit(wj, rank);
         const long id = sj.row * d.n[0] + x;
         const double md = mdot[id];
@@ -190,7 +181,7 @@ k_phase_recon(Dom d, const double* __restrict__ c, const uint64_t* __restrict__ 
 }
 
 __global__ void __launch_bounds__(kPhaseBlock)
-k_phase_apply(Dom d, double* __restrict__ c, double* __restrict__ e, const uint64_t* __restrict__ mask, int cpw,
+k_phase_apply(Dom d, double* __restrict__ c, double* __restrict__ e, const uint64_t* __restrict__ mask,
               const double* __restrict__ mdot, double dt_h, const double* __restrict__ rec,
               uint64_t* __restrict__ mask_out, double* __restrict__ part, long part_stride) {
     constexpr int kWaves = kPhaseBlock / 64;
@@ -200,15 +191,15 @@ k_phase_apply(Dom d, double* __restrict__ c, double* __restrict__ e, const uint6
     __shared__ unsigned long long s_out[kPhaseBlock];
     const int lane = threadIdx.x & 63;
     const long gw = (long)blockIdx.x * kPhaseBlock + threadIdx.x;
-    const Seg s = seg_of(d, gw, cpw);
+    const Seg s = seg_of(d, gw);
     uint64_t todo = 0ull;
     {
         uint64_t w = 0ull, nb[6] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
         if (s.n) {
             const uint64_t valid = seg_bits(s.n);
             w = mask[gw] & valid;
-            nb[0] = ((w << 1) | edge_bit(d, mask, s, cpw, -1)) & valid;                    // x-
-            nb[1] = ((w >> 1) | (edge_bit(d, mask, s, cpw, +1) << (s.n - 1))) & valid;     // x+
+            nb[0] = ((w << 1) | edge_bit(d, mask, s, -1)) & valid;                    // x-
+            nb[1] = ((w >> 1) | (edge_bit(d, mask, s, +1) << (s.n - 1))) & valid;     // x+
             nb[2] = row_word(d, mask, s, 1, -1) & valid;                                   // y-
             nb[3] = row_word(d, mask, s, 1, +1) & valid;                                   // y+
             nb[4] = row_word(d, mask, s, 2, -1) & valid;                                   // z-
@@ -231,7 +222,7 @@ k_phase_apply(Dom d, double* __restrict__ c, double* __restrict__ e, const uint6
         const uint64_t tj = shfl64(todo, j);
         if (t >= L.total) continue;
         const int sw = wbase + j;
-        const Seg sj = seg_of(d, gw - lane + j, cpw);
+        const Seg sj = seg_of(d, gw - lane + j);
         const int b = nth_bit(tj, rank);
         const int x = sj.x0 + b;
         const long id = sj.row * d.n[0] + x;
@@ -298,10 +289,10 @@ Launch phase_launch(const Dom& d) {
 hipError_t launch_phase(const Dom& d, const PhaseIO& io, hipStream_t s) {
     const double dt_h = io.dt / io.h;
     const Launch L = phase_launch(d);
-    hipLaunchKernelGGL(k_phase_recon, L.grid, L.block, 0, s, d, io.c, io.mask, io.mask_cpw, io.mdot, dt_h, io.rec);
+    hipLaunchKernelGGL(k_phase_recon, L.grid, L.block, 0, s, d, io.c, io.mask, io.mdot, dt_h, io.rec);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k_phase_apply, L.grid, L.block, 0, s, d, io.c, io.e, io.mask, io.mask_cpw, io.mdot, dt_h,
+    hipLaunchKernelGGL(k_phase_apply, L.grid, L.block, 0, s, d, io.c, io.e, io.mask, io.mdot, dt_h,
                        io.rec, io.mask_out, io.part, io.part_stride);
     if (io.nblocks) *io.nblocks = L.nblocks;
     return hipGetLastError();

@@ -30,7 +30,7 @@ struct SweepArgs {
     const double* c;
     const double* e;
     const uint64_t* mask;  // mixed cells of c
-    int mask_cpw;
+    int first;             // (here, not last: this order spills fewer scalar registers)
     uint64_t* mask_out;    // mixed cells of c_out
     uint8_t* cc;       // written by the first sweep of a step, read by the others
     void* ec;          // double, or float in the mixed-precision mode
@@ -41,10 +41,9 @@ struct SweepArgs {
     double* e_out;
     double* part;        // quantity-major partial table of this stage
     long part_stride;
-    int first;
 };
 
-// Mask of the mixed cells of c (cpw = 64), after the fractions were set from outside.
+// Mask of the mixed cells of c, after the fractions were set from outside.
 __global__ void __launch_bounds__(256) k_classify(Dom d, const double* __restrict__ c, uint64_t* __restrict__ mask) {
     const int x = blockIdx.x * 64 + threadIdx.x;
     const int y = blockIdx.y * 4 + threadIdx.y;
@@ -237,7 +236,7 @@ static_assert(TFCAP <= 255, "saturated list positions fit 8 bits");
 // position is loaded and divided once per row; the chunk after the current one is
 // staged before its faces are computed (the WENO5 stencil of the last lane reaches 3
 // cells ahead) and loaded one chunk earlier. The output mask words are the chunks
-// (cpw = 64). Before the walk the wavefront lists the faces of all its rows with a mixed
+// (64 cells). Before the walk the wavefront lists the faces of all its rows with a mixed
 // cell on either side (in walk order: first faces, then row by row, chunk by chunk) and
 // reconstructs their mixed donors 64 at a time; the walk recomputes each face's list
 // position from the same mask words, so no per-face index is stored.
@@ -282,7 +281,7 @@ inline XPlan x_plan_rule(int nx, int ny, int nz) {
 }
 inline int x_plan_pack(const XPlan& p) { return p.rows | (p.chunks << 8); }
 
-// Mixed bit of cell x (ghost positions mapped) in row R of the input mask (cpw = 64).
+// Mixed bit of cell x (ghost positions mapped) in row R of the input mask.
 __device__ __forceinline__ bool mask64(const Dom& d, const uint64_t* __restrict__ mask, int R, int x) {
     const int xm = wrap(x, d.n[0], d.bc[0]);
     return (mask[(long)R * d.wpr + (xm >> 6)] >> (xm & 63)) & 1ull;
@@ -539,7 +538,7 @@ __device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a, c
                     }
                 }
             }
-            // mask of the output: the chunk is one word (cpw = 64)
+            // mask of the output: the chunk is one word
             const unsigned long long bits = __ballot(mx);
             if (lane == 0) a.mask_out[(long)R * d.wpr + (x0 >> 6) + k] = bits;
             wave_lds_order();
@@ -577,7 +576,7 @@ __device__ __forceinline__ void sweep_t_body(const Dom& d, const SweepArgs& a, i
 
     // Geometry: the faces s0 .. s1 of the wavefront's columns with a mixed cell on either
     // side, in face order and lane order (item = face offset:lane). The 64 columns of a
-    // wavefront are one mask word per cell of the sweep axis (cpw = 64), so the words of
+    // wavefront are one mask word per cell of the sweep axis, so the words of
     // cells s0-1 .. s1 are staged in LDS and a face's list is the lanes of (w_j | w_j+1).
     // The mixed donors of the listed faces are reconstructed 64 at a time (list position
     // q: flux in s_F[q] below TFCAP, else in fgeo at the face); s_idx keeps each listed
@@ -725,7 +724,7 @@ __device__ __forceinline__ void sweep_t_body(const Dom& d, const SweepArgs& a, i
                 }
             }
         }
-        if (f > s0) {  // mask of the output: the wavefront's 64 cells are one word (cpw = 64)
+        if (f > s0) {  // mask of the output: the wavefront's 64 cells are one word
             const unsigned long long bits = __ballot(mx);
             if (lane == 0 && t < nt) {
                 const long row = AX == 1 ? (long)t * d.n[1] + (f - 1) : (long)(f - 1) * d.n[1] + t;
@@ -948,8 +947,8 @@ int max_chunk() { return TCH; }
 int min_chunk() { return kMinChunk; }
 
 void sweep_args_pack(const SweepIO& io, void* out) {
-    SweepArgs a{io.c,   io.e,    io.mask, io.mask_cpw, io.mask_out, io.cc,   io.ec,          io.vel,
-                io.kfac, io.fgeo, io.c_out, io.e_out,   io.part,     io.part_stride, io.first};
+    SweepArgs a{io.c,    io.e,     io.mask,  io.first, io.mask_out, io.cc,   io.ec,
+                io.vel,  io.kfac,  io.fgeo,  io.c_out, io.e_out,    io.part, io.part_stride};
     memcpy(out, &a, sizeof a);
 }
 
@@ -988,8 +987,8 @@ int sweep_tiles(const Dom& d, int axis, bool mixed, int chunk, int dom, BatchTil
 hipError_t launch_sweep(const Dom& d, int axis, const SweepIO& io, hipStream_t s) {
     int chunk = 0;
     const Launch L = sweep_launch(d, axis, io.mixed != 0, &chunk);
-    SweepArgs a{io.c,   io.e,    io.mask, io.mask_cpw, io.mask_out, io.cc,   io.ec,          io.vel,
-                io.kfac, io.fgeo, io.c_out, io.e_out,   io.part,     io.part_stride, io.first};
+    SweepArgs a{io.c,    io.e,     io.mask,  io.first, io.mask_out, io.cc,   io.ec,
+                io.vel,  io.kfac,  io.fgeo,  io.c_out, io.e_out,    io.part, io.part_stride};
     if (io.mixed)
         launch_sweep_kernel<true>(d, axis, L, chunk, a, s, io.ev_start, io.ev_stop);
     else

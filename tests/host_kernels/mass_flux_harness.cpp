@@ -72,7 +72,7 @@ int main(int argc, char** argv) {
     double* mdot = alloc<double>(N);
     double* dist = alloc<double>(N);
     pcv::MassFluxIO io;
-    io.c = c; io.e = e; io.mask = mask; io.mask_cpw = 64;
+    io.c = c; io.e = e; io.mask = mask;
     io.plane = rec; io.q = fgeo; io.dist = dist; io.mdot = mdot;
     io.h = h; io.k_l = k_l; io.k_g = k_g; io.h_fg = h_fg;
     const pcv::Launch L = pcv::cell_launch(d);

@@ -1,11 +1,11 @@
 """GPU parity of step 2 (section 3.3.2, with the latent correction of section 3.4.1) at
 the edges of its traversal. The library visits the interface cells through the mixed-cell
-bitmask, one 64-bit word (a row segment of 63 or 64 cells) per lane, and updates the
-fractions and energies in place: these cases put interfaces across segment and row
-boundaries, on periodic wraps and outflow sides, in 2D and on grids narrower than a
-segment, with both mask layouts (the last sweep of a step alternates between x, whose
-mask has 63 cells per word, and y / z, 64 per word). Bar: 1e-12 per cell against the
-oracle; the step totals equal the sums of the fields."""
+bitmask, one 64-bit word (a row segment of 64 cells) per lane, and updates the fractions
+and energies in place: these cases put interfaces across segment and row boundaries, on
+periodic wraps and outflow sides, in 2D and on grids narrower than a segment, after each
+of the three sweep axes (the last sweep of a step alternates between x, y and z, which
+write their masks in different orders). Bar: 1e-12 per cell against the oracle; the step
+totals equal the sums of the fields."""
 import math
 
 import numpy as np
@@ -92,7 +92,7 @@ def _run(pc, shape, nd, bc, seed, steps=3, step0=0):
 @pytest.mark.parametrize("nx", [1, 2, 62, 63, 64, 65, 127, 129])
 @pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 1)])
 def test_segment_boundaries_3d(pc, nx, bc):
-    """Three steps (last sweeps z, x, y: masks of 64, 63, 64 cells per word)."""
+    """Three steps (last sweeps z, x, y)."""
     _run(pc, (6, 5, nx), 3, bc, seed=100 + nx)
 
 
