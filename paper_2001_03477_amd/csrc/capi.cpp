@@ -789,7 +789,7 @@ int pcvof_diffuse_static(pcvof_handle* h, double dt, double k_l, double k_g, dou
         return fail(PCVOF_ERR_WORKSPACE,
                     "the diffusion of %ld cells needs %zu bytes of scratch; the static scratch holds %zu "
                     "(about %zu cells): use pcvof_diffuse with a workspace",
-                    h->d.ncell, need, cap, cap / 137);
+                    h->d.ncell, need, cap, (size_t)((double)cap * (double)h->d.ncell / (double)need));
     return pcvof_diffuse(h, dt, k_l, k_g, rel_tol, max_iter, ws, cap, T_out, mem, info);
 }
 
@@ -826,16 +826,16 @@ int pcvof_diffuse(pcvof_handle* h, double dt, double k_l, double k_g, double rel
     if (!isfinite(bb) || !isfinite(rr)) return fail(PCVOF_ERR_NONFINITE, "diffusion: non-finite operator or state");
     int iters = 0;
     bool conv = rr <= rel_tol * rel_tol * bb;
+    // one multigrid-preconditioned iteration takes a few smoothing passes over the cells,
+    // far more than the host's look at the residual after each of them
     while (!conv && iters < max_iter) {
         HIP_TRY(pcv::launch_diff_iteration(h->d, io, h->stream));
         ++iters;
-        if (iters % 4 == 0 || iters == max_iter) {
-            HIP_TRY(hipMemcpyAsync(sc, io.scal, sizeof sc, hipMemcpyDeviceToHost, h->stream));
-            HIP_TRY(hipStreamSynchronize(h->stream));
-            rr = sc[pcv::kBiRr];
-            if (!isfinite(rr)) break;
-            conv = rr <= rel_tol * rel_tol * bb;
-        }
+        HIP_TRY(hipMemcpyAsync(sc, io.scal, sizeof sc, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        rr = sc[pcv::kBiRr];
+        if (!isfinite(rr)) break;
+        conv = rr <= rel_tol * rel_tol * bb;
     }
     const double rel = bb > 0.0 ? sqrt(rr / bb) : 0.0;
     if (!conv)

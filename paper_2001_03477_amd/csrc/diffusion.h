@@ -28,6 +28,17 @@ struct Rows {
     RowConst rc;
 };
 
+// Multigrid preconditioner: levels of 2 x 2 x 2 aggregates (2 x 2 in 2D) down to at most
+// 8 cells along the shortest axis; level l > 0 holds an explicit seven-point operator
+// (diagonal, six neighbour coefficients slot-major in the sides' order x-, x+, y-, y+,
+// z-, z+) and its vectors (right-hand side b, iterate x, scratch y).
+constexpr int kMgMaxLevels = 12;
+struct MgLevel {
+    int n[3];
+    long ncell;
+    double *diag, *off, *b, *x, *y;
+};
+
 // Views into the caller's diffusion workspace (diff_layout gives the offsets).
 struct DiffIO {
     uint8_t* kind;  // per cell: bit 0 liquid, bit 1 row stored (an interface side), bits 2-7 wall sides
@@ -38,16 +49,22 @@ struct DiffIO {
     double* part;   // 3 partial sums per block of the fixed grid
     double* scal;   // kBi* scalars
     Rows rows;      // the operator as the kernels read it (rc set by launch_diff_start)
+    double *mgx0, *mgr0;         // level-0 iterate and residual of the V-cycle
+    int mg_levels;               // levels including the cells' own (1: Jacobi steps only)
+    MgLevel mg[kMgMaxLevels];    // mg[l], l >= 1: the coarse levels
 };
 
 struct DiffLayout {
-    size_t kind, diag, off, b, vec[9], part, scal, bytes;
+    size_t kind, diag, off, b, vec[9], part, scal, mgx0, mgr0, bytes;
+    int mg_levels;
+    int mg_n[kMgMaxLevels][3];
+    size_t mg_diag[kMgMaxLevels], mg_off[kMgMaxLevels], mg_b[kMgMaxLevels], mg_x[kMgMaxLevels], mg_y[kMgMaxLevels];
 };
 DiffLayout diff_layout(const Dom& d);
 DiffIO diff_views(const DiffLayout& L, void* ws);
 
-// Operator, right-hand side and x = T* from the state (c, e); BiCGSTAB start:
-// scal[kBiRr] = |r|^2, scal[kBiBb] = |b|^2.
+// Operator, right-hand side and x = T* from the state (c, e), the coarse operators of the
+// multigrid preconditioner; BiCGSTAB start: scal[kBiRr] = |r|^2, scal[kBiBb] = |b|^2.
 hipError_t launch_diff_start(const Dom& d, const double* c, const double* e, double h, double dt, double k_l,
                              double k_g, DiffIO& io, hipStream_t s);
 // One BiCGSTAB iteration (scal[kBiRr] updated).

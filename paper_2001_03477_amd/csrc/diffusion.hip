@@ -218,13 +218,16 @@ __device__ __forceinline__ int nb_pos(int v, int n, int bc) {
 // registers; the x and y neighbours are rows of the same block (coalesced, in cache).
 // Per row the diagonal first, then the sides in the order x-, x+, y-, y+, z-, z+. MODE 0: start
 // (r = b - A x, rhat = r, p = v = 0; partials rhat.r, r.r, b.b); 1: y = A x with the
-// partial rhat.y; 2: y = A x with the partials y.s, y.y.
+// partial rhat.y; 2: y = A x with the partials y.s, y.y; 3: y = b - A x; 4: one damped
+// Jacobi step y = x + w (b - A x) / diag (3 and 4: the preconditioner's level 0, no
+// partials).
 template <int MODE>
 __global__ void __launch_bounds__(kDiffBlock) k_bi_march(Dom d, Rows m, const double* __restrict__ xin,
                                                          double* __restrict__ y, const double* __restrict__ rh,
                                                          const double* __restrict__ sv, const double* __restrict__ b,
                                                          double* __restrict__ rhw, double* __restrict__ p,
-                                                         double* __restrict__ v, double* __restrict__ part) {
+                                                         double* __restrict__ v, double* __restrict__ part,
+                                                         double w) {
     const int nx = d.n[0], ny = d.n[1], nz = d.n[2];
     const int x = blockIdx.x * 64 + threadIdx.x, yy = blockIdx.y * 4 + threadIdx.y;
     const int z0 = blockIdx.z * kMarch, z1 = z0 + kMarch < nz ? z0 + kMarch : nz;
@@ -256,7 +259,8 @@ __global__ void __launch_bounds__(kDiffBlock) k_bi_march(Dom d, Rows m, const do
                 kn = m.kind[zn + col];
             }
             const int sides = 2 * d.ndim;
-            double yi = row_diag(m, i, k, sides) * xcur;
+            const double dg = row_diag(m, i, k, sides);
+            double yi = dg * xcur;
             if (k & 2) {
                 for (int slot = 0; slot < sides; ++slot) {
                     const double o = m.off[(long)slot * d.ncell + i];
@@ -267,7 +271,11 @@ __global__ void __launch_bounds__(kDiffBlock) k_bi_march(Dom d, Rows m, const do
                 for (int slot = 0; slot < sides; ++slot)
                     if (!(k >> (2 + slot) & 1)) yi += o * nbv[slot];
             }
-            if (MODE == 0) {
+            if (MODE == 3) {
+                y[i] = b[i] - yi;
+            } else if (MODE == 4) {
+                y[i] = xcur + w * (b[i] - yi) / dg;
+            } else if (MODE == 0) {
                 const double ri = b[i] - yi;
                 y[i] = ri;  // r
                 rhw[i] = ri;
@@ -289,40 +297,34 @@ __global__ void __launch_bounds__(kDiffBlock) k_bi_march(Dom d, Rows m, const do
             xcur = xnext;
         }
     }
-    const long blk = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    block_sum3(s0, s1, s2, part, (int)(threadIdx.y * 64 + threadIdx.x), blk);
+    if (MODE < 3) {
+        const long blk = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        block_sum3(s0, s1, s2, part, (int)(threadIdx.y * 64 + threadIdx.x), blk);
+    }
 }
 
 #define GRID_STRIDE(i, n) for (long i = (long)blockIdx.x * kDiffBlock + threadIdx.x; i < (n); i += (long)gridDim.x * kDiffBlock)
 
-// p = r + beta (p - omega v), ph = p / diag.
-__global__ void __launch_bounds__(kDiffBlock) k_bi_dir(Dom d, const double* __restrict__ scal, Rows m,
+// p = r + beta (p - omega v) (then ph = M^-1 p by the preconditioner).
+__global__ void __launch_bounds__(kDiffBlock) k_bi_dir(Dom d, const double* __restrict__ scal,
                                                        const double* __restrict__ r, const double* __restrict__ v,
-                                                       double* __restrict__ p, double* __restrict__ ph) {
+                                                       double* __restrict__ p) {
     const double be = scal[kBiBeta], om = scal[kBiOmega];
-    GRID_STRIDE(i, d.ncell) {
-        const double pi = r[i] + be * (p[i] - om * v[i]);
-        p[i] = pi;
-        ph[i] = pi / row_diag(m, i, m.kind[i], 2 * d.ndim);
-    }
+    GRID_STRIDE(i, d.ncell) p[i] = r[i] + be * (p[i] - om * v[i]);
 }
 
-// s = r - alpha v, sh = s / diag.
-__global__ void __launch_bounds__(kDiffBlock) k_bi_half(Dom d, const double* __restrict__ scal, Rows m,
+// s = r - alpha v (then sh = M^-1 s by the preconditioner).
+__global__ void __launch_bounds__(kDiffBlock) k_bi_half(Dom d, const double* __restrict__ scal,
                                                         const double* __restrict__ r, const double* __restrict__ v,
-                                                        double* __restrict__ s, double* __restrict__ sh) {
+                                                        double* __restrict__ s) {
     const double al = scal[kBiAlpha];
-    GRID_STRIDE(i, d.ncell) {
-        const double si = r[i] - al * v[i];
-        s[i] = si;
-        sh[i] = si / row_diag(m, i, m.kind[i], 2 * d.ndim);
-    }
+    GRID_STRIDE(i, d.ncell) s[i] = r[i] - al * v[i];
 }
 
-// x += alpha ph + omega sh (sh = s / diag recomputed rather than read), r = s - omega t;
-// partials (rhat.r, r.r, 0).
-__global__ void __launch_bounds__(kDiffBlock) k_bi_update(Dom d, const double* __restrict__ scal, Rows m,
-                                                          const double* __restrict__ ph, const double* __restrict__ s,
+// x += alpha ph + omega sh, r = s - omega t; partials (rhat.r, r.r, 0).
+__global__ void __launch_bounds__(kDiffBlock) k_bi_update(Dom d, const double* __restrict__ scal,
+                                                          const double* __restrict__ ph, const double* __restrict__ sh,
+                                                          const double* __restrict__ s,
                                                           const double* __restrict__ t, const double* __restrict__ rh,
                                                           double* __restrict__ x, double* __restrict__ r,
                                                           double* __restrict__ part) {
@@ -330,8 +332,7 @@ __global__ void __launch_bounds__(kDiffBlock) k_bi_update(Dom d, const double* _
     double s0 = 0.0, s1 = 0.0;
     GRID_STRIDE(i, d.ncell) {
         const double si = s[i];
-        const double shi = si / row_diag(m, i, m.kind[i], 2 * d.ndim);  // as k_bi_half stored it
-        x[i] += al * ph[i] + om * shi;
+        x[i] += al * ph[i] + om * sh[i];
         const double ri = si - om * t[i];
         r[i] = ri;
         s0 += rh[i] * ri;
@@ -394,6 +395,184 @@ __global__ void __launch_bounds__(kDiffBlock) k_bi_reduce(const double* __restri
         scal[kBiRho] = t0;
         scal[kBiRr] = t1;
     }
+}
+
+// Multigrid preconditioner M^-1: one V(1,1) cycle over levels of 2 x 2 x 2 aggregates
+// (unsmoothed aggregation: piecewise constant prolongation P, restriction R = P^T,
+// Galerkin coarse operators R A P, built once per call), with damped Jacobi steps
+// (weight kMgOmega, each first step from zero) and kMgCoarseSweeps of them on the
+// coarsest level. Every kernel is a fixed function of its inputs (no atomics), so the
+// preconditioner, like the rest of the solve, is deterministic.
+constexpr double kMgOmega = 0.8;
+constexpr int kMgCoarseSweeps = 4;
+
+// A level's cells per axis, boundary rule per axis, dimension.
+struct MgGeom {
+    int n[3];
+    int bc[3];
+    int ndim;
+    long ncell;
+};
+
+MgGeom mg_geom(const Dom& d, const int* n) {
+    MgGeom g;
+    for (int a = 0; a < 3; ++a) {
+        g.n[a] = n[a];
+        g.bc[a] = d.bc[a];
+    }
+    g.ndim = d.ndim;
+    g.ncell = (long)n[0] * n[1] * n[2];
+    return g;
+}
+
+dim3 mg_grid(const MgGeom& g) { return dim3((g.n[0] + 63) / 64, (g.n[1] + 3) / 4, g.n[2]); }
+
+// The launch covers a level with blocks of 64 x 4 cells per plane (q: the thread's cell).
+#define MG_CELL(g, q, i)                                                                            \
+    const int q[3] = {(int)(blockIdx.x * 64 + threadIdx.x), (int)(blockIdx.y * 4 + threadIdx.y),  \
+                      (int)blockIdx.z};                                                             \
+    if (q[0] >= (g).n[0] || q[1] >= (g).n[1]) return;                                               \
+    const long i = ((long)q[2] * (g).n[1] + q[1]) * (g).n[0] + q[0];
+
+__device__ __forceinline__ long mg_index(const MgGeom& g, const int (&q)[3]) {
+    return ((long)q[2] * g.n[1] + q[1]) * g.n[0] + q[0];
+}
+
+// Neighbour of cell q on side s (x-, x+, y-, y+, z-, z+): wrapped on periodic axes, -1
+// beyond an outflow boundary.
+__device__ __forceinline__ long mg_nb(const MgGeom& g, const int (&q)[3], int s) {
+    const int axis = s >> 1;
+    int r[3] = {q[0], q[1], q[2]};
+    int v = r[axis] + ((s & 1) ? 1 : -1);
+    if (v < 0 || v >= g.n[axis]) {
+        if (g.bc[axis] != 0) return -1;
+        v = v < 0 ? v + g.n[axis] : v - g.n[axis];
+    }
+    r[axis] = v;
+    return mg_index(g, r);
+}
+
+// (A x)_i on a coarse level.
+__device__ __forceinline__ double mg_apply_row(const MgGeom& g, const double* __restrict__ diag,
+                                               const double* __restrict__ off, const double* __restrict__ x,
+                                               const int (&q)[3], long i) {
+    double y = diag[i] * x[i];
+    for (int s = 0; s < 2 * g.ndim; ++s) {
+        const long j = mg_nb(g, q, s);
+        if (j >= 0) y += off[(long)s * g.ncell + i] * x[j];
+    }
+    return y;
+}
+
+// Level 0, first Jacobi step from zero: x0 = w b / diag.
+__global__ void __launch_bounds__(kDiffBlock) k_mg_first0(Dom d, Rows m, const double* __restrict__ b,
+                                                          double* __restrict__ x0) {
+    GRID_STRIDE(i, d.ncell) x0[i] = kMgOmega * b[i] / row_diag(m, i, m.kind[i], 2 * d.ndim);
+}
+
+// Coarse level, first Jacobi step from zero: x = w b / diag.
+__global__ void __launch_bounds__(kDiffBlock) k_mg_first(MgGeom g, const double* __restrict__ diag,
+                                                         const double* __restrict__ b, double* __restrict__ x) {
+    MG_CELL(g, q, i)
+    x[i] = kMgOmega * b[i] / diag[i];
+}
+
+// Coarse level: y = b - A x.
+__global__ void __launch_bounds__(kDiffBlock) k_mg_resid(MgGeom g, const double* __restrict__ diag,
+                                                         const double* __restrict__ off, const double* __restrict__ x,
+                                                         const double* __restrict__ b, double* __restrict__ y) {
+    MG_CELL(g, q, i)
+    y[i] = b[i] - mg_apply_row(g, diag, off, x, q, i);
+}
+
+// Coarse level, one damped Jacobi step: y = x + w (b - A x) / diag.
+__global__ void __launch_bounds__(kDiffBlock) k_mg_smooth(MgGeom g, const double* __restrict__ diag,
+                                                          const double* __restrict__ off, const double* __restrict__ x,
+                                                          const double* __restrict__ b, double* __restrict__ y) {
+    MG_CELL(g, q, i)
+    y[i] = x[i] + kMgOmega * (b[i] - mg_apply_row(g, diag, off, x, q, i)) / diag[i];
+}
+
+// Restriction: bc_I = sum of rf over the aggregate I (fixed order z, y, x).
+__global__ void __launch_bounds__(kDiffBlock) k_mg_restrict(MgGeom fg, MgGeom cg, const double* __restrict__ rf,
+                                                            double* __restrict__ bc) {
+    MG_CELL(cg, q, I)
+    double sum = 0.0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                const int f[3] = {2 * q[0] + dx, 2 * q[1] + dy, 2 * q[2] + dz};
+                if (f[0] < fg.n[0] && f[1] < fg.n[1] && f[2] < fg.n[2]) sum += rf[mg_index(fg, f)];
+            }
+    bc[I] = sum;
+}
+
+// Prolongation: xf_i += xc of the aggregate holding i.
+__global__ void __launch_bounds__(kDiffBlock) k_mg_prolong(MgGeom fg, MgGeom cg, double* __restrict__ xf,
+                                                           const double* __restrict__ xc) {
+    MG_CELL(fg, q, i)
+    const int c[3] = {q[0] >> 1, q[1] >> 1, q[2] >> 1};
+    xf[i] += xc[mg_index(cg, c)];
+}
+
+// Coarse operator entries of one fine row (diagonal dg, side coefficients o[s]) of a cell
+// f of the aggregate I = f / 2: a side whose neighbour lies in I adds to the diagonal,
+// the others to I's coefficient on that side (the neighbour then lies in the aggregate
+// beyond that side, across a periodic wrap too).
+__device__ __forceinline__ void mg_accumulate(const MgGeom& fg, const int (&f)[3], double dg, const double (&o)[6],
+                                              const int (&I)[3], double& cd, double (&co)[6]) {
+    cd += dg;
+    for (int s = 0; s < 2 * fg.ndim; ++s) {
+        if (o[s] == 0.0) continue;
+        const int axis = s >> 1;
+        int v = f[axis] + ((s & 1) ? 1 : -1);
+        if (v < 0 || v >= fg.n[axis]) v = v < 0 ? v + fg.n[axis] : v - fg.n[axis];  // nonzero: periodic
+        if ((v >> 1) == I[axis]) cd += o[s];
+        else co[s] += o[s];
+    }
+}
+
+// Level 1 from the cells' operator (Rows), one thread per coarse cell, the fine rows of
+// the aggregate in the order z, y, x and each row's sides in side order.
+__global__ void __launch_bounds__(kDiffBlock) k_mg_build0(Dom d, Rows m, MgGeom fg, MgGeom cg,
+                                                          double* __restrict__ cdiag, double* __restrict__ coff) {
+    MG_CELL(cg, I, ic)
+    double cd = 0.0, co[6] = {0, 0, 0, 0, 0, 0};
+    const int sides = 2 * d.ndim;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                const int f[3] = {2 * I[0] + dx, 2 * I[1] + dy, 2 * I[2] + dz};
+                if (f[0] >= fg.n[0] || f[1] >= fg.n[1] || f[2] >= fg.n[2]) continue;
+                const long i = mg_index(fg, f);
+                const uint8_t k = m.kind[i];
+                double o[6] = {0, 0, 0, 0, 0, 0};
+                for (int s = 0; s < sides; ++s)
+                    o[s] = (k & 2) ? m.off[(long)s * d.ncell + i] : ((k >> (2 + s) & 1) ? 0.0 : -m.rc.c[k & 1]);
+                mg_accumulate(fg, f, row_diag(m, i, k, sides), o, I, cd, co);
+            }
+    cdiag[ic] = cd;
+    for (int s = 0; s < 6; ++s) coff[(long)s * cg.ncell + ic] = co[s];
+}
+
+// Level l + 1 from level l's explicit operator.
+__global__ void __launch_bounds__(kDiffBlock) k_mg_build(MgGeom fg, const double* __restrict__ fdiag,
+                                                         const double* __restrict__ foff, MgGeom cg,
+                                                         double* __restrict__ cdiag, double* __restrict__ coff) {
+    MG_CELL(cg, I, ic)
+    double cd = 0.0, co[6] = {0, 0, 0, 0, 0, 0};
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                const int f[3] = {2 * I[0] + dx, 2 * I[1] + dy, 2 * I[2] + dz};
+                if (f[0] >= fg.n[0] || f[1] >= fg.n[1] || f[2] >= fg.n[2]) continue;
+                const long i = mg_index(fg, f);
+                double o[6] = {0, 0, 0, 0, 0, 0};
+                for (int s = 0; s < 2 * fg.ndim; ++s) o[s] = foff[(long)s * fg.ncell + i];
+                mg_accumulate(fg, f, fdiag[i], o, I, cd, co);
+            }
+    cdiag[ic] = cd;
+    for (int s = 0; s < 6; ++s) coff[(long)s * cg.ncell + ic] = co[s];
 }
 
 // e = C_p(c) T^{n+1}; T_out (if not null) = T^{n+1}.
@@ -471,6 +650,29 @@ DiffLayout diff_layout(const Dom& d) {
     const size_t nm = (size_t)mg.x * mg.y * mg.z;
     L.part = take(3 * (nm > (size_t)kDiffGrid ? nm : (size_t)kDiffGrid) * sizeof(double));
     L.scal = take(kBiScalars * sizeof(double));
+    // the preconditioner: level-0 iterate and residual, then the coarse levels (every
+    // axis halved, rounding up, while the longest is above 8 cells)
+    L.mgx0 = take(n * sizeof(double));
+    L.mgr0 = take(n * sizeof(double));
+    int nl[3] = {d.n[0], d.n[1], d.ndim == 3 ? d.n[2] : 1};
+    L.mg_levels = 1;
+    for (int a = 0; a < 3; ++a) L.mg_n[0][a] = nl[a];
+    auto longest = [&]() {
+        int m = 1;
+        for (int a = 0; a < d.ndim; ++a) m = nl[a] > m ? nl[a] : m;
+        return m;
+    };
+    while (L.mg_levels < kMgMaxLevels && longest() > 8) {
+        for (int a = 0; a < d.ndim; ++a) nl[a] = (nl[a] + 1) / 2;
+        const int l = L.mg_levels++;
+        for (int a = 0; a < 3; ++a) L.mg_n[l][a] = nl[a];
+        const size_t nc = (size_t)nl[0] * nl[1] * nl[2];
+        L.mg_diag[l] = take(nc * sizeof(double));
+        L.mg_off[l] = take(kSides * nc * sizeof(double));
+        L.mg_b[l] = take(nc * sizeof(double));
+        L.mg_x[l] = take(nc * sizeof(double));
+        L.mg_y[l] = take(nc * sizeof(double));
+    }
     L.bytes = off;
     return L;
 }
@@ -498,8 +700,82 @@ DiffIO diff_views(const DiffLayout& L, void* ws) {
     io.rows.kind = io.kind;
     io.rows.diag = io.diag;
     io.rows.off = io.off;
+    io.mgx0 = (double*)(p + L.mgx0);
+    io.mgr0 = (double*)(p + L.mgr0);
+    io.mg_levels = L.mg_levels;
+    for (int l = 0; l < L.mg_levels; ++l) {
+        MgLevel& v = io.mg[l];
+        for (int a = 0; a < 3; ++a) v.n[a] = L.mg_n[l][a];
+        v.ncell = (long)v.n[0] * v.n[1] * v.n[2];
+        v.diag = v.off = v.b = v.x = v.y = nullptr;
+        if (l > 0) {
+            v.diag = (double*)(p + L.mg_diag[l]);
+            v.off = (double*)(p + L.mg_off[l]);
+            v.b = (double*)(p + L.mg_b[l]);
+            v.x = (double*)(p + L.mg_x[l]);
+            v.y = (double*)(p + L.mg_y[l]);
+        }
+    }
     return io;
 }
+
+namespace {
+
+// z = M^-1 in: one V(1,1) cycle (level 0 on the cells' operator, the coarse levels on
+// their explicit ones). Level 0: x0 = w D^-1 in, r0 = in - A x0, restricted; on the way
+// back x0 += P x1, then z = x0 + w D^-1 (in - A x0). With a single level, the two Jacobi
+// steps alone.
+void mg_vcycle(const Dom& d, const DiffIO& io, const double* in, double* z, hipStream_t s) {
+    const dim3 mg = march_grid(d);
+    const dim3 blk(64, 4);
+    const int ng = grid_for(d.ncell);
+    const double* dn = nullptr;
+    double* dw = nullptr;
+    hipLaunchKernelGGL(k_mg_first0, dim3(ng), dim3(kDiffBlock), 0, s, d, io.rows, in, io.mgx0);
+    const int L = io.mg_levels;
+    if (L > 1) {
+        hipLaunchKernelGGL(k_bi_march<3>, mg, blk, 0, s, d, io.rows, (const double*)io.mgx0, io.mgr0, dn, dn, in, dw,
+                           dw, dw, dw, 0.0);
+        MgGeom g[kMgMaxLevels];
+        for (int l = 0; l < L; ++l) g[l] = mg_geom(d, io.mg[l].n);
+        hipLaunchKernelGGL(k_mg_restrict, mg_grid(g[1]), blk, 0, s, g[0], g[1], (const double*)io.mgr0, io.mg[1].b);
+        for (int l = 1; l + 1 < L; ++l) {  // down: first step, residual, restriction
+            const MgLevel& v = io.mg[l];
+            hipLaunchKernelGGL(k_mg_first, mg_grid(g[l]), blk, 0, s, g[l], (const double*)v.diag, (const double*)v.b,
+                               v.x);
+            hipLaunchKernelGGL(k_mg_resid, mg_grid(g[l]), blk, 0, s, g[l], (const double*)v.diag,
+                               (const double*)v.off, (const double*)v.x, (const double*)v.b, v.y);
+            hipLaunchKernelGGL(k_mg_restrict, mg_grid(g[l + 1]), blk, 0, s, g[l], g[l + 1], (const double*)v.y,
+                               io.mg[l + 1].b);
+        }
+        // coarsest: Jacobi steps from zero, alternating between x and y
+        const MgLevel& c = io.mg[L - 1];
+        hipLaunchKernelGGL(k_mg_first, mg_grid(g[L - 1]), blk, 0, s, g[L - 1], (const double*)c.diag,
+                           (const double*)c.b, c.x);
+        double* cur = c.x;
+        double* oth = c.y;
+        for (int k = 1; k < kMgCoarseSweeps; ++k) {
+            hipLaunchKernelGGL(k_mg_smooth, mg_grid(g[L - 1]), blk, 0, s, g[L - 1], (const double*)c.diag,
+                               (const double*)c.off, (const double*)cur, (const double*)c.b, oth);
+            double* t = cur;
+            cur = oth;
+            oth = t;
+        }
+        const double* below = cur;  // the level below's result
+        for (int l = L - 2; l >= 1; --l) {  // up: prolongation, one step into y
+            const MgLevel& v = io.mg[l];
+            hipLaunchKernelGGL(k_mg_prolong, mg_grid(g[l]), blk, 0, s, g[l], g[l + 1], v.x, below);
+            hipLaunchKernelGGL(k_mg_smooth, mg_grid(g[l]), blk, 0, s, g[l], (const double*)v.diag,
+                               (const double*)v.off, (const double*)v.x, (const double*)v.b, v.y);
+            below = v.y;
+        }
+        hipLaunchKernelGGL(k_mg_prolong, mg_grid(g[0]), blk, 0, s, g[0], g[1], io.mgx0, below);
+    }
+    hipLaunchKernelGGL(k_bi_march<4>, mg, blk, 0, s, d, io.rows, (const double*)io.mgx0, z, dn, dn, in, dw, dw, dw,
+                       dw, kMgOmega);
+}
+
+}  // namespace
 
 // The neighbour coefficient of each phase's regular row, computed as the assembly
 // computes it (width and distances of one cell on every side).
@@ -519,27 +795,39 @@ hipError_t launch_diff_start(const Dom& d, const double* c, const double* e, dou
     io.rows.rc = row_const(h, dt, k_l, k_g, d.cp_l, d.cp_g);
     hipLaunchKernelGGL(k_diff_assemble, dim3(ng), dim3(kDiffBlock), 0, s, d, c, e, h, dt, k_l, k_g, io.kind, io.diag,
                        io.off, io.b, io.x);
+    // the coarse operators of the preconditioner
+    for (int l = 1; l < io.mg_levels; ++l) {
+        const MgGeom fg = mg_geom(d, io.mg[l - 1].n), cg = mg_geom(d, io.mg[l].n);
+        if (l == 1)
+            hipLaunchKernelGGL(k_mg_build0, mg_grid(cg), dim3(64, 4), 0, s, d, io.rows, fg, cg, io.mg[1].diag,
+                               io.mg[1].off);
+        else
+            hipLaunchKernelGGL(k_mg_build, mg_grid(cg), dim3(64, 4), 0, s, fg, (const double*)io.mg[l - 1].diag,
+                               (const double*)io.mg[l - 1].off, cg, io.mg[l].diag, io.mg[l].off);
+    }
     const dim3 mg = march_grid(d);
     const int nm = (int)(mg.x * mg.y * mg.z);
     hipLaunchKernelGGL(k_bi_march<0>, mg, dim3(64, 4), 0, s, d, io.rows, io.x, io.r, (const double*)nullptr,
-                       (const double*)nullptr, io.b, io.rh, io.p, io.v, io.part);
+                       (const double*)nullptr, io.b, io.rh, io.p, io.v, io.part, 0.0);
     hipLaunchKernelGGL(k_bi_reduce, dim3(1), dim3(kDiffBlock), 0, s, io.part, nm, io.scal, 0);
     return hipGetLastError();
 }
 
 hipError_t launch_diff_iteration(const Dom& d, const DiffIO& io, hipStream_t s) {
     const int ng = grid_for(d.ncell);
-    hipLaunchKernelGGL(k_bi_dir, dim3(ng), dim3(kDiffBlock), 0, s, d, io.scal, io.rows, io.r, io.v, io.p, io.ph);
+    hipLaunchKernelGGL(k_bi_dir, dim3(ng), dim3(kDiffBlock), 0, s, d, io.scal, io.r, io.v, io.p);
+    mg_vcycle(d, io, io.p, io.ph, s);
     const dim3 mg = march_grid(d);
     const int nm = (int)(mg.x * mg.y * mg.z);
     hipLaunchKernelGGL(k_bi_march<1>, mg, dim3(64, 4), 0, s, d, io.rows, io.ph, io.v, io.rh, (const double*)nullptr,
-                       (const double*)nullptr, (double*)nullptr, (double*)nullptr, (double*)nullptr, io.part);
+                       (const double*)nullptr, (double*)nullptr, (double*)nullptr, (double*)nullptr, io.part, 0.0);
     hipLaunchKernelGGL(k_bi_reduce, dim3(1), dim3(kDiffBlock), 0, s, io.part, nm, io.scal, 1);
-    hipLaunchKernelGGL(k_bi_half, dim3(ng), dim3(kDiffBlock), 0, s, d, io.scal, io.rows, io.r, io.v, io.s, io.sh);
+    hipLaunchKernelGGL(k_bi_half, dim3(ng), dim3(kDiffBlock), 0, s, d, io.scal, io.r, io.v, io.s);
+    mg_vcycle(d, io, io.s, io.sh, s);
     hipLaunchKernelGGL(k_bi_march<2>, mg, dim3(64, 4), 0, s, d, io.rows, io.sh, io.t, io.rh, (const double*)io.s,
-                       (const double*)nullptr, (double*)nullptr, (double*)nullptr, (double*)nullptr, io.part);
+                       (const double*)nullptr, (double*)nullptr, (double*)nullptr, (double*)nullptr, io.part, 0.0);
     hipLaunchKernelGGL(k_bi_reduce, dim3(1), dim3(kDiffBlock), 0, s, io.part, nm, io.scal, 2);
-    hipLaunchKernelGGL(k_bi_update, dim3(ng), dim3(kDiffBlock), 0, s, d, io.scal, io.rows, io.ph, io.s, io.t, io.rh,
+    hipLaunchKernelGGL(k_bi_update, dim3(ng), dim3(kDiffBlock), 0, s, d, io.scal, io.ph, io.sh, io.s, io.t, io.rh,
                        io.x, io.r, io.part);
     hipLaunchKernelGGL(k_bi_reduce, dim3(1), dim3(kDiffBlock), 0, s, io.part, ng, io.scal, 3);
     return hipGetLastError();

@@ -139,8 +139,10 @@ def test_diffusion_full_size_bubble256(pc):
     capacities, one step of the workload's dt: the maximum principle everywhere, and the
     backward-Euler equation T^{n+1} - T* = (dt / C_p) operator(T^{n+1}) at sampled nodes
     (all nodes next to the interface in a slab, and random ones), the operator
-    evaluated node by node by the oracle, to 1e-8 max |T| (the solver bounds the 2-norm of
-    its residual by 1e-13 |b|_2, about 1e-9 max |T| on any single node at this size)."""
+    evaluated node by node by the oracle. Both to 1e-8 max |T|: the exact solution of the
+    system obeys the maximum principle exactly, the computed one within the solver's
+    error, and the solver bounds the 2-norm of its residual by 1e-13 |b|_2, about 1e-9
+    max |T| on any single node at this size."""
     wl = W.bubble_3d(256)
     print("bubble3d_256: fields ready", flush=True)
     spec = pc.DomainSpec(shape=wl.shape, h=wl.h, ndim=3, bc=wl.bc, cp_l=wl.cp_l, cp_g=wl.cp_g, rho_l=wl.rho_l,
@@ -155,7 +157,8 @@ def test_diffusion_full_size_bubble256(pc):
     print(f"bubble3d_256: {info}", flush=True)
     T0 = wl.e / _cp(wl.c, wl.cp_l, wl.cp_g)
     lo, hi = min(T0.min(), wl.T_gamma), max(T0.max(), wl.T_gamma)
-    assert T1.min() >= lo - 1e-12 and T1.max() <= hi + 1e-12
+    tol = 1e-8 * max(abs(lo), abs(hi))
+    assert T1.min() >= lo - tol and T1.max() <= hi + tol, (T1.min() - lo, T1.max() - hi)
     cfg = oracle.Config(shape=wl.shape, h=wl.h, ndim=3, bc=wl.bc, cp_l=wl.cp_l, cp_g=wl.cp_g)
     liquid = wl.c >= 0.5
     near = np.zeros(wl.shape, dtype=bool)
