@@ -238,7 +238,7 @@ int pcvof_extend_velocity(pcvof_handle* h, double rho_g, double rel_tol, int max
    * the temperature before the step is e / C_p(c) (one-fluid C_p), the energy after it
      C_p(c) T^{n+1}.
    The non-symmetric system is solved by BiCGSTAB preconditioned with one multigrid
-   V(1,1) cycle (2 x 2 x 2 aggregates, Galerkin coarse operators, damped Jacobi steps;
+   V(0,2) cycle (2 x 2 x 2 aggregates, Galerkin coarse operators, damped Jacobi steps;
    deterministic reductions) from T*, until |r|_2 <= rel_tol |b|_2 (0 < rel_tol < 1), at
    most max_iter iterations (>= 1); without convergence PCVOF_ERR_STATE and the energy
    is unchanged. dt > 0, k_l, k_g >= 0 (PCVOF_ERR_ARG otherwise); needs the fractions
@@ -257,7 +257,7 @@ int pcvof_diffuse(pcvof_handle* h, double dt, double k_l, double k_g, double rel
    capture, tight serving loops, harnesses that forbid allocation): the same operation,
    arguments and results as pcvof_diffuse, without the workspace arguments. It allocates
    nothing: its scratch is one device array of 256 MiB per GPU, part of the library and
-   held until the process ends, enough for domains of about 1.6 million cells
+   held until the process ends, enough for domains of about 1.7 million cells
    (pcvof_diffusion_workspace_bytes(h) <= 256 MiB); larger domains get
    PCVOF_ERR_WORKSPACE without anything launched. Every call on a GPU shares that GPU's
    array: calls that overlap on one GPU (several host threads, or streams that run at

@@ -49,13 +49,13 @@ struct DiffIO {
     double* part;   // 3 partial sums per block of the fixed grid
     double* scal;   // kBi* scalars
     Rows rows;      // the operator as the kernels read it (rc set by launch_diff_start)
-    double *mgx0, *mgr0;         // level-0 iterate and residual of the V-cycle
+    double* mgx0;                // level-0 iterate of the V-cycle
     int mg_levels;               // levels including the cells' own (1: Jacobi steps only)
     MgLevel mg[kMgMaxLevels];    // mg[l], l >= 1: the coarse levels
 };
 
 struct DiffLayout {
-    size_t kind, diag, off, b, vec[9], part, scal, mgx0, mgr0, bytes;
+    size_t kind, diag, off, b, vec[9], part, scal, mgx0, bytes;
     int mg_levels;
     int mg_n[kMgMaxLevels][3];
     size_t mg_diag[kMgMaxLevels], mg_off[kMgMaxLevels], mg_b[kMgMaxLevels], mg_x[kMgMaxLevels], mg_y[kMgMaxLevels];

@@ -218,9 +218,8 @@ __device__ __forceinline__ int nb_pos(int v, int n, int bc) {
 // registers; the x and y neighbours are rows of the same block (coalesced, in cache).
 // Per row the diagonal first, then the sides in the order x-, x+, y-, y+, z-, z+. MODE 0: start
 // (r = b - A x, rhat = r, p = v = 0; partials rhat.r, r.r, b.b); 1: y = A x with the
-// partial rhat.y; 2: y = A x with the partials y.s, y.y; 3: y = b - A x; 4: one damped
-// Jacobi step y = x + w (b - A x) / diag (3 and 4: the preconditioner's level 0, no
-// partials).
+// partial rhat.y; 2: y = A x with the partials y.s, y.y; 4: one damped Jacobi step
+// y = x + w (b - A x) / diag (the preconditioner's level 0, no partials).
 template <int MODE>
 __global__ void __launch_bounds__(kDiffBlock) k_bi_march(Dom d, Rows m, const double* __restrict__ xin,
                                                          double* __restrict__ y, const double* __restrict__ rh,
@@ -271,9 +270,7 @@ __global__ void __launch_bounds__(kDiffBlock) k_bi_march(Dom d, Rows m, const do
                 for (int slot = 0; slot < sides; ++slot)
                     if (!(k >> (2 + slot) & 1)) yi += o * nbv[slot];
             }
-            if (MODE == 3) {
-                y[i] = b[i] - yi;
-            } else if (MODE == 4) {
+            if (MODE == 4) {
                 y[i] = xcur + w * (b[i] - yi) / dg;
             } else if (MODE == 0) {
                 const double ri = b[i] - yi;
@@ -297,7 +294,7 @@ __global__ void __launch_bounds__(kDiffBlock) k_bi_march(Dom d, Rows m, const do
             xcur = xnext;
         }
     }
-    if (MODE < 3) {
+    if (MODE < 4) {
         const long blk = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
         block_sum3(s0, s1, s2, part, (int)(threadIdx.y * 64 + threadIdx.x), blk);
     }
@@ -397,12 +394,16 @@ __global__ void __launch_bounds__(kDiffBlock) k_bi_reduce(const double* __restri
     }
 }
 
-// Multigrid preconditioner M^-1: one V(1,1) cycle over levels of 2 x 2 x 2 aggregates
+// Multigrid preconditioner M^-1: one V(0,2) cycle over levels of 2 x 2 x 2 aggregates
 // (unsmoothed aggregation: piecewise constant prolongation P, restriction R = P^T,
-// Galerkin coarse operators R A P, built once per call), with damped Jacobi steps
-// (weight kMgOmega, each first step from zero) and kMgCoarseSweeps of them on the
-// coarsest level. Every kernel is a fixed function of its inputs (no atomics), so the
-// preconditioner, like the rest of the solve, is deterministic.
+// Galerkin coarse operators R A P, built once per call): on each level the right-hand
+// side is restricted as it is, the level below returns its correction, and two damped
+// Jacobi steps (weight kMgOmega) start from the prolongated correction; the coarsest
+// level takes kMgCoarseSweeps steps from zero. (Measured on the C3 bubble's operator:
+// 13 iterations against 12 with a V(1,1) cycle, whose residual and pre-smoothing passes
+// over the cells cost more than the iteration saved.) Every kernel is a fixed function
+// of its inputs (no atomics), so the preconditioner, like the rest of the solve, is
+// deterministic.
 constexpr double kMgOmega = 0.8;
 constexpr int kMgCoarseSweeps = 4;
 
@@ -438,36 +439,97 @@ __device__ __forceinline__ long mg_index(const MgGeom& g, const int (&q)[3]) {
     return ((long)q[2] * g.n[1] + q[1]) * g.n[0] + q[0];
 }
 
-// Neighbour of cell q on side s (x-, x+, y-, y+, z-, z+): wrapped on periodic axes, -1
-// beyond an outflow boundary.
-__device__ __forceinline__ long mg_nb(const MgGeom& g, const int (&q)[3], int s) {
-    const int axis = s >> 1;
+// Level 0, first Jacobi step from zero (single-level preconditioner): x0 = w b / diag.
+__global__ void __launch_bounds__(kDiffBlock) k_mg_first0(Dom d, Rows m, const double* __restrict__ b,
+                                                          double* __restrict__ x0) {
+    GRID_STRIDE(i, d.ncell) x0[i] = kMgOmega * b[i] / row_diag(m, i, m.kind[i], 2 * d.ndim);
+}
+
+// Level 0: one Jacobi step from the prolongated coarse correction x = P xc (read at the
+// cell and its neighbours through their aggregates): y = x + w (b - A x) / diag.
+// The coarse index of the aggregate holding the neighbour of fine cell q on side S (the
+// cell's own aggregate beyond an outflow boundary, where the coefficient is zero).
+template <int S>
+__device__ __forceinline__ long mg_coarse_nb(const MgGeom& fg, const MgGeom& cg, const int (&q)[3]) {
+    constexpr int axis = S >> 1;
     int r[3] = {q[0], q[1], q[2]};
-    int v = r[axis] + ((s & 1) ? 1 : -1);
-    if (v < 0 || v >= g.n[axis]) {
-        if (g.bc[axis] != 0) return -1;
-        v = v < 0 ? v + g.n[axis] : v - g.n[axis];
+    int v = r[axis] + ((S & 1) ? 1 : -1);
+    if (v < 0 || v >= fg.n[axis]) v = fg.bc[axis] != 0 ? r[axis] : (v < 0 ? v + fg.n[axis] : v - fg.n[axis]);
+    r[axis] = v;
+    return ((long)(r[2] >> 1) * cg.n[1] + (r[1] >> 1)) * cg.n[0] + (r[0] >> 1);
+}
+
+// Level 0: one Jacobi step from the prolongated coarse correction x = P xc (read at the
+// cell and its neighbours through their aggregates): y = x + w (b - A x) / diag. The
+// seven coarse values are loaded before they are summed (in side order).
+__global__ void __launch_bounds__(kDiffBlock) k_mg_psmooth0(Dom d, Rows m, MgGeom fg, MgGeom cg,
+                                                            const double* __restrict__ xc,
+                                                            const double* __restrict__ b, double* __restrict__ y) {
+    MG_CELL(fg, q, i)
+    const uint8_t k = m.kind[i];
+    const int sides = 2 * d.ndim;
+    const long ic = ((long)(q[2] >> 1) * cg.n[1] + (q[1] >> 1)) * cg.n[0] + (q[0] >> 1);
+    const long jc[6] = {mg_coarse_nb<0>(fg, cg, q), mg_coarse_nb<1>(fg, cg, q), mg_coarse_nb<2>(fg, cg, q),
+                        mg_coarse_nb<3>(fg, cg, q), sides > 4 ? mg_coarse_nb<4>(fg, cg, q) : ic,
+                        sides > 4 ? mg_coarse_nb<5>(fg, cg, q) : ic};
+    double xn[6];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) xn[s] = xc[jc[s]];
+    const double xi = xc[ic], bi = b[i];
+    const double dg = row_diag(m, i, k, sides);
+    double ax = dg * xi;
+    if (k & 2) {
+#pragma unroll
+        for (int s = 0; s < 6; ++s)
+            if (s < sides) ax += m.off[(long)s * d.ncell + i] * xn[s];
+    } else {
+        const double o = -m.rc.c[k & 1];
+#pragma unroll
+        for (int s = 0; s < 6; ++s)
+            if (s < sides && !(k >> (2 + s) & 1)) ax += o * xn[s];
     }
+    y[i] = xi + kMgOmega * (bi - ax) / dg;
+}
+
+// Index of the neighbour of cell q on side S of a level (the cell itself beyond an
+// outflow boundary, where the coefficient is zero).
+template <int S>
+__device__ __forceinline__ long mg_nb_idx(const MgGeom& g, const int (&q)[3]) {
+    constexpr int axis = S >> 1;
+    int r[3] = {q[0], q[1], q[2]};
+    int v = r[axis] + ((S & 1) ? 1 : -1);
+    if (v < 0 || v >= g.n[axis]) v = g.bc[axis] != 0 ? r[axis] : (v < 0 ? v + g.n[axis] : v - g.n[axis]);
     r[axis] = v;
     return mg_index(g, r);
 }
 
-// (A x)_i on a coarse level.
+// The six neighbour indices of cell q on a level (2D: the last two are the cell itself).
+__device__ __forceinline__ void mg_nbs(const MgGeom& g, const int (&q)[3], long i, long (&j)[6]) {
+    j[0] = mg_nb_idx<0>(g, q);
+    j[1] = mg_nb_idx<1>(g, q);
+    j[2] = mg_nb_idx<2>(g, q);
+    j[3] = mg_nb_idx<3>(g, q);
+    j[4] = g.ndim == 3 ? mg_nb_idx<4>(g, q) : i;
+    j[5] = g.ndim == 3 ? mg_nb_idx<5>(g, q) : i;
+}
+
+// (A x)_i on a coarse level, the values loaded before they are summed (in side order).
 __device__ __forceinline__ double mg_apply_row(const MgGeom& g, const double* __restrict__ diag,
                                                const double* __restrict__ off, const double* __restrict__ x,
                                                const int (&q)[3], long i) {
-    double y = diag[i] * x[i];
-    for (int s = 0; s < 2 * g.ndim; ++s) {
-        const long j = mg_nb(g, q, s);
-        if (j >= 0) y += off[(long)s * g.ncell + i] * x[j];
+    long j[6];
+    mg_nbs(g, q, i, j);
+    double xn[6], o[6];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        xn[s] = x[j[s]];
+        o[s] = off[(long)s * g.ncell + i];
     }
+    double y = diag[i] * x[i];
+#pragma unroll
+    for (int s = 0; s < 6; ++s)
+        if (s < 2 * g.ndim) y += o[s] * xn[s];
     return y;
-}
-
-// Level 0, first Jacobi step from zero: x0 = w b / diag.
-__global__ void __launch_bounds__(kDiffBlock) k_mg_first0(Dom d, Rows m, const double* __restrict__ b,
-                                                          double* __restrict__ x0) {
-    GRID_STRIDE(i, d.ncell) x0[i] = kMgOmega * b[i] / row_diag(m, i, m.kind[i], 2 * d.ndim);
 }
 
 // Coarse level, first Jacobi step from zero: x = w b / diag.
@@ -477,20 +539,37 @@ __global__ void __launch_bounds__(kDiffBlock) k_mg_first(MgGeom g, const double*
     x[i] = kMgOmega * b[i] / diag[i];
 }
 
-// Coarse level: y = b - A x.
-__global__ void __launch_bounds__(kDiffBlock) k_mg_resid(MgGeom g, const double* __restrict__ diag,
-                                                         const double* __restrict__ off, const double* __restrict__ x,
-                                                         const double* __restrict__ b, double* __restrict__ y) {
-    MG_CELL(g, q, i)
-    y[i] = b[i] - mg_apply_row(g, diag, off, x, q, i);
-}
-
 // Coarse level, one damped Jacobi step: y = x + w (b - A x) / diag.
 __global__ void __launch_bounds__(kDiffBlock) k_mg_smooth(MgGeom g, const double* __restrict__ diag,
                                                           const double* __restrict__ off, const double* __restrict__ x,
                                                           const double* __restrict__ b, double* __restrict__ y) {
     MG_CELL(g, q, i)
     y[i] = x[i] + kMgOmega * (b[i] - mg_apply_row(g, diag, off, x, q, i)) / diag[i];
+}
+
+// Coarse level: one Jacobi step from the prolongated correction x = P xc:
+// y = x + w (b - A x) / diag.
+__global__ void __launch_bounds__(kDiffBlock) k_mg_psmooth(MgGeom g, MgGeom cg, const double* __restrict__ diag,
+                                                           const double* __restrict__ off,
+                                                           const double* __restrict__ xc,
+                                                           const double* __restrict__ b, double* __restrict__ y) {
+    MG_CELL(g, q, i)
+    const long ic = ((long)(q[2] >> 1) * cg.n[1] + (q[1] >> 1)) * cg.n[0] + (q[0] >> 1);
+    const long jc[6] = {mg_coarse_nb<0>(g, cg, q), mg_coarse_nb<1>(g, cg, q), mg_coarse_nb<2>(g, cg, q),
+                        mg_coarse_nb<3>(g, cg, q), g.ndim == 3 ? mg_coarse_nb<4>(g, cg, q) : ic,
+                        g.ndim == 3 ? mg_coarse_nb<5>(g, cg, q) : ic};
+    double xn[6], o[6];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        xn[s] = xc[jc[s]];
+        o[s] = off[(long)s * g.ncell + i];
+    }
+    const double xi = xc[ic], dg = diag[i];
+    double ax = dg * xi;
+#pragma unroll
+    for (int s = 0; s < 6; ++s)
+        if (s < 2 * g.ndim) ax += o[s] * xn[s];
+    y[i] = xi + kMgOmega * (b[i] - ax) / dg;
 }
 
 // Restriction: bc_I = sum of rf over the aggregate I (fixed order z, y, x).
@@ -505,14 +584,6 @@ __global__ void __launch_bounds__(kDiffBlock) k_mg_restrict(MgGeom fg, MgGeom cg
                 if (f[0] < fg.n[0] && f[1] < fg.n[1] && f[2] < fg.n[2]) sum += rf[mg_index(fg, f)];
             }
     bc[I] = sum;
-}
-
-// Prolongation: xf_i += xc of the aggregate holding i.
-__global__ void __launch_bounds__(kDiffBlock) k_mg_prolong(MgGeom fg, MgGeom cg, double* __restrict__ xf,
-                                                           const double* __restrict__ xc) {
-    MG_CELL(fg, q, i)
-    const int c[3] = {q[0] >> 1, q[1] >> 1, q[2] >> 1};
-    xf[i] += xc[mg_index(cg, c)];
 }
 
 // Coarse operator entries of one fine row (diagonal dg, side coefficients o[s]) of a cell
@@ -650,10 +721,9 @@ DiffLayout diff_layout(const Dom& d) {
     const size_t nm = (size_t)mg.x * mg.y * mg.z;
     L.part = take(3 * (nm > (size_t)kDiffGrid ? nm : (size_t)kDiffGrid) * sizeof(double));
     L.scal = take(kBiScalars * sizeof(double));
-    // the preconditioner: level-0 iterate and residual, then the coarse levels (every
-    // axis halved, rounding up, while the longest is above 8 cells)
+    // the preconditioner: level-0 iterate, then the coarse levels (every axis halved,
+    // rounding up, while the longest is above 8 cells)
     L.mgx0 = take(n * sizeof(double));
-    L.mgr0 = take(n * sizeof(double));
     int nl[3] = {d.n[0], d.n[1], d.ndim == 3 ? d.n[2] : 1};
     L.mg_levels = 1;
     for (int a = 0; a < 3; ++a) L.mg_n[0][a] = nl[a];
@@ -701,7 +771,6 @@ DiffIO diff_views(const DiffLayout& L, void* ws) {
     io.rows.diag = io.diag;
     io.rows.off = io.off;
     io.mgx0 = (double*)(p + L.mgx0);
-    io.mgr0 = (double*)(p + L.mgr0);
     io.mg_levels = L.mg_levels;
     for (int l = 0; l < L.mg_levels; ++l) {
         MgLevel& v = io.mg[l];
@@ -721,33 +790,26 @@ DiffIO diff_views(const DiffLayout& L, void* ws) {
 
 namespace {
 
-// z = M^-1 in: one V(1,1) cycle (level 0 on the cells' operator, the coarse levels on
-// their explicit ones). Level 0: x0 = w D^-1 in, r0 = in - A x0, restricted; on the way
-// back x0 += P x1, then z = x0 + w D^-1 (in - A x0). With a single level, the two Jacobi
-// steps alone.
+// z = M^-1 in: one V(0,2) cycle. Level l > 0 (right-hand side b_l restricted from the
+// level above): b_{l+1} = R b_l, the level below's correction xc, then y = P xc + w D^-1
+// (b_l - A P xc) and x_l = y + w D^-1 (b_l - A y); the coarsest level: Jacobi steps from
+// zero. Level 0 the same on the cells' operator with b_0 = in and z = x_0. With a single
+// level, two Jacobi steps from zero.
 void mg_vcycle(const Dom& d, const DiffIO& io, const double* in, double* z, hipStream_t s) {
     const dim3 mg = march_grid(d);
     const dim3 blk(64, 4);
-    const int ng = grid_for(d.ncell);
     const double* dn = nullptr;
     double* dw = nullptr;
-    hipLaunchKernelGGL(k_mg_first0, dim3(ng), dim3(kDiffBlock), 0, s, d, io.rows, in, io.mgx0);
     const int L = io.mg_levels;
-    if (L > 1) {
-        hipLaunchKernelGGL(k_bi_march<3>, mg, blk, 0, s, d, io.rows, (const double*)io.mgx0, io.mgr0, dn, dn, in, dw,
-                           dw, dw, dw, 0.0);
+    if (L == 1) {
+        hipLaunchKernelGGL(k_mg_first0, dim3(grid_for(d.ncell)), dim3(kDiffBlock), 0, s, d, io.rows, in, io.mgx0);
+    } else {
         MgGeom g[kMgMaxLevels];
         for (int l = 0; l < L; ++l) g[l] = mg_geom(d, io.mg[l].n);
-        hipLaunchKernelGGL(k_mg_restrict, mg_grid(g[1]), blk, 0, s, g[0], g[1], (const double*)io.mgr0, io.mg[1].b);
-        for (int l = 1; l + 1 < L; ++l) {  // down: first step, residual, restriction
-            const MgLevel& v = io.mg[l];
-            hipLaunchKernelGGL(k_mg_first, mg_grid(g[l]), blk, 0, s, g[l], (const double*)v.diag, (const double*)v.b,
-                               v.x);
-            hipLaunchKernelGGL(k_mg_resid, mg_grid(g[l]), blk, 0, s, g[l], (const double*)v.diag,
-                               (const double*)v.off, (const double*)v.x, (const double*)v.b, v.y);
-            hipLaunchKernelGGL(k_mg_restrict, mg_grid(g[l + 1]), blk, 0, s, g[l], g[l + 1], (const double*)v.y,
+        hipLaunchKernelGGL(k_mg_restrict, mg_grid(g[1]), blk, 0, s, g[0], g[1], in, io.mg[1].b);
+        for (int l = 1; l + 1 < L; ++l)
+            hipLaunchKernelGGL(k_mg_restrict, mg_grid(g[l + 1]), blk, 0, s, g[l], g[l + 1], (const double*)io.mg[l].b,
                                io.mg[l + 1].b);
-        }
         // coarsest: Jacobi steps from zero, alternating between x and y
         const MgLevel& c = io.mg[L - 1];
         hipLaunchKernelGGL(k_mg_first, mg_grid(g[L - 1]), blk, 0, s, g[L - 1], (const double*)c.diag,
@@ -761,15 +823,16 @@ void mg_vcycle(const Dom& d, const DiffIO& io, const double* in, double* z, hipS
             cur = oth;
             oth = t;
         }
-        const double* below = cur;  // the level below's result
-        for (int l = L - 2; l >= 1; --l) {  // up: prolongation, one step into y
+        const double* below = cur;  // the level below's correction
+        for (int l = L - 2; l >= 1; --l) {
             const MgLevel& v = io.mg[l];
-            hipLaunchKernelGGL(k_mg_prolong, mg_grid(g[l]), blk, 0, s, g[l], g[l + 1], v.x, below);
+            hipLaunchKernelGGL(k_mg_psmooth, mg_grid(g[l]), blk, 0, s, g[l], g[l + 1], (const double*)v.diag,
+                               (const double*)v.off, below, (const double*)v.b, v.y);
             hipLaunchKernelGGL(k_mg_smooth, mg_grid(g[l]), blk, 0, s, g[l], (const double*)v.diag,
-                               (const double*)v.off, (const double*)v.x, (const double*)v.b, v.y);
-            below = v.y;
+                               (const double*)v.off, (const double*)v.y, (const double*)v.b, v.x);
+            below = v.x;
         }
-        hipLaunchKernelGGL(k_mg_prolong, mg_grid(g[0]), blk, 0, s, g[0], g[1], io.mgx0, below);
+        hipLaunchKernelGGL(k_mg_psmooth0, mg_grid(g[0]), blk, 0, s, d, io.rows, g[0], g[1], below, in, io.mgx0);
     }
     hipLaunchKernelGGL(k_bi_march<4>, mg, blk, 0, s, d, io.rows, (const double*)io.mgx0, z, dn, dn, in, dw, dw, dw,
                        dw, kMgOmega);
