@@ -142,7 +142,8 @@ def test_diffusion_full_size_bubble256(pc):
     evaluated node by node by the oracle. Both to 1e-8 max |T|: the exact solution of the
     system obeys the maximum principle exactly, the computed one within the solver's
     error, and the solver bounds the 2-norm of its residual by 1e-13 |b|_2, about 1e-9
-    max |T| on any single node at this size."""
+    max |T| on any single node at this size. The multigrid preconditioner keeps the
+    iterations at 20 or fewer (14 measured; 76 with the diagonal alone)."""
     wl = W.bubble_3d(256)
     print("bubble3d_256: fields ready", flush=True)
     spec = pc.DomainSpec(shape=wl.shape, h=wl.h, ndim=3, bc=wl.bc, cp_l=wl.cp_l, cp_g=wl.cp_g, rho_l=wl.rho_l,
@@ -155,6 +156,7 @@ def test_diffusion_full_size_bubble256(pc):
     T1 = Tg.cpu().numpy()
     del d
     print(f"bubble3d_256: {info}", flush=True)
+    assert info["iterations"] <= 20, info
     T0 = wl.e / _cp(wl.c, wl.cp_l, wl.cp_g)
     lo, hi = min(T0.min(), wl.T_gamma), max(T0.max(), wl.T_gamma)
     tol = 1e-8 * max(abs(lo), abs(hi))
