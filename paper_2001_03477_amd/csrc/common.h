@@ -100,6 +100,20 @@ __device__ __forceinline__ void block_sum8(const double (&v)[8], double* out, lo
     }
 }
 
+// A pointer read from memory (a table of per-domain arguments) is generic to the
+// compiler, which then accesses it with flat instructions: each counts as a
+// vector-memory and as an LDS operation, so that every wait for one kind also waits for
+// the other. Passed through a global-address-space pointer, which the empty asm keeps
+// from being folded away, it is accessed with global instructions, like a kernel
+// argument. The pointer must be wavefront-uniform and held in scalar registers.
+template <typename T>
+__device__ __forceinline__ T* in_global(T* p) {
+    using G = __attribute__((address_space(1))) T*;
+    G g = (G)p;
+    __asm__("" : "+s"(g));
+    return (T*)g;
+}
+
 // Bit of the mixed-cell mask for cell x of the row starting at word rowword.
 __device__ __forceinline__ bool mask_bit(const uint64_t* __restrict__ mask, long rowword, int x) {
     return (mask[rowword + (x >> 6)] >> (x & 63)) & 1ull;
