@@ -174,9 +174,14 @@ __global__ void __launch_bounds__(kDiffBlock) k_diff_assemble(Dom d, const doubl
 // coefficient on every side that is not a wall, and the diagonal 1 plus those
 // coefficients summed in side order (the same values the assembly computes); the others
 // the stored ones.
+// The coefficient of a regular row of the phase in bit 0 of its kind, chosen between the
+// two values rather than indexed by the lane's kind (an indexed read of the argument
+// structure would be a memory load per lane, waited for with everything in flight).
+__device__ __forceinline__ double phase_coef(const Rows& m, uint8_t k) { return (k & 1) ? m.rc.c[1] : m.rc.c[0]; }
+
 __device__ __forceinline__ double row_diag(const Rows& m, long i, uint8_t k, int sides) {
     if (k & 2) return m.diag[i];
-    const double c = m.rc.c[k & 1];
+    const double c = phase_coef(m, k);
     double dg = 1.0;
     for (int slot = 0; slot < sides; ++slot)
         if (!(k >> (2 + slot) & 1)) dg += c;
@@ -237,61 +242,82 @@ __global__ void __launch_bounds__(kDiffBlock) k_bi_march(Dom d, Rows m, const do
         const long xm = (long)yy * nx + nb_pos(x - 1, nx, d.bc[0]), xp = (long)yy * nx + nb_pos(x + 1, nx, d.bc[0]);
         const long ym = (long)nb_pos(yy - 1, ny, d.bc[1]) * nx + x, yp = (long)nb_pos(yy + 1, ny, d.bc[1]) * nx + x;
         const bool three = d.ndim == 3;
+        // the vector read beside x: b (residual, relaxation), rhat or s (dot products)
+        const double* __restrict__ dop = MODE == 1 ? rh : (MODE == 2 ? sv : b);
         double xprev = three ? xin[nb_pos(z0 - 1, nz, d.bc[2]) * plane + col] : 0.0;
         double xcur = xin[z0 * plane + col];
-        // the plane z's in-plane neighbours and kind, loaded one step ahead
+        double xnext = three ? xin[nb_pos(z0 + 1, nz, d.bc[2]) * plane + col] : 0.0;
+        // plane z's in-plane neighbours, kind and dop, and x at z + 1, loaded one step ahead
         double n0 = xin[z0 * plane + xm], n1 = xin[z0 * plane + xp], n2 = xin[z0 * plane + ym],
                n3 = xin[z0 * plane + yp];
         uint8_t kn = m.kind[z0 * plane + col];
-        for (int z = z0; z < z1; ++z) {
+        double dn = dop[z0 * plane + col];
+        // fully unrolled, so that the values carried from step to step are renamed
+        // registers rather than moved ones (a move of a value still being loaded waits for it)
+#pragma unroll
+        for (int t = 0; t < kMarch; ++t) {
+            const int z = z0 + t;
+            if (z >= z1) break;
             const long zb = z * plane;
             const long i = zb + col;
-            const double xnext = three ? xin[nb_pos(z + 1, nz, d.bc[2]) * plane + col] : 0.0;
             const double nbv[6] = {n0, n1, n2, n3, xprev, xnext};
             const uint8_t k = kn;
-            if (z + 1 < z1) {
-                const long zn = zb + plane;
+            const double di = dn;
+            // The next step's loads are issued at every step (the last step repeats its own
+            // plane, in cache): with a fixed number of loads per step the compiler waits for
+            // each value by its count, not for every load in flight.
+            {
+                const long zn = (z + 1 < z1 ? z + 1 : z) * plane;
                 n0 = xin[zn + xm];
                 n1 = xin[zn + xp];
                 n2 = xin[zn + ym];
                 n3 = xin[zn + yp];
                 kn = m.kind[zn + col];
+                dn = dop[zn + col];
             }
+            const double xnn = three ? xin[nb_pos(z + 2 < z1 ? z + 2 : z1, nz, d.bc[2]) * plane + col] : 0.0;
             const int sides = 2 * d.ndim;
-            const double dg = row_diag(m, i, k, sides);
-            double yi = dg * xcur;
+            // Each branch uses up its own loads: a stored (interface) row's diagonal or
+            // coefficients read in one branch and used after the join would make every
+            // step wait there for all loads in flight.
+            double dg, yi;
             if (k & 2) {
+                dg = m.diag[i];
+                yi = dg * xcur;
                 for (int slot = 0; slot < sides; ++slot) {
                     const double o = m.off[(long)slot * d.ncell + i];
                     if (o != 0.0) yi += o * nbv[slot];
                 }
             } else {
-                const double o = -m.rc.c[k & 1];
+                dg = row_diag(m, i, k, sides);
+                yi = dg * xcur;
+                const double o = -phase_coef(m, k);
                 for (int slot = 0; slot < sides; ++slot)
                     if (!(k >> (2 + slot) & 1)) yi += o * nbv[slot];
             }
             if (MODE == 4) {
-                y[i] = xcur + w * (b[i] - yi) / dg;
+                y[i] = xcur + w * (di - yi) / dg;
             } else if (MODE == 0) {
-                const double ri = b[i] - yi;
+                const double ri = di - yi;
                 y[i] = ri;  // r
                 rhw[i] = ri;
                 p[i] = 0.0;
                 v[i] = 0.0;
                 s0 += ri * ri;
                 s1 += ri * ri;
-                s2 += b[i] * b[i];
+                s2 += di * di;
             } else {
                 y[i] = yi;
                 if (MODE == 2) {
-                    s0 += yi * sv[i];
+                    s0 += yi * di;
                     s1 += yi * yi;
                 } else {
-                    s0 += rh[i] * yi;
+                    s0 += di * yi;
                 }
             }
             xprev = xcur;
             xcur = xnext;
+            xnext = xnn;
         }
     }
     if (MODE < 4) {
@@ -483,7 +509,7 @@ __global__ void __launch_bounds__(kDiffBlock) k_mg_psmooth0(Dom d, Rows m, MgGeo
         for (int s = 0; s < 6; ++s)
             if (s < sides) ax += m.off[(long)s * d.ncell + i] * xn[s];
     } else {
-        const double o = -m.rc.c[k & 1];
+        const double o = -phase_coef(m, k);
 #pragma unroll
         for (int s = 0; s < 6; ++s)
             if (s < sides && !(k >> (2 + s) & 1)) ax += o * xn[s];
@@ -619,7 +645,7 @@ __global__ void __launch_bounds__(kDiffBlock) k_mg_build0(Dom d, Rows m, MgGeom 
                 const uint8_t k = m.kind[i];
                 double o[6] = {0, 0, 0, 0, 0, 0};
                 for (int s = 0; s < sides; ++s)
-                    o[s] = (k & 2) ? m.off[(long)s * d.ncell + i] : ((k >> (2 + s) & 1) ? 0.0 : -m.rc.c[k & 1]);
+                    o[s] = (k & 2) ? m.off[(long)s * d.ncell + i] : ((k >> (2 + s) & 1) ? 0.0 : -phase_coef(m, k));
                 mg_accumulate(fg, f, row_diag(m, i, k, sides), o, I, cd, co);
             }
     cdiag[ic] = cd;
