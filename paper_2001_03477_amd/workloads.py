@@ -623,6 +623,23 @@ def bubble_3d(n=256, R=0.1, u0=0.05, smooth=0.8, cfl=0.3, rho_l=2.5, cp_l=6.25, 
                     mdot, dt, 10)
 
 
+def wide_mixed_3d(nx=1100, ny=16, nz=4, seed=53) -> Workload:
+    """A box whose rows are longer than one 512-cell x range of the x sweep (three ranges
+    at nx = 1100, the last one ragged), every cell mixed (c uniform in [0.05, 0.95], e
+    from per-phase temperatures 0.7 and 0.3 at water-like heat capacities), in a periodic
+    divergence-free Fourier velocity (6 modes) at CFL 0.3."""
+    rng = np.random.default_rng(seed)
+    shape, h = (nz, ny, nx), 1.0 / nx
+    c = rng.uniform(0.05, 0.95, size=shape)
+    cp_l, cp_g = 4039.0, 1.248
+    e = energy_from_phase_temperatures(c, 0.7, 0.3, cp_l, cp_g)
+    ks, amps, phis = fourier_modes(rng, 6, 3, 3)
+    u, v, w = fourier_mac_velocity(ks, amps, phis, shape, h, lengths=(nx * h, ny * h, nz * h))
+    dt = 0.3 * h / max_abs_face(u, v, w)
+    return Workload(f"wide_mixed_{nx}x{ny}x{nz}", shape, h, 3, (0, 0, 0), cp_l, cp_g, 1.0, 1.0, c, e, u, v, w,
+                    None, dt, 2)
+
+
 def batch_domains(nd=64, seed=5, smin=32, smax=160, cfl=0.3, cp=(1000.0, 1.0)):
     """nd independent periodic 3D domains with sides uniform in [smin, smax] cells per
     axis (cubic cells of side 1/nx), each holding one drop (liquid sphere) or bubble

@@ -116,6 +116,24 @@ def test_batch_tile_choices_give_the_same_fields(pc, chunk):
     b.close()
 
 
+def test_batch_long_x_ranges_overflow_the_flux_tables(pc):
+    """Eight rows per x wavefront over 512-cell ranges of an all-mixed 1100-cell-wide
+    domain list about 4,100 faces per wavefront, far past the x sweep's LDS flux table,
+    and 8-cell y / z columns list about 580 per wavefront, past theirs: the fluxes go
+    through the global face array. The fields must equal the single-domain runs
+    (one-row, 64-cell x ranges there; that path is checked against the oracle)."""
+    wls = [W.wide_mixed_3d(), _workloads()[0]]
+    ref = _singles(pc, wls, 3)
+    b = _batch(pc, wls)
+    b.set_tiles(chunk=[8, 8, 8])
+    for _ in range(3):
+        b.step([wl.dt for wl in wls])
+    for d, (c, e, _) in zip(b.domains, ref):
+        assert np.array_equal(d.vof().cpu().numpy(), c)
+        assert np.array_equal(d.energy().cpu().numpy(), e)
+    b.close()
+
+
 def test_batch_autotune_keeps_the_state(pc):
     wls = _workloads()
     ref = _singles(pc, wls, 2)

@@ -352,6 +352,22 @@ def test_profiling_times_the_selected_classes(pc):
 
 
 @pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 1)])
+def test_wide_rows_every_cell_mixed(pc, bc):
+    """Rows of 1100 cells split into several x ranges (first faces inside a row, a ragged
+    last range, the chunk past a range's end), every face with a mixed donor."""
+    wl = W.wide_mixed_3d()
+    wl.bc = bc
+    spec, cfg = _specs(pc, wl)
+    d = _domain(pc, spec, wl)
+    c, e = wl.c, wl.e
+    for k in range(2):
+        d.step(wl.dt)
+        c, e, _ = oracle.step(cfg, c, e, wl.u, wl.v, wl.w, None, wl.dt, 1.0, k)
+    _assert_close(d.vof().cpu().numpy(), c, 1.0, "c")
+    _assert_close(d.energy().cpu().numpy(), e, float(np.max(np.abs(wl.e))), "e")
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 1)])
 def test_every_cell_mixed(pc, bc):
     """A field where every cell is mixed: every face needs the donor geometry, which
     overflows the sweep blocks' LDS flux tables into the global face array."""
