@@ -983,6 +983,16 @@ int batch_build_tiles(pcvof_batch* b) {
             b->dom_tiles[a][i] = n;
         }
         if ((int)t.size() > b->L.max_tiles[a]) return fail(PCVOF_ERR_WORKSPACE, "tile table overflow");
+        if (a > 0) {
+            // y / z: every whole aligned group of 64 entries transposed as 8 x 8, so that the
+            // XCD that runs blocks 8 m + k of a group gets the consecutive tiles 8 k .. 8 k + 7
+            // (neighbouring column blocks of a domain share cache lines), as the single-domain
+            // launches order their blocks
+            std::vector<pcv::BatchTile> p(t);
+            const size_t full = t.size() & ~(size_t)63;
+            for (size_t q = 0; q < full; ++q) p[q] = t[(q & ~(size_t)63) | ((q & 7) << 3) | ((q >> 3) & 7)];
+            t.swap(p);
+        }
         b->ntiles[a] = (int)t.size();
         HIP_TRY(hipMemcpy(b->tiles(a), t.data(), t.size() * sizeof(pcv::BatchTile), hipMemcpyHostToDevice));
     }
