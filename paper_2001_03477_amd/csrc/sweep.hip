@@ -346,17 +346,20 @@ struct TileAt {
 
 template <bool MP>
 __device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a, const TileAt& tl, int plan) {
-    __shared__ double s_c[XWAVES][XRING];
-    __shared__ double s_e[XWAVES][XRING];
-    __shared__ double s_T[XWAVES][XRING];
-    __shared__ double s_F[XWAVES][XFCAP];           // liquid flux of listed faces, by position
-    __shared__ double s_first[XWAVES][3][XRMAX];    // Phi, E, lambda of each row's carried face
-    __shared__ unsigned short s_work[XWAVES][128];  // listed faces not yet reconstructed (ring)
-    __shared__ uint64_t s_mw[XWAVES][XRMAX * (XKMAX + 1)];  // input mask words of the rows
-    __shared__ uint64_t s_bal[XWAVES][XRMAX * XKMAX];       // listed faces of each chunk (ballot)
+    // one record per wavefront, so that every table is one base address plus a constant
+    struct WaveLds {
+        double c[XRING], e[XRING], T[XRING];
+        double F[XFCAP];                      // liquid flux of listed faces, by position
+        double first[3][XRMAX];               // Phi, E, lambda of each row's carried face
+        uint64_t mw[XRMAX * (XKMAX + 1)];     // input mask words of the rows
+        uint64_t bal[XRMAX * XKMAX];          // listed faces of each chunk (ballot)
+        unsigned short work[128];             // listed faces not yet reconstructed (ring)
+    };
+    __shared__ WaveLds s_x[XWAVES];
     using T = typename Prec<MP>::T;
     const int lane = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    WaveLds& W = s_x[wave];
     const int nx = d.n[0];
     const int prows = plan & 0xff, pchunks = plan >> 8;  // rows per wavefront, chunks per range
     const int x0 = tl.bx * pchunks * XW;
@@ -373,14 +376,14 @@ __device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a, c
     unsigned nwork = 0, ndone = 0;
     auto append = [&](bool need, unsigned item) {
         const unsigned long long bal = __ballot(need);
-        if (need) s_work[wave][(nwork + (unsigned)__popcll(bal & __lanemask_lt())) & 127] = (unsigned short)item;
+        if (need) W.work[(nwork + (unsigned)__popcll(bal & __lanemask_lt())) & 127] = (unsigned short)item;
         nwork += (unsigned)__popcll(bal);
     };
     auto reconstruct = [&]() {  // items ndone .. min(nwork, ndone + 64) - 1
         wave_lds_order();
         const unsigned q = ndone + lane;
         if (q < nwork) {
-            const unsigned it = s_work[wave][q & 127];
+            const unsigned it = W.work[q & 127];
             const int r = it >> 11, f = x0 + (int)(it & 2047);
             const int R = R0 + r;
             const double lam = vel_at<MP>(a, (long)R * (nx + 1) + f) * a.kfac;
@@ -394,7 +397,7 @@ __device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a, c
                 }
                 const double F = donor_flux<0, MP>(d, a.c, xd, y0 + r, tl.bz, cd, lam, s);
                 if (q < XFCAP)
-                    s_F[wave][q] = F;
+                    W.F[q] = F;
                 else
                     a.fgeo[(long)R * (nx + 1) + f] = F;
             }
@@ -410,7 +413,7 @@ __device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a, c
     // bits of the rows' ghost cells right of their last cells
     for (int i = lane; i < nrows * (XKMAX + 1); i += XW) {
         const int r = i / (XKMAX + 1), w = (x0 >> 6) + (i - r * (XKMAX + 1));
-        s_mw[wave][i] = w < d.wpr ? a.mask[(long)(R0 + r) * d.wpr + w] : 0ull;
+        W.mw[i] = w < d.wpr ? a.mask[(long)(R0 + r) * d.wpr + w] : 0ull;
     }
     const uint64_t gbits = __ballot(lane < nrows && mask64(d, a.mask, R0 + lane, nx));
     wave_lds_order();
@@ -418,10 +421,10 @@ __device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a, c
         const bool gbit = (gbits >> r) & 1ull;
         for (int k = 0; k < K; ++k) {
             const int x = x0 + 64 * k + lane;
-            const uint64_t w0 = s_mw[wave][r * (XKMAX + 1) + k], w1 = s_mw[wave][r * (XKMAX + 1) + k + 1];
+            const uint64_t w0 = W.mw[r * (XKMAX + 1) + k], w1 = W.mw[r * (XKMAX + 1) + k + 1];
             const bool need = x_face_need(nx, w0, w1, x, lane, x < x1, gbit);
             const uint64_t bal = __ballot(need);
-            if (lane == 0) s_bal[wave][r * XKMAX + k] = bal;
+            if (lane == 0) W.bal[r * XKMAX + k] = bal;
             append(need, ((unsigned)r << 11) | (unsigned)(64 * k + lane + 1));
             while (nwork - ndone >= (unsigned)XW) reconstruct();
         }
@@ -446,12 +449,12 @@ __device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a, c
             const double Tf = weno5(Ts[0], Ts[1], Ts[2], Ts[3], Ts[4], d.weno_eps);
             const double cd = a.c[rb + wrap(lam > 0.0 ? x0 - 1 : x0, nx, d.bc[0])];
             double F = fabs(lam) * cd;
-            if (mixed(d, cd)) F = s_F[wave][pos0];
+            if (mixed(d, cd)) F = W.F[pos0];
             face_energy(d, lam, F, Tf, Phi, E);
         }
-        s_first[wave][0][lane] = Phi;
-        s_first[wave][1][lane] = E;
-        s_first[wave][2][lane] = lam;
+        W.first[0][lane] = Phi;
+        W.first[1][lane] = E;
+        W.first[2][lane] = lam;
     }
 
     // The walk. Prefetched registers: the next chunk to stage (c, e) and the next step's
@@ -491,9 +494,9 @@ __device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a, c
             if (j <= klast) {  // stage chunk j
                 const int q = (64 * j + lane) & (XRING - 1);
                 const double cj = pc, ej = pe;
-                s_c[wave][q] = cj;
-                s_e[wave][q] = ej;
-                s_T[wave][q] = ej / cp_of(d, cj);
+                W.c[q] = cj;
+                W.e[q] = ej;
+                W.T[q] = ej / cp_of(d, cj);
             }
             if (j < klast)
                 load_chunk(R, j + 1);
@@ -509,23 +512,23 @@ __device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a, c
             const int x = x0 + 64 * k + lane;
             const bool own = x < x1;
             const int p = 64 * k + lane + 2;
-            const uint64_t bal = uniform64(s_bal[wave][r * XKMAX + k]);
+            const uint64_t bal = uniform64(W.bal[r * XKMAX + k]);
             const unsigned pos = pos_base + (unsigned)__popcll(bal & __lanemask_lt());
             pos_base += (unsigned)__popcll(bal);
             double Phi = 0.0, E = 0.0, lam = 0.0;
             if (own) {
                 lam = u * a.kfac;
                 if (lam != 0.0) {
-                    const double cd = lam > 0.0 ? s_c[wave][p & (XRING - 1)] : s_c[wave][(p + 1) & (XRING - 1)];
+                    const double cd = lam > 0.0 ? W.c[p & (XRING - 1)] : W.c[(p + 1) & (XRING - 1)];
                     // upwind stencil selected first (cells x-2 .. x+2, or x+3 .. x-1 mirrored),
                     // so that one WENO5 evaluation serves both signs
                     const int b = lam > 0.0 ? p - 2 : p + 3, st = lam > 0.0 ? 1 : -1;
-                    const double Tf = weno5(s_T[wave][b & (XRING - 1)], s_T[wave][(b + st) & (XRING - 1)],
-                                            s_T[wave][(b + 2 * st) & (XRING - 1)],
-                                            s_T[wave][(b + 3 * st) & (XRING - 1)],
-                                            s_T[wave][(b + 4 * st) & (XRING - 1)], d.weno_eps);
+                    const double Tf = weno5(W.T[b & (XRING - 1)], W.T[(b + st) & (XRING - 1)],
+                                            W.T[(b + 2 * st) & (XRING - 1)],
+                                            W.T[(b + 3 * st) & (XRING - 1)],
+                                            W.T[(b + 4 * st) & (XRING - 1)], d.weno_eps);
                     double F = fabs(lam) * cd;
-                    if (mixed(d, cd)) F = listed_flux(s_F[wave], pos, XFCAP, a.fgeo + (long)R * (nx + 1) + x + 1);
+                    if (mixed(d, cd)) F = listed_flux(W.F, pos, XFCAP, a.fgeo + (long)R * (nx + 1) + x + 1);
                     face_energy(d, lam, F, Tf, Phi, E);
                 }
             }
@@ -533,23 +536,23 @@ __device__ __forceinline__ void sweep_x_body(const Dom& d, const SweepArgs& a, c
             // carried face (its first face, then lane 63's face of the previous chunk)
             double PhiL = __shfl_up(Phi, 1, 64), EL = __shfl_up(E, 1, 64), lamL = __shfl_up(lam, 1, 64);
             if (lane == 0) {
-                PhiL = s_first[wave][0][r];
-                EL = s_first[wave][1][r];
-                lamL = s_first[wave][2][r];
+                PhiL = W.first[0][r];
+                EL = W.first[1][r];
+                lamL = W.first[2][r];
             }
             wave_lds_order();
             if (lane == XW - 1) {
-                s_first[wave][0][r] = Phi;
-                s_first[wave][1][r] = E;
-                s_first[wave][2][r] = lam;
+                W.first[0][r] = Phi;
+                W.first[1][r] = E;
+                W.first[2][r] = lam;
             }
             bool mx = false;
             if (own) {
                 const int pq = p & (XRING - 1);
-                const double cv = s_c[wave][pq];
+                const double cv = W.c[pq];
                 double ELc = EL, ERc = E;
                 cell_energy_flux(d, cv, ELc, ERc);
-                const double cn = update_cell<MP>(d, a, rb + x, cv, s_e[wave][pq], s_T[wave][pq], lamL, lam, PhiL,
+                const double cn = update_cell<MP>(d, a, rb + x, cv, W.e[pq], W.T[pq], lamL, lam, PhiL,
                                                   Phi, ELc, ERc, cc_own, ec_own, acc);
                 mx = mixed(d, cn);
                 if (d.bc[0] == 1) {
